@@ -1,0 +1,294 @@
+"""FP64 oracle for k-means|| -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may use
+this module.  It wraps ``kmpar_oracle.c`` (plain C, FP64) with ctypes and
+composes Algorithm 2 of the paper (Section 3.3) from its steps:
+
+1. first center uniformly at random                     -- ``first_center``
+2. psi = phi_X(C)                                        -- ``orc_sum`` of D^2
+3-6. r rounds: keep each x with p = min(1, ell d^2/phi)  -- ``orc_select``
+     and update d^2(x, C) for the new candidates         -- ``orc_fold``
+7. weights w_c = |{x : c nearest to x}|                  -- ``orc_weights``
+8. recluster the weighted candidates with k-means++      -- ``orc_kpp_weighted``
+
+plus Lloyd's iteration (Section 1, Section 3.1) -- ``lloyd_step``.
+
+Replay ("follow").  Another implementation that computes in lower precision
+may legitimately take a different discrete decision where the oracle's margin
+is within that precision's error band: a draw with |u - p| small, an argmin
+whose top-2 gap is small, a recluster pick whose threshold is near a boundary.
+``kmeans_parallel_init(..., follow=...)`` takes that implementation's
+decisions, accepts each disagreement that lies inside the stated band (counted
+as *flagged*), counts every other one as *bad*, and continues from the
+followed decision so the rest of the run stays comparable.
+
+The module never imports the library under test and shares no code with it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libkmpar_oracle.so")
+_SRC_PATH = os.path.join(_HERE, "kmpar_oracle.c")
+
+TAG_FIRST, TAG_ROUND, TAG_RECL = 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (FP64, no contraction into FMA)."""
+    import subprocess
+
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-std=c11", _SRC_PATH, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        u64, i64, i32, dbl = ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        vp = ctypes.c_void_p
+        L.orc_philox4x64_10.argtypes = [vp, vp, vp]
+        L.orc_word.argtypes = [u64, u64, u64, u64, u64]
+        L.orc_word.restype = u64
+        L.orc_uniform.argtypes = [u64, u64, u64, u64, u64]
+        L.orc_uniform.restype = dbl
+        L.orc_index.argtypes = [u64, u64, u64, u64, u64, i64]
+        L.orc_index.restype = i64
+        L.orc_sum.argtypes = [vp, i64]
+        L.orc_sum.restype = dbl
+        L.orc_nearest.argtypes = [vp, i64, i32, vp, i64, vp, vp, vp]
+        L.orc_first_center.argtypes = [i64, u64, u64]
+        L.orc_first_center.restype = i64
+        L.orc_select.argtypes = [vp, i64, dbl, dbl, u64, i64, u64, vp, vp, vp]
+        L.orc_select.restype = i64
+        L.orc_fold.argtypes = [vp, i64, i32, vp, i64, i64, vp, vp, vp]
+        L.orc_weights.argtypes = [vp, i64, i64, vp]
+        L.orc_kpp_weighted.argtypes = [vp, i64, i32, vp, i64, u64, u64, vp, dbl, vp, vp, vp]
+        L.orc_kpp_weighted.restype = i64
+        L.orc_lloyd_update.argtypes = [vp, i64, i32, vp, i64, vp, vp]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(X) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# --------------------------------------------------------------------------- RNG
+def philox_block(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint64))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64))
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def uniform(seed, tag, a, b, inst=0) -> float:
+    return float(lib().orc_uniform(seed, tag, a, b, inst))
+
+
+def index(seed, tag, a, b, inst, n) -> int:
+    return int(lib().orc_index(seed, tag, a, b, inst, n))
+
+
+def first_center(n: int, seed: int, inst: int = 0) -> int:
+    return int(lib().orc_first_center(n, seed, inst))
+
+
+# --------------------------------------------------------------------- distances
+def total(v) -> float:
+    v = _f64(v)
+    return float(lib().orc_sum(_p(v), v.size))
+
+
+def nearest(X, C):
+    """Section 3.1: (argmin, d^2, second smallest d^2) of each point."""
+    X, C = _f64(X), _f64(C)
+    n, d = X.shape
+    m = C.shape[0]
+    arg = np.empty(n, np.int64)
+    d2 = np.empty(n, np.float64)
+    snd = np.empty(n, np.float64)
+    lib().orc_nearest(_p(X), n, d, _p(C), m, _p(arg), _p(d2), _p(snd))
+    return arg, d2, snd
+
+
+def cost(X, C) -> float:
+    """phi_X(C) (Section 3.1)."""
+    return total(nearest(X, C)[1])
+
+
+def select(D2, phi, ell, seed, t, inst=0):
+    D2 = _f64(D2)
+    n = D2.size
+    sel = np.empty(n, np.uint8)
+    p = np.empty(n, np.float64)
+    u = np.empty(n, np.float64)
+    lib().orc_select(_p(D2), n, float(phi), float(ell), seed, t, inst, _p(sel), _p(p), _p(u))
+    return sel.astype(bool), p, u
+
+
+def fold(X, Cnew, first_id, D2, A, S=None):
+    X, Cnew = _f64(X), _f64(Cnew)
+    n, d = X.shape
+    lib().orc_fold(_p(X), n, d, _p(Cnew), Cnew.shape[0], first_id, _p(D2), _p(A),
+                   _p(S) if S is not None else None)
+
+
+def weights(A, ncand) -> np.ndarray:
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.int64))
+    w = np.empty(ncand, np.int64)
+    lib().orc_weights(_p(A), A.size, ncand, _p(w))
+    return w
+
+
+def kpp_weighted(C, w, k, seed, inst=0, follow=None, tol=0.0):
+    """Weighted k-means++ (Algorithm 1 with weights).  Returns
+    (picks, n_flagged, n_bad)."""
+    C = _f64(C)
+    m, d = C.shape
+    wf = _f64(w)
+    picks = np.full(k, -1, np.int64)
+    nf = ctypes.c_int64(0)
+    nb = ctypes.c_int64(0)
+    fo = None
+    if follow is not None:
+        fo = np.full(k, -1, np.int64)
+        f = np.asarray(follow, dtype=np.int64)
+        fo[:f.size] = f[:k]
+    made = lib().orc_kpp_weighted(_p(C), m, d, _p(wf), k, seed, inst,
+                                  _p(fo) if fo is not None else None, float(tol), _p(picks),
+                                  ctypes.byref(nf), ctypes.byref(nb))
+    return picks[:made], int(nf.value), int(nb.value)
+
+
+def lloyd_update(X, a, C):
+    X = _f64(X)
+    n, d = X.shape
+    C = _f64(C).copy()
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+    cnt = np.empty(C.shape[0], np.int64)
+    lib().orc_lloyd_update(_p(X), n, d, _p(a), C.shape[0], _p(C), _p(cnt))
+    return C, cnt
+
+
+def lloyd_step(X, C):
+    """One Lloyd iteration: assign, then move centers to centroids.
+    Returns (new C, assignment, cost of the input centers)."""
+    a, d2, _ = nearest(X, C)
+    Cn, _ = lloyd_update(X, a, C)
+    return Cn, a, total(d2)
+
+
+# ---------------------------------------------------------------- k-means||
+def fp32_band(d: int) -> float:
+    """Relative error bound of a squared distance computed in FP32 in direct
+    form sum_j (x_j - c_j)^2 against its exact value: each difference and
+    square rounds once and a d-term nonnegative sum adds at most (d-1)
+    roundings, so |err| <= (d + 2) u D^2 with u = 2^-24.  The bands below use
+    twice that (both operands of a comparison carry error)."""
+    return 2.0 * (d + 2) * 2.0 ** -24
+
+
+@dataclass
+class InitResult:
+    cand_point: np.ndarray            # point index of every candidate, id order
+    round_count: list                 # |C'_t| per round (entry 0 is the first center)
+    phi: list                         # phi after the first center and after each round
+    assign: np.ndarray                # nearest candidate id per point after the rounds
+    d2: np.ndarray                    # D^2 per point after the rounds
+    weights: np.ndarray               # Step 7 weights per candidate
+    picks: np.ndarray                 # candidate ids chosen by the recluster
+    centers: np.ndarray               # X rows of the picks (FP64)
+    flags: dict = field(default_factory=dict)
+    bad: dict = field(default_factory=dict)
+
+
+def kmeans_parallel_init(X, k, ell, rounds, seed, inst=0, follow=None, band=None):
+    """Algorithm 2 (Section 3.3) with k-means++ as the Step-8 recluster.
+
+    ``follow`` (optional) is a dict with any of
+      ``rounds``: list of arrays, the point indices kept in round t=1..r,
+      ``assign``: the other side's nearest-candidate id per point,
+      ``picks``:  the other side's recluster picks (candidate ids),
+    and ``band`` the relative error band of the other side's distances
+    (default: ``fp32_band(d)``).
+    """
+    X = _f64(X)
+    n, d = X.shape
+    band = fp32_band(d) if band is None else band
+    flags = {"draw": 0, "argmin": 0, "pick": 0}
+    bad = {"draw": 0, "argmin": 0, "pick": 0}
+
+    i0 = first_center(n, seed, inst)
+    cand = [i0]
+    D2 = np.full(n, np.inf)
+    A = np.zeros(n, np.int64)
+    fold(X, X[i0:i0 + 1], 0, D2, A)
+    phi = [total(D2)]
+    counts = [1]
+    for t in range(1, rounds + 1):
+        sel, p, u = select(D2, phi[-1], ell, seed, t, inst)
+        if follow is not None and "rounds" in follow:
+            other = np.zeros(n, bool)
+            other[np.asarray(follow["rounds"][t - 1], dtype=np.int64)] = True
+            diff = np.nonzero(other != sel)[0]
+            if diff.size:
+                within = np.abs(u[diff] - p[diff]) <= band * p[diff] + 1e-300
+                flags["draw"] += int(within.sum())
+                bad["draw"] += int((~within).sum())
+                sel = other
+        new = np.nonzero(sel)[0]
+        fold(X, X[new], len(cand), D2, A)
+        cand.extend(new.tolist())
+        counts.append(int(new.size))
+        phi.append(total(D2))
+
+    cand = np.asarray(cand, dtype=np.int64)
+    if follow is not None and "assign" in follow:
+        other = np.asarray(follow["assign"], dtype=np.int64)
+        diff = np.nonzero(other != A)[0]
+        if diff.size:
+            ok = (other[diff] >= 0) & (other[diff] < cand.size)
+            dg = np.full(diff.size, np.inf)
+            idx = np.nonzero(ok)[0]
+            if idx.size:
+                xs = X[diff[idx]]
+                cs = X[cand[other[diff[idx]]]]
+                dg[idx] = ((xs - cs) ** 2).sum(axis=1)
+            within = ok & (dg - D2[diff] <= band * D2[diff])
+            flags["argmin"] += int(within.sum())
+            bad["argmin"] += int((~within).sum())
+            A = A.copy()
+            A[diff[ok]] = other[diff[ok]]
+    w = weights(A, cand.size)
+    fpk = None if follow is None else follow.get("picks")
+    picks, nf, nb = kpp_weighted(X[cand], w, k, seed, inst, follow=fpk, tol=band)
+    flags["pick"] += nf
+    bad["pick"] += nb
+    return InitResult(cand_point=cand, round_count=counts, phi=phi, assign=A, d2=D2,
+                      weights=w, picks=picks, centers=X[cand[picks]], flags=flags, bad=bad)
