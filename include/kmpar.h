@@ -1,0 +1,178 @@
+/*
+ * kmpar.h -- C ABI of libkmpar.so: k-means|| (Bahmani, Moseley, Vattani,
+ * Kumar, Vassilvitskii, "Scalable K-Means++", PVLDB 2012) on AMD MI355X.
+ *
+ * Problem statement (Section 3.1): X = {x_1..x_n} in R^d, an integer k; the
+ * cost of a center set C is phi_X(C) = sum_x min_{c in C} ||x - c||^2; every
+ * center defines the cluster of points closer to it than to any other.
+ *
+ * Conventions shared by every call
+ *  - X is row-major n x d.  dtype KMPAR_F32: float; KMPAR_BF16: bfloat16 bits
+ *    (uint16); KMPAR_FP8_E4M3: OCP e4m3 bytes with one float scale per row
+ *    (x_ij = decode(q_ij) * row_scale[i]).  row_scale must be NULL for the
+ *    other dtypes.
+ *  - Every array argument is a DEVICE pointer owned by the caller and at least
+ *    16-byte aligned.  The library never allocates device memory: scratch
+ *    comes from the caller's workspace `ws` of `ws_bytes` bytes, sized with
+ *    kmpar_workspace_size().  Its contents on entry do not matter.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
+ *    work: outputs are valid once the stream has been synchronised.  Calls
+ *    make no host synchronisation and may be captured in a hipGraph.
+ *  - Arguments are validated on the host before any HIP call.  Return value
+ *    0 (KMPAR_OK) or a negative kmpar_status; kmpar_last_error() gives text.
+ *  - Limits: 1 <= n < 2^31, 1 <= d <= 256, 1 <= k <= n, k <= 16384,
+ *    rounds <= KMPAR_MAX_ROUNDS.
+ *  - Results are deterministic: the same inputs, seed, mode and device give
+ *    bit-identical outputs (every reduction runs in a fixed order).
+ *  - Calls that share one workspace or one context must not overlap.
+ */
+#ifndef KMPAR_H_
+#define KMPAR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KMPAR_MAX_ROUNDS 64
+
+typedef enum kmpar_dtype { KMPAR_F32 = 0, KMPAR_BF16 = 1, KMPAR_FP8_E4M3 = 2 } kmpar_dtype;
+
+/* PLAIN_FP32: every point-center distance in FP32 direct form
+ * sum_j (x_j - c_j)^2.  REFINED: distances screened on the matrix cores
+ * from ||x||^2 - 2 x.c + ||c||^2 with a rigorous error band, and every
+ * decision the band cannot settle recomputed in FP32 direct form, so both
+ * modes take the same decisions up to FP32 rounding. */
+typedef enum kmpar_mode { KMPAR_MODE_PLAIN_FP32 = 0, KMPAR_MODE_REFINED = 1 } kmpar_mode;
+
+typedef enum kmpar_status {
+  KMPAR_OK = 0,
+  KMPAR_E_INVAL = -1,     /* argument out of range, NULL or misaligned pointer */
+  KMPAR_E_WORKSPACE = -2, /* ws_bytes smaller than kmpar_workspace_size()      */
+  KMPAR_E_HIP = -3,       /* a HIP call failed; text in kmpar_last_error()     */
+  KMPAR_E_TOOFEW = -4,    /* (stats.status) fewer than k distinct candidates  */
+  KMPAR_E_OVERFLOW = -5,  /* (stats.status) a round kept more points than the
+                             per-round capacity; that round was truncated     */
+  KMPAR_E_NODEVICE = -6   /* context created without a device                 */
+} kmpar_status;
+
+/* Which call a workspace is sized for. */
+typedef enum kmpar_op {
+  KMPAR_OP_INIT = 0,
+  KMPAR_OP_COST = 1,
+  KMPAR_OP_ASSIGN = 2,
+  KMPAR_OP_LLOYD = 3
+} kmpar_op;
+
+typedef struct kmpar_ctx kmpar_ctx;
+
+/* Per-call record of kmpar_init, written on the device (caller-owned device
+ * memory of kmpar_sizeof_stats() bytes). */
+typedef struct kmpar_stats {
+  double phi[KMPAR_MAX_ROUNDS + 1];          /* phi_X(C): [0] = psi after the first
+                                                center (Alg. 2 step 2), [t] after
+                                                round t (steps 4-5)               */
+  int32_t round_count[KMPAR_MAX_ROUNDS + 1]; /* |C'_t| kept in round t; [0] = 1   */
+  int32_t n_candidates;                      /* |C| after the last round          */
+  int32_t n_centers;                         /* centers written (k unless TOOFEW) */
+  int32_t status;                            /* KMPAR_OK, _E_TOOFEW or _E_OVERFLOW */
+  int32_t n_rescanned;                       /* REFINED: point passes the screen
+                                                could not settle (recomputed in
+                                                direct form), summed over passes  */
+  int32_t reserved[4];
+} kmpar_stats;
+
+/* Optional device outputs of kmpar_init for inspection (each may be NULL). */
+typedef struct kmpar_trace {
+  int32_t* cand_point;  /* [max_candidates] point index of candidate id c; ids are
+                           given in append order: round, then point index      */
+  int32_t* cand_weight; /* [max_candidates] Step-7 weight w_c                    */
+  int32_t* center_cand; /* [k] candidate id of the s-th recluster pick            */
+  int32_t* assign;      /* [n] id of the nearest candidate after the last round   */
+  float* d2;            /* [n] D^2(x, C) after the last round (FP32)             */
+} kmpar_trace;
+
+/* Kernel timing for measurement: while enabled, every launch of a distance
+ * kernel (the fold of Algorithm 2 steps 4-5 and of the assignment passes) is
+ * bracketed by two hipEvents recorded on the call's stream.
+ * kmpar_profile_read() synchronises on those events and reports, for kernel
+ * slot `slot` (0 = direct-form fold), the number of launches, their summed
+ * duration in milliseconds and their summed algorithmic work in point-center
+ * pairs (n * m per launch, m read back from the device after the call);
+ * reading also clears the slot.  Disabled by default; enabling adds one
+ * event pair per launch and must not be used under graph capture. */
+int kmpar_profile_enable(kmpar_ctx* ctx, int on);
+int kmpar_profile_read(kmpar_ctx* ctx, int slot, int64_t* launches, double* total_ms,
+                       double* pairs);
+
+/* Creates a context bound to HIP device `hip_device`, or a host-only context
+ * when hip_device == -1 (validation and size queries only; compute calls then
+ * return KMPAR_E_NODEVICE).  Returns KMPAR_E_HIP when the device cannot be
+ * queried. */
+int kmpar_create(int hip_device, kmpar_mode mode, kmpar_ctx** out);
+void kmpar_destroy(kmpar_ctx* ctx);
+const char* kmpar_strerror(int status);
+const char* kmpar_last_error(const kmpar_ctx* ctx);
+size_t kmpar_sizeof_stats(void);
+
+/* Upper bound on |C| that kmpar_init keeps: 1 + rounds * per-round capacity,
+ * where the capacity min(n, ceil(ell + 12 sqrt(ell) + 64)) sits more than
+ * 12 standard deviations above the expected ell points per round (Section
+ * 3.3: each round keeps ell points in expectation). */
+int kmpar_max_candidates(int64_t n, double ell, int32_t rounds, int64_t* out);
+
+/* Workspace bytes for `op` at the given sizes (k = number of centers m for
+ * COST/ASSIGN/LLOYD; ell and rounds are ignored there).  Host only. */
+int kmpar_workspace_size(const kmpar_ctx* ctx, kmpar_op op, int64_t n, int32_t d, int32_t k,
+                         double ell, int32_t rounds, kmpar_dtype dtype, size_t* bytes_out);
+
+/* Algorithm 2 (Section 3.3), k-means|| initialisation:
+ *  1. the first center is a uniformly random point;
+ *  2. psi = phi_X(C);
+ *  3-6. for `rounds` rounds each point x is kept independently with
+ *     probability min(1, ell * d^2(x, C) / phi_X(C)) and the kept points join C;
+ *  7. w_c = number of points whose nearest candidate is c (ties: lowest id);
+ *  8. the weighted candidates are reclustered into k centers with k-means++
+ *     (Algorithm 1, weights multiplying the D^2 probabilities), as in the
+ *     experiments (Section 4.2).
+ * Randomness: Philox4x64-10 keyed (seed, tag) at counter (a, b, inst, 0):
+ * tag 1 first center (a=b=0), tag 2 round draws (a = point index, b = round
+ * t >= 1), tag 3 recluster picks (a = pick number s, b = 0); inst = 0.
+ * Output: `centers` [k x d] FP32 in pick order (each is a row of X).  `stats`
+ * (device, nullable) and `trace` (host struct of device pointers, nullable).
+ * Errors found on the device (too few candidates, capacity overflow) are
+ * reported in stats->status. */
+int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+               int64_t n, int32_t d, int32_t k, double ell, int32_t rounds, uint64_t seed,
+               float* centers, void* ws, size_t ws_bytes, kmpar_stats* stats,
+               const kmpar_trace* trace, void* stream);
+
+/* phi_X(C) (Section 3.1) of the m centers C [m x d FP32] into *phi (device
+ * double), summed in FP64 in a fixed order. */
+int kmpar_cost(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+               int64_t n, int32_t d, const float* C, int32_t m, double* phi, void* ws,
+               size_t ws_bytes, void* stream);
+
+/* Nearest center of every point (Section 3.1; ties to the lowest index):
+ * assign [n] int32, d2 [n] FP32 squared distance (nullable). */
+int kmpar_assign(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                 int64_t n, int32_t d, const float* C, int32_t m, int32_t* assign, float* d2,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* One Lloyd iteration (Section 1; Section 3.1): assign every point to its
+ * nearest center, then replace each center by the centroid of its points; a
+ * center with no points is kept.  C [k x d FP32] is updated in place.
+ * assign [n] (nullable) receives the assignment to the INPUT centers and
+ * *phi (device double, nullable) their cost.  Centroids are summed in FP64
+ * in a fixed order and rounded once to FP32. */
+int lloyd_step(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+               int64_t n, int32_t d, float* C, int32_t k, int32_t* assign, double* phi, void* ws,
+               size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KMPAR_H_ */

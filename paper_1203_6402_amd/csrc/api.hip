@@ -1,0 +1,523 @@
+// Host side of the kmpar C ABI: argument validation (before any HIP call),
+// workspace layout, and the launch sequence of each call.  No call allocates
+// device memory or synchronises the host.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/kmpar.h"
+#include "kernels.hpp"
+
+namespace {
+// One timed launch of a distance kernel (see kmpar_profile_enable).
+struct ProfRec {
+  int slot;
+  hipEvent_t a, b;
+  int64_t npts;          // points processed (when npts_dev == nullptr)
+  const int* npts_dev;   // device count of points processed (nullable)
+  const int* rs_dev;     // device rs pair: m = rs[1] - rs[0] (nullable)
+  int m_host;
+};
+}  // namespace
+
+struct kmpar_ctx {
+  int device = -1;
+  kmpar_mode mode = KMPAR_MODE_PLAIN_FP32;
+  std::string err;
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+using namespace kmpar;
+
+constexpr int kMaxD = 256;
+constexpr int kMaxK = 16384;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int set_err(kmpar_ctx* ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int set_err(kmpar_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int64_t cap_round_of(int64_t n, double ell) {
+  const double c = ceil(ell + 12.0 * sqrt(ell) + 64.0);
+  return c >= (double)n ? n : (int64_t)c;
+}
+
+// Sequential carve-up of the caller's workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? (T*)(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+struct InitLayout {
+  float* D2;
+  int* A;
+  double* phi_part;
+  int* cnt;
+  int* rs;
+  int* scan_total;
+  int* cand_point;
+  float* Call;
+  float* CallT;
+  int* w;
+  float* E;
+  int* picks;
+  kmpar_stats* st;
+  size_t bytes;
+};
+
+InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds) {
+  const int DP = padded_dim(d);
+  const int64_t capT = 1 + (int64_t)rounds * cap_round_of(n, ell);
+  Carver c(ws);
+  InitLayout L;
+  L.D2 = c.take<float>(n);
+  L.A = c.take<int>(n);
+  L.phi_part = c.take<double>((n + kPhiChunk - 1) / kPhiChunk);
+  L.cnt = c.take<int>((n + kDrawChunk - 1) / kDrawChunk + 1);
+  L.rs = c.take<int>(rounds + 2);
+  L.scan_total = c.take<int>(4);
+  L.cand_point = c.take<int>(capT);
+  L.Call = c.take<float>(capT * DP);
+  L.CallT = c.take<float>(capT * DP);
+  L.w = c.take<int>(capT);
+  L.E = c.take<float>(capT);
+  L.picks = c.take<int>(k);
+  L.st = c.take<kmpar_stats>(1);
+  L.bytes = c.off;
+  return L;
+}
+
+struct AssignLayout {
+  float* D2;
+  int* A;
+  double* phi_part;
+  double* phi_tmp;
+  float* Cpad;
+  LloydWs lw;
+  size_t bytes;
+};
+
+AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op) {
+  const int DP = padded_dim(d);
+  Carver c(ws);
+  AssignLayout L{};
+  L.D2 = c.take<float>(n);
+  L.A = c.take<int>(n);
+  L.phi_part = c.take<double>((n + kPhiChunk - 1) / kPhiChunk);
+  L.phi_tmp = c.take<double>(1);
+  L.Cpad = c.take<float>((size_t)k * DP);
+  if (op == KMPAR_OP_LLOYD) {
+    const int64_t nbs = (n + kSortChunk - 1) / kSortChunk;
+    const int64_t Lt = (int64_t)k * nbs;
+    L.lw.bcnt = c.take<int>(Lt);
+    L.lw.scan_tmp = c.take<int>((Lt + kScanTile - 1) / kScanTile + 1);
+    L.lw.sorted = c.take<int>(n);
+    L.lw.cstart = c.take<int>(k + 1);
+    L.lw.coff = c.take<int>(k + 1);
+    L.lw.part = c.take<double>(((n + kSegChunk - 1) / kSegChunk + k) * (int64_t)d);
+  }
+  L.bytes = c.off;
+  return L;
+}
+
+int check_common(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dt, int64_t n,
+                 int32_t d) {
+  if (dt != KMPAR_F32 && dt != KMPAR_BF16 && dt != KMPAR_FP8_E4M3)
+    return set_err(ctx, KMPAR_E_INVAL, "unknown dtype %d", (int)dt);
+  if (n < 1 || n >= (int64_t)1 << 31) return set_err(ctx, KMPAR_E_INVAL, "n=%lld out of range", (long long)n);
+  if (d < 1 || d > kMaxD) return set_err(ctx, KMPAR_E_INVAL, "d=%d out of range [1,%d]", d, kMaxD);
+  if (!X || !aligned16(X)) return set_err(ctx, KMPAR_E_INVAL, "X is NULL or not 16-byte aligned");
+  if (dt == KMPAR_FP8_E4M3) {
+    if (!row_scale || !aligned16(row_scale))
+      return set_err(ctx, KMPAR_E_INVAL, "FP8 input needs a 16-byte aligned row_scale");
+  } else if (row_scale) {
+    return set_err(ctx, KMPAR_E_INVAL, "row_scale is only valid with KMPAR_FP8_E4M3");
+  }
+  return KMPAR_OK;
+}
+
+bool ell_ok(double ell) { return isfinite(ell) && ell > 0.0; }
+
+// Makes ctx->device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  hipError_t e = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    e = hipGetDevice(&prev);
+    if (e != hipSuccess) return;
+    if (prev != dev) e = hipSetDevice(dev);
+    ok = (e == hipSuccess);
+  }
+  ~DeviceGuard() {
+    if (ok && prev >= 0) {
+      int cur = -1;
+      if (hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+  }
+};
+
+int hip_fail(kmpar_ctx* ctx, hipError_t e, const char* where) {
+  return set_err(ctx, KMPAR_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define KMPAR_HIP(call)                                       \
+  do {                                                        \
+    hipError_t _e = (call);                                   \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, #call);    \
+  } while (0)
+
+hipError_t prof_event(kmpar_ctx* ctx, hipEvent_t* e) {
+  if (!ctx->pool.empty()) {
+    *e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Launches a distance pass, bracketed by events when profiling is on.
+hipError_t timed_fold(kmpar_ctx* ctx, int slot, kmpar_dtype dt, int DP, const FoldArgs& fa,
+                      hipStream_t s) {
+  if (!ctx->prof) return launch_fold_direct(dt, DP, fa, s);
+  ProfRec r{};
+  r.slot = slot;
+  hipError_t e;
+  if ((e = prof_event(ctx, &r.a)) != hipSuccess) return e;
+  if ((e = prof_event(ctx, &r.b)) != hipSuccess) return e;
+  if ((e = hipEventRecord(r.a, s)) != hipSuccess) return e;
+  if ((e = launch_fold_direct(dt, DP, fa, s)) != hipSuccess) return e;
+  if ((e = hipEventRecord(r.b, s)) != hipSuccess) return e;
+  r.npts = fa.list ? 0 : fa.n;
+  r.npts_dev = fa.list ? fa.list_len : nullptr;
+  r.rs_dev = fa.rs;
+  r.m_host = fa.m_host;
+  ctx->recs.push_back(r);
+  return hipSuccess;
+}
+
+int device_ready(kmpar_ctx* ctx) {
+  if (ctx->device < 0) return set_err(ctx, KMPAR_E_NODEVICE, "context has no device");
+  return KMPAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kmpar_create(int hip_device, kmpar_mode mode, kmpar_ctx** out) {
+  if (!out) return KMPAR_E_INVAL;
+  *out = nullptr;
+  if (mode != KMPAR_MODE_PLAIN_FP32 && mode != KMPAR_MODE_REFINED) return KMPAR_E_INVAL;
+  if (hip_device < -1) return KMPAR_E_INVAL;
+  if (hip_device >= 0) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device >= count) return KMPAR_E_HIP;
+  }
+  kmpar_ctx* c = new kmpar_ctx;
+  c->device = hip_device;
+  c->mode = mode;
+  *out = c;
+  return KMPAR_OK;
+}
+
+void kmpar_destroy(kmpar_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& r : ctx->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+int kmpar_profile_enable(kmpar_ctx* ctx, int on) {
+  if (!ctx) return KMPAR_E_INVAL;
+  ctx->prof = on != 0;
+  return KMPAR_OK;
+}
+
+int kmpar_profile_read(kmpar_ctx* ctx, int slot, int64_t* launches, double* total_ms,
+                       double* pairs) {
+  if (!ctx || !launches || !total_ms || !pairs) return KMPAR_E_INVAL;
+  *launches = 0;
+  *total_ms = 0.0;
+  *pairs = 0.0;
+  if (ctx->recs.empty()) return KMPAR_OK;
+  if (ctx->device < 0) return set_err(ctx, KMPAR_E_NODEVICE, "context has no device");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  std::vector<ProfRec> keep;
+  for (auto& r : ctx->recs) {
+    if (r.slot != slot) {
+      keep.push_back(r);
+      continue;
+    }
+    KMPAR_HIP(hipEventSynchronize(r.b));
+    float ms = 0.0f;
+    KMPAR_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    int64_t npts = r.npts;
+    if (r.npts_dev) {
+      int v = 0;
+      KMPAR_HIP(hipMemcpy(&v, r.npts_dev, sizeof(int), hipMemcpyDeviceToHost));
+      npts = v;
+    }
+    int64_t m = r.m_host;
+    if (r.rs_dev) {
+      int v[2] = {0, 0};
+      KMPAR_HIP(hipMemcpy(v, r.rs_dev, sizeof v, hipMemcpyDeviceToHost));
+      m = v[1] - v[0];
+    }
+    *launches += 1;
+    *total_ms += ms;
+    *pairs += (double)npts * (double)m;
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->recs.swap(keep);
+  return KMPAR_OK;
+}
+
+const char* kmpar_strerror(int status) {
+  switch (status) {
+    case KMPAR_OK: return "ok";
+    case KMPAR_E_INVAL: return "invalid argument";
+    case KMPAR_E_WORKSPACE: return "workspace too small";
+    case KMPAR_E_HIP: return "HIP runtime error";
+    case KMPAR_E_TOOFEW: return "fewer than k distinct candidates";
+    case KMPAR_E_OVERFLOW: return "a round exceeded the candidate capacity";
+    case KMPAR_E_NODEVICE: return "context has no device";
+  }
+  return "unknown status";
+}
+
+const char* kmpar_last_error(const kmpar_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+size_t kmpar_sizeof_stats(void) { return sizeof(kmpar_stats); }
+
+int kmpar_max_candidates(int64_t n, double ell, int32_t rounds, int64_t* out) {
+  if (!out || n < 1 || !ell_ok(ell) || rounds < 0 || rounds > KMPAR_MAX_ROUNDS)
+    return KMPAR_E_INVAL;
+  *out = 1 + (int64_t)rounds * cap_round_of(n, ell);
+  return KMPAR_OK;
+}
+
+int kmpar_workspace_size(const kmpar_ctx* cctx, kmpar_op op, int64_t n, int32_t d, int32_t k,
+                         double ell, int32_t rounds, kmpar_dtype dtype, size_t* bytes_out) {
+  kmpar_ctx* ctx = const_cast<kmpar_ctx*>(cctx);
+  if (!bytes_out) return set_err(ctx, KMPAR_E_INVAL, "bytes_out is NULL");
+  if (dtype != KMPAR_F32 && dtype != KMPAR_BF16 && dtype != KMPAR_FP8_E4M3)
+    return set_err(ctx, KMPAR_E_INVAL, "unknown dtype");
+  if (n < 1 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
+    return set_err(ctx, KMPAR_E_INVAL, "size out of range");
+  switch (op) {
+    case KMPAR_OP_INIT: {
+      if (k > n || !ell_ok(ell) || rounds < 0 || rounds > KMPAR_MAX_ROUNDS)
+        return set_err(ctx, KMPAR_E_INVAL, "k, ell or rounds out of range");
+      const int64_t capT = 1 + (int64_t)rounds * cap_round_of(n, ell);
+      if (capT >= (int64_t)1 << 31) return set_err(ctx, KMPAR_E_INVAL, "candidate capacity too large");
+      *bytes_out = init_layout(nullptr, n, d, k, ell, rounds).bytes;
+      return KMPAR_OK;
+    }
+    case KMPAR_OP_COST:
+    case KMPAR_OP_ASSIGN:
+    case KMPAR_OP_LLOYD:
+      *bytes_out = assign_layout(nullptr, n, d, k, op).bytes;
+      return KMPAR_OK;
+  }
+  return set_err(ctx, KMPAR_E_INVAL, "unknown op");
+}
+
+int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype, int64_t n,
+               int32_t d, int32_t k, double ell, int32_t rounds, uint64_t seed, float* centers,
+               void* ws, size_t ws_bytes, kmpar_stats* stats, const kmpar_trace* trace,
+               void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  int rc = check_common(ctx, X, row_scale, dtype, n, d);
+  if (rc) return rc;
+  if (k < 1 || k > n || k > kMaxK) return set_err(ctx, KMPAR_E_INVAL, "k=%d out of range", k);
+  if (!ell_ok(ell)) return set_err(ctx, KMPAR_E_INVAL, "ell must be finite and > 0");
+  if (rounds < 0 || rounds > KMPAR_MAX_ROUNDS)
+    return set_err(ctx, KMPAR_E_INVAL, "rounds=%d out of range", rounds);
+  if (!centers || !aligned16(centers)) return set_err(ctx, KMPAR_E_INVAL, "centers NULL/misaligned");
+  if (stats && ((uintptr_t)stats & 7u)) return set_err(ctx, KMPAR_E_INVAL, "stats misaligned");
+  if (!ws) return set_err(ctx, KMPAR_E_INVAL, "workspace is NULL");
+  size_t need = 0;
+  rc = kmpar_workspace_size(ctx, KMPAR_OP_INIT, n, d, k, ell, rounds, dtype, &need);
+  if (rc) return rc;
+  if (ws_bytes < need)
+    return set_err(ctx, KMPAR_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  if ((rc = device_ready(ctx))) return rc;
+
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int N = (int)n, DP = padded_dim(d);
+  const int cap_round = (int)cap_round_of(n, ell);
+  const int capT = 1 + rounds * cap_round;
+  InitLayout L = init_layout(ws, n, d, k, ell, rounds);
+  kmpar_stats* st = stats ? stats : L.st;
+  const uint64_t inst = 0;
+
+  // Steps 1-2: first center, D2 against it, psi.
+  KMPAR_HIP(launch_first(N, seed, inst, L.cand_point, L.rs, st, s));
+  KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, 0, 1, L.Call, L.CallT,
+                          capT, s));
+  FoldArgs fa{};
+  fa.X = X;
+  fa.row_scale = row_scale;
+  fa.n = N;
+  fa.d = d;
+  fa.C = L.Call;
+  fa.D2 = L.D2;
+  fa.A = L.A;
+  fa.rs = L.rs;
+  fa.first = 1;
+  KMPAR_HIP(timed_fold(ctx, 0, dtype, DP, fa, s));
+  KMPAR_HIP(launch_phi(L.D2, N, L.phi_part, &st->phi[0], s));
+  // Steps 3-6: rounds.
+  fa.first = 0;
+  for (int t = 1; t <= rounds; ++t) {
+    KMPAR_HIP(launch_draw(L.D2, N, &st->phi[t - 1], ell, seed, t, inst, L.cnt, L.scan_total, L.rs,
+                          cap_round, L.cand_point, st, s));
+    KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, t, cap_round, L.Call,
+                            L.CallT, capT, s));
+    fa.rs = L.rs + t;
+    KMPAR_HIP(timed_fold(ctx, 0, dtype, DP, fa, s));
+    KMPAR_HIP(launch_phi(L.D2, N, L.phi_part, &st->phi[t], s));
+  }
+  KMPAR_HIP(launch_finish_rounds(L.rs, rounds, st, s));
+  // Step 7: weights.
+  KMPAR_HIP(launch_hist(L.A, N, L.w, capT, s));
+  // Step 8: weighted k-means++.
+  int* picks = (trace && trace->center_cand) ? trace->center_cand : L.picks;
+  KMPAR_HIP(launch_recluster(L.CallT, capT, d, L.w, L.rs + rounds + 1, k, seed, inst, L.E, picks,
+                             centers, st, s));
+  if (trace) {
+    if (trace->cand_point) KMPAR_HIP(launch_copy_i32(L.cand_point, trace->cand_point, capT, s));
+    if (trace->cand_weight) KMPAR_HIP(launch_copy_i32(L.w, trace->cand_weight, capT, s));
+    if (trace->assign) KMPAR_HIP(launch_copy_i32(L.A, trace->assign, N, s));
+    if (trace->d2) KMPAR_HIP(launch_copy_i32((const int*)L.D2, (int*)trace->d2, N, s));
+  }
+  return KMPAR_OK;
+}
+
+static int assign_common(kmpar_ctx* ctx, kmpar_op op, const void* X, const float* row_scale,
+                         kmpar_dtype dtype, int64_t n, int32_t d, const float* C, int32_t m,
+                         void* ws, size_t ws_bytes, AssignLayout* L, FoldArgs* fa) {
+  int rc = check_common(ctx, X, row_scale, dtype, n, d);
+  if (rc) return rc;
+  if (m < 1 || m > kMaxK) return set_err(ctx, KMPAR_E_INVAL, "number of centers %d out of range", m);
+  if (!C || !aligned16(C)) return set_err(ctx, KMPAR_E_INVAL, "C NULL/misaligned");
+  if (!ws) return set_err(ctx, KMPAR_E_INVAL, "workspace is NULL");
+  size_t need = 0;
+  rc = kmpar_workspace_size(ctx, op, n, d, m, 1.0, 0, dtype, &need);
+  if (rc) return rc;
+  if (ws_bytes < need)
+    return set_err(ctx, KMPAR_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  if ((rc = device_ready(ctx))) return rc;
+  *L = assign_layout(ws, n, d, m, op);
+  *fa = FoldArgs{};
+  fa->X = X;
+  fa->row_scale = row_scale;
+  fa->n = (int)n;
+  fa->d = d;
+  fa->C = L->Cpad;
+  fa->rs = nullptr;
+  fa->m_host = m;
+  fa->id0_host = 0;
+  fa->D2 = L->D2;
+  fa->A = L->A;
+  fa->first = 1;
+  return KMPAR_OK;
+}
+
+int kmpar_cost(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype, int64_t n,
+               int32_t d, const float* C, int32_t m, double* phi, void* ws, size_t ws_bytes,
+               void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  if (!phi || ((uintptr_t)phi & 7u)) return set_err(ctx, KMPAR_E_INVAL, "phi NULL/misaligned");
+  AssignLayout L;
+  FoldArgs fa;
+  int rc = assign_common(ctx, KMPAR_OP_COST, X, row_scale, dtype, n, d, C, m, ws, ws_bytes, &L, &fa);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  KMPAR_HIP(launch_pad_rows(C, m, d, padded_dim(d), L.Cpad, s));
+  KMPAR_HIP(timed_fold(ctx, 0, dtype, padded_dim(d), fa, s));
+  KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi, s));
+  return KMPAR_OK;
+}
+
+int kmpar_assign(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                 int64_t n, int32_t d, const float* C, int32_t m, int32_t* assign, float* d2,
+                 void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  if (!assign || !aligned16(assign)) return set_err(ctx, KMPAR_E_INVAL, "assign NULL/misaligned");
+  if (d2 && !aligned16(d2)) return set_err(ctx, KMPAR_E_INVAL, "d2 misaligned");
+  AssignLayout L;
+  FoldArgs fa;
+  int rc = assign_common(ctx, KMPAR_OP_ASSIGN, X, row_scale, dtype, n, d, C, m, ws, ws_bytes, &L, &fa);
+  if (rc) return rc;
+  fa.A = assign;
+  if (d2) fa.D2 = d2;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  KMPAR_HIP(launch_pad_rows(C, m, d, padded_dim(d), L.Cpad, s));
+  KMPAR_HIP(timed_fold(ctx, 0, dtype, padded_dim(d), fa, s));
+  return KMPAR_OK;
+}
+
+int lloyd_step(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype, int64_t n,
+               int32_t d, float* C, int32_t k, int32_t* assign, double* phi, void* ws,
+               size_t ws_bytes, void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  if (assign && !aligned16(assign)) return set_err(ctx, KMPAR_E_INVAL, "assign misaligned");
+  if (phi && ((uintptr_t)phi & 7u)) return set_err(ctx, KMPAR_E_INVAL, "phi misaligned");
+  if (k > n) return set_err(ctx, KMPAR_E_INVAL, "k=%d > n", k);
+  AssignLayout L;
+  FoldArgs fa;
+  int rc = assign_common(ctx, KMPAR_OP_LLOYD, X, row_scale, dtype, n, d, C, k, ws, ws_bytes, &L, &fa);
+  if (rc) return rc;
+  if (assign) fa.A = assign;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  KMPAR_HIP(launch_pad_rows(C, k, d, padded_dim(d), L.Cpad, s));
+  KMPAR_HIP(timed_fold(ctx, 0, dtype, padded_dim(d), fa, s));
+  if (phi) KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi, s));
+  KMPAR_HIP(launch_lloyd_update(dtype, X, row_scale, (int)n, d, fa.A, k, C, L.lw, s));
+  return KMPAR_OK;
+}
+
+}  // extern "C"

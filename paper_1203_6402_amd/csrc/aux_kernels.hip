@@ -1,0 +1,586 @@
+// The passes of k-means|| around the distance fold: first center, cost phi,
+// Bernoulli draws with order-preserving compaction, candidate gather, the
+// Step-7 weight histogram, the Step-8 weighted k-means++ recluster and the
+// Lloyd centroid update.  Every reduction and scan runs in a fixed order, so
+// results are bit-reproducible.
+#include <math.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace kmpar {
+
+#define KMPAR_RET_LAST() return hipGetLastError()
+
+// --------------------------------------------------------------- first center
+// Algorithm 2 step 1: the first center is point Index(n) of the FIRST stream.
+__global__ void k_first(int n, uint64_t seed, uint64_t inst, int* cand_point, int* rs,
+                        kmpar_stats* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int i0 = (int)philox_index(seed, kTagFirst, 0, 0, inst, (uint64_t)n);
+  cand_point[0] = i0;
+  rs[0] = 0;
+  rs[1] = 1;
+  st->round_count[0] = 1;
+  st->status = KMPAR_OK;
+  st->n_rescanned = 0;
+}
+
+hipError_t launch_first(int n, uint64_t seed, uint64_t inst, int* cand_point, int* rs,
+                        kmpar_stats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_first, dim3(1), dim3(64), 0, s, n, seed, inst, cand_point, rs, st);
+  KMPAR_RET_LAST();
+}
+
+// --------------------------------------------------------------------- gather
+// Copies the m_t rows kept in round t into the candidate buffers: row-major
+// Call[id][DP] (read by the fold) and dim-major CallT[e][capT] (read by the
+// recluster).  Pads with zeros beyond d.
+template <typename T>
+__global__ void k_gather(const T* X, const float* row_scale, int d, int DP, const int* cand_point,
+                         const int* rs, int t, float* Call, float* CallT, int capT) {
+  const int id0 = rs[t];
+  const int m = rs[t + 1] - id0;
+  const int j = blockIdx.x;
+  if (j >= m) return;
+  const int c = id0 + j;
+  const int p = cand_point[c];
+  const float sc = row_scale_of<T>(row_scale, p);
+  for (int e = threadIdx.x; e < DP; e += blockDim.x) {
+    const float v = (e < d) ? Elem<T>::get(X, (int64_t)p * d + e, sc) : 0.0f;
+    Call[(int64_t)c * DP + e] = v;
+    CallT[(int64_t)e * capT + c] = v;
+  }
+}
+
+hipError_t launch_gather(kmpar_dtype dt, const void* X, const float* row_scale, int d, int DP,
+                         const int* cand_point, const int* rs, int t, int cap_round, float* Call,
+                         float* CallT, int capT, hipStream_t s) {
+  const dim3 grid(cap_round), block(64);
+  switch (dt) {
+    case KMPAR_F32:
+      hipLaunchKernelGGL(k_gather<float>, grid, block, 0, s, (const float*)X, row_scale, d, DP,
+                         cand_point, rs, t, Call, CallT, capT);
+      break;
+    case KMPAR_BF16:
+      hipLaunchKernelGGL(k_gather<bf16_t>, grid, block, 0, s, (const bf16_t*)X, row_scale, d, DP,
+                         cand_point, rs, t, Call, CallT, capT);
+      break;
+    case KMPAR_FP8_E4M3:
+      hipLaunchKernelGGL(k_gather<fp8_t>, grid, block, 0, s, (const fp8_t*)X, row_scale, d, DP,
+                         cand_point, rs, t, Call, CallT, capT);
+      break;
+  }
+  KMPAR_RET_LAST();
+}
+
+// Pads m rows of length d into rows of length DP.
+__global__ void k_pad_rows(const float* C, int m, int d, int DP, float* Cpad) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * DP) return;
+  const int r = (int)(idx / DP), e = (int)(idx % DP);
+  Cpad[idx] = (e < d) ? C[(int64_t)r * d + e] : 0.0f;
+}
+
+hipError_t launch_pad_rows(const float* C, int m, int d, int DP, float* Cpad, hipStream_t s) {
+  const int64_t tot = (int64_t)m * DP;
+  hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, C, m, d,
+                     DP, Cpad);
+  KMPAR_RET_LAST();
+}
+
+// ------------------------------------------------------------------ cost phi
+// phi = sum_i D2_i in FP64: fixed chunks per block, fixed tree per block, then
+// one block sums the block partials in order (Section 3.5: per-partition
+// partial costs summed by one reducer).
+__global__ __launch_bounds__(256) void k_phi_partial(const float* D2, int n, double* part) {
+  __shared__ double sh[8];
+  const int base = blockIdx.x * kPhiChunk;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < kPhiChunk / 256; ++r) {
+    const int i = base + r * 256 + threadIdx.x;
+    if (i < n) acc += (double)D2[i];
+  }
+  const double tot = block_sum<double, 256>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_phi_final(const double* part, int nb, double* out) {
+  __shared__ double sh[8];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
+  const double tot = block_sum<double, 256>(acc, sh);
+  if (threadIdx.x == 0) *out = tot;
+}
+
+hipError_t launch_phi(const float* D2, int n, double* part, double* out, hipStream_t s) {
+  const int nb = (n + kPhiChunk - 1) / kPhiChunk;
+  hipLaunchKernelGGL(k_phi_partial, dim3(nb), dim3(256), 0, s, D2, n, part);
+  hipLaunchKernelGGL(k_phi_final, dim3(1), dim3(256), 0, s, part, nb, out);
+  KMPAR_RET_LAST();
+}
+
+// ---------------------------------------------------------------------- draw
+// Algorithm 2 step 4: point i is kept in round t iff u < p with
+// p = min(1, ell * D2_i / phi) and u = U(seed, ROUND, (i, t, inst)).
+__device__ __forceinline__ int keep_point(const float* D2, int i, double phi, double ell,
+                                          uint64_t seed, int t, uint64_t inst) {
+  if (!(phi > 0.0)) return 0;
+  double p = ell * (double)D2[i] / phi;
+  if (p > 1.0) p = 1.0;
+  const double u = philox_uniform(seed, kTagRound, (uint64_t)i, (uint64_t)t, inst);
+  return u < p ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_draw_count(const float* D2, int n, const double* phi,
+                                                    double ell, uint64_t seed, int t,
+                                                    uint64_t inst, int* cnt) {
+  __shared__ int sh[8];
+  const double ph = *phi;
+  const int base = blockIdx.x * kDrawChunk;
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < kDrawChunk / 256; ++r) {
+    const int i = base + r * 256 + threadIdx.x;
+    if (i < n) c += keep_point(D2, i, ph, ell, seed, t, inst);
+  }
+  const int tot = block_sum<int, 256>(c, sh);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+}
+
+// In-place exclusive scan of a[0..L) by one block; *total = sum.
+__global__ __launch_bounds__(1024) void k_scan1(int* a, int L, int* total) {
+  __shared__ long long sh[17];
+  const int R = (L + 1023) / 1024;
+  const int lo = min(L, (int)threadIdx.x * R), hi = min(L, lo + R);
+  long long s = 0;
+  for (int j = lo; j < hi; ++j) s += a[j];
+  long long tot;
+  long long run = block_excl_scan<long long, 1024>(s, sh, &tot);
+  for (int j = lo; j < hi; ++j) {
+    const int v = a[j];
+    a[j] = (int)run;
+    run += v;
+  }
+  if (threadIdx.x == 0 && total) *total = (int)tot;
+}
+
+// Commits round t: m_t = min(total, cap), rs[t+1] = rs[t] + m_t.
+__global__ void k_round_commit(const int* total, int* rs, int t, int cap, kmpar_stats* st) {
+  if (threadIdx.x != 0) return;
+  const int tot = *total;
+  const int m = tot < cap ? tot : cap;
+  rs[t + 1] = rs[t] + m;
+  st->round_count[t] = m;
+  if (tot > cap) st->status = KMPAR_E_OVERFLOW;
+}
+
+// Writes the kept point indices in increasing point order.
+__global__ __launch_bounds__(256) void k_draw_write(const float* D2, int n, const double* phi,
+                                                    double ell, uint64_t seed, int t,
+                                                    uint64_t inst, const int* off, const int* rs,
+                                                    int cap, int* cand_point) {
+  __shared__ int sh[8];
+  const double ph = *phi;
+  const int base = blockIdx.x * kDrawChunk;
+  int run = off[blockIdx.x];
+  const int start = rs[t];
+  for (int r = 0; r < kDrawChunk / 256; ++r) {
+    const int i = base + r * 256 + threadIdx.x;
+    const int keep = (i < n) ? keep_point(D2, i, ph, ell, seed, t, inst) : 0;
+    int tot;
+    const int rank = block_excl_scan<int, 256>(keep, sh, &tot);
+    if (keep && run + rank < cap) cand_point[start + run + rank] = i;
+    run += tot;
+  }
+}
+
+hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, uint64_t seed, int t,
+                       uint64_t inst, int* cnt, int* scan_total, int* rs, int cap_round,
+                       int* cand_point, kmpar_stats* st, hipStream_t s) {
+  const int nb = (n + kDrawChunk - 1) / kDrawChunk;
+  hipLaunchKernelGGL(k_draw_count, dim3(nb), dim3(256), 0, s, D2, n, phi, ell, seed, t, inst, cnt);
+  hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, cnt, nb, scan_total);
+  hipLaunchKernelGGL(k_round_commit, dim3(1), dim3(64), 0, s, scan_total, rs, t, cap_round, st);
+  hipLaunchKernelGGL(k_draw_write, dim3(nb), dim3(256), 0, s, D2, n, phi, ell, seed, t, inst, cnt,
+                     rs, cap_round, cand_point);
+  KMPAR_RET_LAST();
+}
+
+__global__ void k_finish_rounds(const int* rs, int rounds, kmpar_stats* st) {
+  if (threadIdx.x == 0) st->n_candidates = rs[rounds + 1];
+}
+
+hipError_t launch_finish_rounds(const int* rs, int rounds, kmpar_stats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_rounds, dim3(1), dim3(64), 0, s, rs, rounds, st);
+  KMPAR_RET_LAST();
+}
+
+// ------------------------------------------------------------ fills / copies
+__global__ void k_fill_i32(int* p, int v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v,
+                     count);
+  KMPAR_RET_LAST();
+}
+__global__ void k_copy_i32(const int* src, int* dst, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+hipError_t launch_copy_i32(const int* src, int* dst, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, src, dst,
+                     count);
+  KMPAR_RET_LAST();
+}
+
+// ------------------------------------------------------------- Step 7 weights
+// w_c = |{i : A_i = c}|, counted in LDS per block, then merged with integer
+// atomics (exact, so the result does not depend on their order).
+__global__ __launch_bounds__(256) void k_hist_lds(const int* A, int n, int* w, int nbins) {
+  extern __shared__ int h[];
+  for (int b = threadIdx.x; b < nbins; b += 256) h[b] = 0;
+  __syncthreads();
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int a = A[i];
+    if (a >= 0 && a < nbins) atomicAdd(&h[a], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += 256)
+    if (h[b]) atomicAdd(&w[b], h[b]);
+}
+
+__global__ __launch_bounds__(256) void k_hist_global(const int* A, int n, int* w, int nbins) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int a = A[i];
+    if (a >= 0 && a < nbins) atomicAdd(&w[a], 1);
+  }
+}
+
+constexpr int kLdsBudget = 64 * 1024;
+
+hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s) {
+  hipError_t e = launch_fill_i32(w, 0, nbins, s);
+  if (e != hipSuccess) return e;
+  const int blocks = 512;
+  if ((size_t)nbins * 4 <= (size_t)kLdsBudget) {
+    hipLaunchKernelGGL(k_hist_lds, dim3(blocks), dim3(256), (size_t)nbins * 4, s, A, n, w, nbins);
+  } else {
+    hipLaunchKernelGGL(k_hist_global, dim3(blocks), dim3(256), 0, s, A, n, w, nbins);
+  }
+  KMPAR_RET_LAST();
+}
+
+// ---------------------------------------------------------- Step 8 recluster
+// Weighted k-means++ (Algorithm 1 with weights) on the candidates, one block.
+// Pick 0 has probability w_j / sum w (integer prefix, exact); pick s >= 1 has
+// probability w_j E_j / T with E_j the FP32 direct-form distance to the
+// nearest earlier pick and T accumulated in FP64.  Pick s takes the smallest
+// j whose running sum exceeds u*T, u = U(seed, RECL, (s, 0, inst)).  Each
+// thread owns a contiguous run of candidates for the running sums.
+constexpr int kReclBlock = 1024;
+
+template <bool E_LDS>
+__global__ __launch_bounds__(kReclBlock) void k_recluster(const float* CallT, int capT, int d,
+                                                          const int* w, const int* rs_end, int k,
+                                                          uint64_t seed, uint64_t inst,
+                                                          float* E_glob, int* picks,
+                                                          float* centers, kmpar_stats* st) {
+  extern __shared__ float E_sh[];
+  __shared__ double bounds[kReclBlock + 1];
+  __shared__ double shd[kReclBlock / kWave + 1];
+  __shared__ long long shl[kReclBlock / kWave + 1];
+  __shared__ float cp[256];
+  __shared__ int pick_sh;
+  float* E = E_LDS ? E_sh : E_glob;
+  const int m = *rs_end;
+  const int tid = threadIdx.x;
+  const int R = (m + kReclBlock - 1) / kReclBlock;
+  const int lo = min(m, tid * R), hi = min(m, lo + R);
+
+  int made = 0;
+  for (int s = 0; s < k; ++s) {
+    const double u = philox_uniform(seed, kTagRecluster, (uint64_t)s, 0, inst);
+    if (tid == 0) pick_sh = 0x7fffffff;
+    double T;
+    if (s == 0) {
+      long long loc = 0;
+      for (int j = lo; j < hi; ++j) loc += w[j];
+      long long tot;
+      const long long ex = block_excl_scan<long long, kReclBlock>(loc, shl, &tot);
+      bounds[tid] = (double)ex;
+      if (tid == 0) bounds[kReclBlock] = (double)tot;
+      T = (double)tot;
+    } else {
+      double loc = 0.0;
+      for (int j = lo; j < hi; ++j) loc += (double)w[j] * (double)E[j];
+      double tot;
+      const double ex = block_excl_scan<double, kReclBlock>(loc, shd, &tot);
+      bounds[tid] = ex;
+      if (tid == 0) bounds[kReclBlock] = tot;
+      T = tot;
+    }
+    __syncthreads();
+    if (!(T > 0.0)) break;
+    const double thr = u * T;
+    const double b0 = bounds[tid], b1 = bounds[tid + 1];
+    if (b0 <= thr && thr < b1) {
+      double run = b0;
+      int pick = -1, last = -1;
+      for (int j = lo; j < hi; ++j) {
+        const double v = (s == 0) ? (double)w[j] : (double)w[j] * (double)E[j];
+        run += v;
+        if (v > 0.0) last = j;
+        if (v > 0.0 && run > thr) {
+          pick = j;
+          break;
+        }
+      }
+      // Bounds of neighbouring threads come from different FP64 association
+      // orders; should two runs claim thr, the lower candidate id wins.
+      atomicMin(&pick_sh, pick >= 0 ? pick : (last >= 0 ? last : 0x7fffffff));
+    }
+    __syncthreads();
+    if (pick_sh == 0x7fffffff) {
+      // thr fell at or beyond the total by rounding: take the last candidate
+      // with positive mass (thread runs are ordered, so scan from the end).
+      if (tid == 0) {
+        pick_sh = -1;
+        for (int j = m - 1; j >= 0; --j) {
+          const double v = (s == 0) ? (double)w[j] : (double)w[j] * (double)E[j];
+          if (v > 0.0) {
+            pick_sh = j;
+            break;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int pick = pick_sh;
+    if (pick < 0) break;
+    for (int e = tid; e < d; e += kReclBlock) {
+      const float v = CallT[(int64_t)e * capT + pick];
+      cp[e] = v;
+      centers[(int64_t)s * d + e] = v;
+    }
+    if (tid == 0) picks[s] = pick;
+    __syncthreads();
+    for (int j = tid; j < m; j += kReclBlock) {
+      float acc = 0.0f;
+      for (int e = 0; e < d; ++e) {
+        const float t = CallT[(int64_t)e * capT + j] - cp[e];
+        acc = fmaf(t, t, acc);
+      }
+      E[j] = (s == 0) ? acc : fminf(E[j], acc);
+    }
+    __syncthreads();
+    made = s + 1;
+  }
+  if (tid == 0) {
+    st->n_centers = made;
+    if (made < k && st->status == KMPAR_OK) st->status = KMPAR_E_TOOFEW;
+  }
+}
+
+hipError_t launch_recluster(const float* CallT, int capT, int d, const int* w, const int* rs_end,
+                            int k, uint64_t seed, uint64_t inst, float* E_global, int* picks,
+                            float* centers, kmpar_stats* st, hipStream_t s) {
+  const size_t e_bytes = (size_t)capT * sizeof(float);
+  if (e_bytes <= 48 * 1024) {
+    hipLaunchKernelGGL(k_recluster<true>, dim3(1), dim3(kReclBlock), e_bytes, s, CallT, capT, d, w,
+                       rs_end, k, seed, inst, E_global, picks, centers, st);
+  } else {
+    hipLaunchKernelGGL(k_recluster<false>, dim3(1), dim3(kReclBlock), 0, s, CallT, capT, d, w,
+                       rs_end, k, seed, inst, E_global, picks, centers, st);
+  }
+  KMPAR_RET_LAST();
+}
+
+// ------------------------------------------------------------- Lloyd update
+// Deterministic centroid update (Section 3.1 centroid; Section 1 Lloyd):
+//  1. per-block cluster counts   bcnt[c * nbs + b]
+//  2. exclusive scan of the flattened table -> each (cluster, block) slot
+//  3. stable scatter of point indices into cluster-sorted order
+//  4. cluster chunks of kSegChunk sorted points, summed in FP64 in order
+//  5. per cluster: sum of its chunk sums in order, divided by the count.
+__global__ __launch_bounds__(256) void k_sort_count(const int* A, int n, int k, int* bcnt,
+                                                    int nbs) {
+  extern __shared__ int h[];
+  for (int c = threadIdx.x; c < k; c += 256) h[c] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortChunk;
+  for (int r = threadIdx.x; r < kSortChunk; r += 256) {
+    const int i = base + r;
+    if (i < n) {
+      const int a = A[i];
+      if (a >= 0 && a < k) atomicAdd(&h[a], 1);
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += 256) bcnt[(int64_t)c * nbs + blockIdx.x] = h[c];
+}
+
+// Three-phase exclusive scan of a[0..L): tile sums, scan of the tile sums,
+// tile-local scans plus offsets.
+__global__ __launch_bounds__(256) void k_scan_tiles(const int* a, int64_t L, int* tsum) {
+  __shared__ int sh[8];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int s = 0;
+  for (int r = threadIdx.x; r < kScanTile; r += 256) {
+    const int64_t j = base + r;
+    if (j < L) s += a[j];
+  }
+  const int tot = block_sum<int, 256>(s, sh);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(int* a, int64_t L, const int* toff) {
+  __shared__ int sh[8];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int run = toff[blockIdx.x];
+  for (int r = 0; r < kScanTile; r += 256) {
+    const int64_t j = base + r + threadIdx.x;
+    const int v = (j < L) ? a[j] : 0;
+    int tot;
+    const int ex = block_excl_scan<int, 256>(v, sh, &tot);
+    if (j < L) a[j] = run + ex;
+    run += tot;
+  }
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x % kWave;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// One wave per block scatters its chunk in point order; equal keys inside a
+// 64-point tile are ranked by lane, and the per-cluster cursor advances once
+// per key group.
+__global__ __launch_bounds__(64) void k_sort_scatter(const int* A, int n, int k, const int* bbase,
+                                                     int nbs, int* sorted) {
+  extern __shared__ int cur[];
+  for (int c = threadIdx.x; c < k; c += 64) cur[c] = bbase[(int64_t)c * nbs + blockIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x;
+  const int base = blockIdx.x * kSortChunk;
+  for (int tile = 0; tile < kSortChunk; tile += 64) {
+    const int i = base + tile + lane;
+    const int key0 = (i < n) ? A[i] : -1;
+    const bool valid = key0 >= 0 && key0 < k;
+    const int key = valid ? key0 : -1;
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int lkey = __shfl(key, leader, kWave);
+      const uint64_t grp = __ballot(valid && key == lkey);
+      const int pos0 = cur[lkey];
+      if (valid && key == lkey) sorted[pos0 + __popcll(grp & lanemask_lt())] = i;
+      __syncthreads();
+      if (lane == leader) cur[lkey] = pos0 + __popcll(grp);
+      __syncthreads();
+      pending &= ~grp;
+    }
+  }
+}
+
+// Cluster offsets and the chunk list: cluster c owns sorted positions
+// [coff[c], coff[c+1]) split into chunks cstart[c] .. cstart[c+1]-1.
+__global__ __launch_bounds__(1024) void k_chunk_list(const int* bbase, int nbs, int k, int n,
+                                                     int* coff, int* cstart) {
+  __shared__ long long sh[17];
+  const int R = (k + 1023) / 1024;
+  const int lo = min(k, (int)threadIdx.x * R), hi = min(k, lo + R);
+  long long s = 0;
+  for (int c = lo; c < hi; ++c) {
+    const int o = bbase[(int64_t)c * nbs];
+    const int o1 = (c + 1 < k) ? bbase[(int64_t)(c + 1) * nbs] : n;
+    coff[c] = o;
+    s += (o1 - o + kSegChunk - 1) / kSegChunk;
+  }
+  long long tot;
+  long long run = block_excl_scan<long long, 1024>(s, sh, &tot);
+  for (int c = lo; c < hi; ++c) {
+    const int o = bbase[(int64_t)c * nbs];
+    const int o1 = (c + 1 < k) ? bbase[(int64_t)(c + 1) * nbs] : n;
+    cstart[c] = (int)run;
+    run += (o1 - o + kSegChunk - 1) / kSegChunk;
+  }
+  if (threadIdx.x == 0) {
+    coff[k] = n;
+    cstart[k] = (int)tot;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_seg_sum(const T* X, const float* row_scale, int d,
+                                                const int* sorted, const int* coff,
+                                                const int* cstart, int k, double* part) {
+  const int q = blockIdx.x;
+  if (q >= cstart[k]) return;
+  int lo = 0, hi = k;  // largest c with cstart[c] <= q
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (cstart[mid] <= q) lo = mid; else hi = mid;
+  }
+  const int c = lo;
+  const int p0 = coff[c] + (q - cstart[c]) * kSegChunk;
+  const int p1 = min(coff[c + 1], p0 + kSegChunk);
+  for (int e = threadIdx.x; e < d; e += 64) {
+    double acc = 0.0;
+    for (int p = p0; p < p1; ++p) {
+      const int i = sorted[p];
+      acc += (double)Elem<T>::get(X, (int64_t)i * d + e, row_scale_of<T>(row_scale, i));
+    }
+    part[(int64_t)q * d + e] = acc;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_centroid(const double* part, const int* coff,
+                                                 const int* cstart, int d, float* C) {
+  const int c = blockIdx.x;
+  const int cnt = coff[c + 1] - coff[c];
+  if (cnt == 0) return;  // an empty cluster keeps its center
+  for (int e = threadIdx.x; e < d; e += 64) {
+    double s = 0.0;
+    for (int q = cstart[c]; q < cstart[c + 1]; ++q) s += part[(int64_t)q * d + e];
+    C[(int64_t)c * d + e] = (float)(s / (double)cnt);
+  }
+}
+
+hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
+                               const int* A, int k, float* C, const LloydWs& w, hipStream_t s) {
+  const int nbs = (n + kSortChunk - 1) / kSortChunk;
+  const int64_t L = (int64_t)k * nbs;
+  const int ntiles = (int)((L + kScanTile - 1) / kScanTile);
+  const size_t lds = (size_t)k * sizeof(int);
+  hipLaunchKernelGGL(k_sort_count, dim3(nbs), dim3(256), lds, s, A, n, k, w.bcnt, nbs);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, w.bcnt, L, w.scan_tmp);
+  hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, w.scan_tmp, ntiles, (int*)nullptr);
+  hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(256), 0, s, w.bcnt, L, w.scan_tmp);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(nbs), dim3(64), lds, s, A, n, k, w.bcnt, nbs, w.sorted);
+  hipLaunchKernelGGL(k_chunk_list, dim3(1), dim3(1024), 0, s, w.bcnt, nbs, k, n, w.coff, w.cstart);
+  const int max_chunks = (n + kSegChunk - 1) / kSegChunk + k;
+  switch (dt) {
+    case KMPAR_F32:
+      hipLaunchKernelGGL(k_seg_sum<float>, dim3(max_chunks), dim3(64), 0, s, (const float*)X,
+                         row_scale, d, w.sorted, w.coff, w.cstart, k, w.part);
+      break;
+    case KMPAR_BF16:
+      hipLaunchKernelGGL(k_seg_sum<bf16_t>, dim3(max_chunks), dim3(64), 0, s, (const bf16_t*)X,
+                         row_scale, d, w.sorted, w.coff, w.cstart, k, w.part);
+      break;
+    case KMPAR_FP8_E4M3:
+      hipLaunchKernelGGL(k_seg_sum<fp8_t>, dim3(max_chunks), dim3(64), 0, s, (const fp8_t*)X,
+                         row_scale, d, w.sorted, w.coff, w.cstart, k, w.part);
+      break;
+  }
+  hipLaunchKernelGGL(k_centroid, dim3(k), dim3(64), 0, s, w.part, w.coff, w.cstart, d, C);
+  KMPAR_RET_LAST();
+}
+
+}  // namespace kmpar

@@ -1,0 +1,73 @@
+// Host-side launchers of the kmpar kernels (internal to libkmpar.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kmpar.h"
+
+namespace kmpar {
+
+// Padded row length used for candidate / center rows (zeros past d).
+int padded_dim(int d);
+
+// Point tile of the direct-form distance pass and the other chunked passes.
+constexpr int kFoldBlock = 256;
+constexpr int kPhiChunk = 4096;    // points per block of the phi reduction
+constexpr int kDrawChunk = 2048;   // points per block of the draw passes
+constexpr int kSortChunk = 4096;   // points per block of the Lloyd counting sort
+constexpr int kSegChunk = 2048;    // sorted points per block of the centroid sums
+
+// Parameters of one distance-fold pass: every listed point meets the m
+// candidate rows C[id0 .. id0+m) (DP-padded FP32) and keeps the nearest.
+struct FoldArgs {
+  const void* X;
+  const float* row_scale;
+  int n;
+  int d;
+  const float* C;        // candidate rows, row r at C + r*DP
+  const int* rs;         // device: id0 = rs[0], m = rs[1] - rs[0]  (nullable)
+  int m_host;            // used when rs == nullptr
+  int id0_host;
+  float* D2;
+  int* A;
+  int first;             // 1: previous D2/A are ignored
+  const int* list;       // nullable: only points list[0 .. *list_len)
+  const int* list_len;
+  int list_cap;          // grid bound when list != nullptr
+};
+
+hipError_t launch_fold_direct(kmpar_dtype dt, int DP, const FoldArgs& a, hipStream_t s);
+
+hipError_t launch_first(int n, uint64_t seed, uint64_t inst, int* cand_point, int* rs,
+                        kmpar_stats* st, hipStream_t s);
+hipError_t launch_gather(kmpar_dtype dt, const void* X, const float* row_scale, int d, int DP,
+                         const int* cand_point, const int* rs, int t, int cap_round, float* Call,
+                         float* CallT, int capT, hipStream_t s);
+hipError_t launch_phi(const float* D2, int n, double* part, double* out, hipStream_t s);
+hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, uint64_t seed, int t,
+                       uint64_t inst, int* cnt, int* scan_total, int* rs, int cap_round,
+                       int* cand_point, kmpar_stats* st, hipStream_t s);
+hipError_t launch_finish_rounds(const int* rs, int rounds, kmpar_stats* st, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s);
+hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s);
+hipError_t launch_recluster(const float* CallT, int capT, int d, const int* w, const int* rs_end,
+                            int k, uint64_t seed, uint64_t inst, float* E_global, int* picks,
+                            float* centers, kmpar_stats* st, hipStream_t s);
+hipError_t launch_pad_rows(const float* C, int m, int d, int DP, float* Cpad, hipStream_t s);
+hipError_t launch_copy_i32(const int* src, int* dst, int64_t count, hipStream_t s);
+
+// Lloyd centroid update by a deterministic counting sort.
+struct LloydWs {
+  int* bcnt;      // k * nbs
+  int* scan_tmp;  // ceil(k*nbs / kScanTile) + 1
+  int* sorted;    // n
+  int* cstart;    // k + 1
+  int* coff;      // k + 1
+  double* part;   // (ceil(n / kSegChunk) + k) * d
+};
+constexpr int kScanTile = 4096;
+hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
+                               const int* A, int k, float* C, const LloydWs& w, hipStream_t s);
+
+}  // namespace kmpar

@@ -1,0 +1,255 @@
+"""Python binding of libkmpar.so (the C ABI in include/kmpar.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  Importing this module fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkmpar.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MAX_ROUNDS = 64
+F32, BF16, FP8_E4M3 = 0, 1, 2
+MODE_PLAIN_FP32, MODE_REFINED = 0, 1
+OP_INIT, OP_COST, OP_ASSIGN, OP_LLOYD = 0, 1, 2, 3
+OK, E_INVAL, E_WORKSPACE, E_HIP, E_TOOFEW, E_OVERFLOW, E_NODEVICE = 0, -1, -2, -3, -4, -5, -6
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_double * (MAX_ROUNDS + 1)),
+                ("round_count", ctypes.c_int32 * (MAX_ROUNDS + 1)),
+                ("n_candidates", ctypes.c_int32),
+                ("n_centers", ctypes.c_int32),
+                ("status", ctypes.c_int32),
+                ("n_rescanned", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("cand_point", ctypes.c_void_p), ("cand_weight", ctypes.c_void_p),
+                ("center_cand", ctypes.c_void_p), ("assign", ctypes.c_void_p),
+                ("d2", ctypes.c_void_p)]
+
+
+_vp, _i64, _i32, _u64, _dbl, _sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
+_lib.kmpar_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]
+_lib.kmpar_destroy.argtypes = [_vp]
+_lib.kmpar_strerror.argtypes = [ctypes.c_int]
+_lib.kmpar_strerror.restype = ctypes.c_char_p
+_lib.kmpar_last_error.argtypes = [_vp]
+_lib.kmpar_last_error.restype = ctypes.c_char_p
+_lib.kmpar_sizeof_stats.restype = _sz
+_lib.kmpar_max_candidates.argtypes = [_i64, _dbl, _i32, ctypes.POINTER(_i64)]
+_lib.kmpar_workspace_size.argtypes = [_vp, ctypes.c_int, _i64, _i32, _i32, _dbl, _i32,
+                                      ctypes.c_int, ctypes.POINTER(_sz)]
+_lib.kmpar_init.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _i32, _dbl, _i32, _u64,
+                            _vp, _vp, _sz, _vp, ctypes.POINTER(Trace), _vp]
+_lib.kmpar_cost.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _vp, _vp, _sz, _vp]
+_lib.kmpar_assign.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _vp, _vp, _vp,
+                              _sz, _vp]
+_lib.lloyd_step.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _vp, _vp, _vp,
+                            _sz, _vp]
+_lib.kmpar_profile_enable.argtypes = [_vp, ctypes.c_int]
+_lib.kmpar_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i64),
+                                    ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]
+assert _lib.kmpar_sizeof_stats() == ctypes.sizeof(Stats), "kmpar_stats layout mismatch"
+
+EXPORTED = ["kmpar_create", "kmpar_destroy", "kmpar_strerror", "kmpar_last_error",
+            "kmpar_sizeof_stats", "kmpar_max_candidates", "kmpar_workspace_size", "kmpar_init",
+            "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_profile_enable",
+            "kmpar_profile_read"]
+SLOT_FOLD_DIRECT = 0
+
+
+class KmparError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"kmpar status {status} ({_lib.kmpar_strerror(status).decode()}): {msg}")
+        self.status = status
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def dtype_code(X: torch.Tensor, row_scale) -> int:
+    if X.dtype == torch.float32:
+        return F32
+    if X.dtype == torch.bfloat16:
+        return BF16
+    if X.dtype in (torch.uint8, getattr(torch, "float8_e4m3fn", None)):
+        if row_scale is None:
+            raise ValueError("FP8 input needs a per-row scale")
+        return FP8_E4M3
+    raise TypeError(f"unsupported X dtype {X.dtype}")
+
+
+def max_candidates(n: int, ell: float, rounds: int) -> int:
+    out = _i64(0)
+    rc = _lib.kmpar_max_candidates(n, ell, rounds, ctypes.byref(out))
+    if rc:
+        raise KmparError(rc, "kmpar_max_candidates")
+    return int(out.value)
+
+
+@dataclass
+class InitResult:
+    centers: torch.Tensor
+    stats: dict
+    trace: dict | None
+
+
+class Context:
+    """One library context on one device; caches its workspace."""
+
+    def __init__(self, device: int | None = 0, mode: int = MODE_PLAIN_FP32):
+        h = _vp()
+        dev = -1 if device is None else int(device)
+        rc = _lib.kmpar_create(dev, mode, ctypes.byref(h))
+        if rc:
+            raise KmparError(rc, "kmpar_create")
+        self._h = h
+        self.device = dev
+        self.mode = mode
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.kmpar_destroy(h)
+            self._h = None
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, rc: int, what: str):
+        if rc:
+            raise KmparError(rc, f"{what}: {_lib.kmpar_last_error(self._h).decode()}")
+
+    def workspace_size(self, op, n, d, k, ell=1.0, rounds=0, dtype=F32) -> int:
+        out = _sz(0)
+        self._check(_lib.kmpar_workspace_size(self._h, op, n, d, k, ell, rounds, dtype,
+                                              ctypes.byref(out)), "kmpar_workspace_size")
+        return int(out.value)
+
+    def _workspace(self, nbytes: int, device) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes or self._ws.device != device:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        return self._ws
+
+    @staticmethod
+    def _x(X, row_scale):
+        if not X.is_contiguous():
+            raise ValueError("X must be contiguous row-major")
+        if X.dim() != 2:
+            raise ValueError("X must be 2-D")
+        return dtype_code(X, row_scale)
+
+    def profile(self, on: bool = True):
+        self._check(_lib.kmpar_profile_enable(self._h, 1 if on else 0), "kmpar_profile_enable")
+
+    def profile_read(self, slot: int = SLOT_FOLD_DIRECT) -> dict:
+        """Launch count, summed milliseconds and summed point-center pairs of
+        the timed launches of one distance kernel (clears them)."""
+        la, ms, pr = _i64(0), _dbl(0), _dbl(0)
+        self._check(_lib.kmpar_profile_read(self._h, slot, ctypes.byref(la), ctypes.byref(ms),
+                                            ctypes.byref(pr)), "kmpar_profile_read")
+        return {"launches": int(la.value), "ms": float(ms.value), "pairs": float(pr.value)}
+
+    # ----------------------------------------------------------------- calls
+    def init(self, X: torch.Tensor, k: int, ell: float, rounds: int, seed: int = 0,
+             row_scale: torch.Tensor | None = None, trace: bool = False,
+             stream=None, check: bool = True) -> InitResult:
+        dt = self._x(X, row_scale)
+        n, d = X.shape
+        ws = self._workspace(self.workspace_size(OP_INIT, n, d, k, ell, rounds, dt), X.device)
+        centers = torch.empty(k, d, dtype=torch.float32, device=X.device)
+        st = torch.zeros(ctypes.sizeof(Stats), dtype=torch.uint8, device=X.device)
+        tr = None
+        trp = None
+        if trace:
+            cap = max_candidates(n, ell, rounds)
+            i32 = dict(dtype=torch.int32, device=X.device)
+            tr = {"cand_point": torch.empty(cap, **i32), "cand_weight": torch.empty(cap, **i32),
+                  "center_cand": torch.full((k,), -1, **i32), "assign": torch.empty(n, **i32),
+                  "d2": torch.empty(n, dtype=torch.float32, device=X.device)}
+            trp = Trace(*(tr[f].data_ptr() for f in ("cand_point", "cand_weight", "center_cand",
+                                                     "assign", "d2")))
+        rc = _lib.kmpar_init(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d, k, float(ell),
+                             rounds, seed, centers.data_ptr(), ws.data_ptr(), ws.numel(),
+                             st.data_ptr(), ctypes.byref(trp) if trp is not None else None,
+                             _stream(stream))
+        self._check(rc, "kmpar_init")
+        if not check:
+            return InitResult(centers, {"_raw": st}, tr)
+        stats = parse_stats(st, rounds)
+        if stats["status"] == E_OVERFLOW:
+            raise KmparError(E_OVERFLOW, "a round exceeded the candidate capacity")
+        if tr is not None:
+            nc = stats["n_candidates"]
+            tr["cand_point"] = tr["cand_point"][:nc]
+            tr["cand_weight"] = tr["cand_weight"][:nc]
+            tr["center_cand"] = tr["center_cand"][:stats["n_centers"]]
+        return InitResult(centers[:stats["n_centers"]], stats, tr)
+
+    def cost(self, X, C, row_scale=None, stream=None) -> torch.Tensor:
+        dt = self._x(X, row_scale)
+        n, d = X.shape
+        C = C.contiguous().float()
+        ws = self._workspace(self.workspace_size(OP_COST, n, d, C.shape[0], dtype=dt), X.device)
+        phi = torch.empty(1, dtype=torch.float64, device=X.device)
+        self._check(_lib.kmpar_cost(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d,
+                                    C.data_ptr(), C.shape[0], phi.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), _stream(stream)), "kmpar_cost")
+        return phi
+
+    def assign(self, X, C, row_scale=None, stream=None):
+        dt = self._x(X, row_scale)
+        n, d = X.shape
+        C = C.contiguous().float()
+        ws = self._workspace(self.workspace_size(OP_ASSIGN, n, d, C.shape[0], dtype=dt), X.device)
+        a = torch.empty(n, dtype=torch.int32, device=X.device)
+        d2 = torch.empty(n, dtype=torch.float32, device=X.device)
+        self._check(_lib.kmpar_assign(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d,
+                                      C.data_ptr(), C.shape[0], a.data_ptr(), d2.data_ptr(),
+                                      ws.data_ptr(), ws.numel(), _stream(stream)), "kmpar_assign")
+        return a, d2
+
+    def lloyd_step(self, X, C, row_scale=None, want_assign=False, stream=None):
+        """Updates C (k x d FP32, contiguous) in place; returns (assign|None, phi)."""
+        dt = self._x(X, row_scale)
+        n, d = X.shape
+        if C.dtype != torch.float32 or not C.is_contiguous():
+            raise ValueError("C must be contiguous float32")
+        k = C.shape[0]
+        ws = self._workspace(self.workspace_size(OP_LLOYD, n, d, k, dtype=dt), X.device)
+        a = torch.empty(n, dtype=torch.int32, device=X.device) if want_assign else None
+        phi = torch.empty(1, dtype=torch.float64, device=X.device)
+        self._check(_lib.lloyd_step(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d,
+                                    C.data_ptr(), k, _ptr(a), phi.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), _stream(stream)), "lloyd_step")
+        return a, phi
+
+
+def parse_stats(st: torch.Tensor, rounds: int) -> dict:
+    raw = st.cpu().numpy().tobytes()
+    s = Stats.from_buffer_copy(raw)
+    return {"phi": [s.phi[i] for i in range(rounds + 1)],
+            "round_count": [s.round_count[i] for i in range(rounds + 1)],
+            "n_candidates": s.n_candidates, "n_centers": s.n_centers, "status": s.status,
+            "n_rescanned": s.n_rescanned}

@@ -1,0 +1,160 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Sizes span several point tiles with ragged tails; inputs are the seeded
+synthetic workloads.  Discrete decisions (draws, argmins, recluster picks)
+must be identical except where the oracle's margin lies inside the FP32
+error band, which the oracle's replay counts as flagged."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1203_6402_amd import synth
+from tests.gpu_util import (D2_RTOL, compare_init, decoded_fp64, gpu_init, to_bf16_bits,
+                            to_e4m3)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_1203_6402_amd import kmpar
+    assert torch.cuda.is_available()
+    return kmpar
+
+
+@pytest.fixture(scope="module")
+def ctx(K):
+    return K.Context(0, K.MODE_PLAIN_FP32)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def test_init_gaussmixture_c0(ctx):
+    # k=50 GaussMixture, n=10,000, d=15, R=10, ell=2k, r=5 (Section 4.1, Table 1).
+    X = synth.gauss_mixture(10000, 15, 50, 10.0, seed=0)
+    r, tr = gpu_init(ctx, _dev(X), 50, 100.0, 5, 0)
+    o = compare_init(X.astype(np.float64), r, tr, 50, 100.0, 5, 0)
+    assert r.stats["status"] == 0 and r.stats["n_centers"] == 50
+    assert o.flags["draw"] + o.flags["argmin"] + o.flags["pick"] <= 2
+
+
+@pytest.mark.parametrize("n,d,k,ell,rounds,kind", [
+    (1, 1, 1, 1.0, 0, "gauss"),
+    (257, 3, 5, 10.0, 3, "gauss"),
+    (3001, 42, 40, 80.0, 5, "heavy"),
+    (4099, 44, 25, 12.5, 5, "heavy"),
+    (2500, 128, 30, 60.0, 4, "sigma"),
+    (1500, 256, 20, 40.0, 3, "sigma"),
+    (777, 7, 6, 1e9, 1, "gauss"),        # every point kept in round 1: C = X
+])
+def test_init_shapes(ctx, n, d, k, ell, rounds, kind):
+    if kind == "gauss":
+        X = synth.gauss_mixture(n, d, max(1, k), 10.0, seed=n)
+    elif kind == "heavy":
+        X = synth.heavy_tailed(n, d, seed=n)
+    else:
+        X = synth.gauss_mixture_sigma(n, d, 50, seed=n)
+    r, tr = gpu_init(ctx, _dev(X), k, ell, rounds, seed=3)
+    if r.stats["status"] == 0:
+        compare_init(X.astype(np.float64), r, tr, k, ell, rounds, 3)
+    if ell >= 1e9:
+        assert r.stats["n_candidates"] == n
+        assert np.all(tr["cand_weight"] == 1)
+
+
+def test_init_bf16_and_fp8_inputs(ctx):
+    X = synth.gauss_mixture_sigma(3000, 64, 40, seed=5)
+    Xb = to_bf16_bits(X)
+    r, tr = gpu_init(ctx, _dev(Xb).view(torch.bfloat16), 30, 60.0, 4, 9)
+    compare_init(decoded_fp64(Xb, "bf16"), r, tr, 30, 60.0, 4, 9)
+    q, s = to_e4m3(X)
+    r, tr = gpu_init(ctx, _dev(q), 30, 60.0, 4, 9, row_scale=_dev(s))
+    compare_init(decoded_fp64(q, "fp8", s), r, tr, 30, 60.0, 4, 9)
+
+
+def test_init_degenerate_inputs(ctx, K):
+    # All points identical: psi = 0, nothing is ever sampled, |C| = 1.
+    X = np.ones((1000, 5), np.float32)
+    r, tr = gpu_init(ctx, _dev(X), 1, 10.0, 3, 0)
+    assert r.stats["status"] == 0 and r.stats["n_candidates"] == 1
+    assert r.stats["phi"] == [0.0] * 4 and tr["cand_weight"].tolist() == [1000]
+    r = ctx.init(_dev(X), k=3, ell=10.0, rounds=3, seed=0)
+    assert r.stats["status"] == K.E_TOOFEW and r.stats["n_centers"] == 1
+    # Duplicated points: a duplicate sampled in the same round gets weight 0
+    # (ties go to the lowest id) and is never picked by the recluster.
+    base = synth.gauss_mixture(300, 4, 5, 10.0, seed=1)
+    Xd = np.concatenate([base, base, base])
+    r, tr = gpu_init(ctx, _dev(Xd), 10, 1e9, 1, 2)
+    compare_init(Xd.astype(np.float64), r, tr, 10, 1e9, 1, 2)
+    assert (tr["cand_weight"] == 0).sum() == 600
+    # rounds = 0: only the first center.
+    r = ctx.init(_dev(base), k=1, ell=5.0, rounds=0, seed=4, trace=True)
+    assert r.stats["n_candidates"] == 1 and r.trace["center_cand"].tolist() == [0]
+
+
+def test_init_deterministic(ctx):
+    X = synth.heavy_tailed(20000, 42, seed=11)
+    a = ctx.init(_dev(X), k=50, ell=100.0, rounds=5, seed=1, trace=True)
+    b = ctx.init(_dev(X), k=50, ell=100.0, rounds=5, seed=1, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a.centers, b.centers)
+    for key in a.trace:
+        assert torch.equal(a.trace[key], b.trace[key]), key
+    assert a.stats == b.stats
+
+
+@pytest.mark.parametrize("n,d,m", [(1, 1, 1), (1000, 15, 50), (5003, 42, 333), (2049, 200, 17)])
+def test_assign_and_cost(ctx, n, d, m):
+    rng = np.random.default_rng(n + m)
+    X = (rng.normal(size=(n, d)) * rng.exponential(size=(1, d))).astype(np.float32)
+    C = (X[rng.integers(0, n, m)] + 0.3 * rng.normal(size=(m, d))).astype(np.float32)
+    a, d2 = ctx.assign(_dev(X), _dev(C))
+    phi = ctx.cost(_dev(X), _dev(C))
+    torch.cuda.synchronize()
+    a, d2 = a.cpu().numpy(), d2.cpu().numpy()
+    oa, od2, osnd = O.nearest(X.astype(np.float64), C.astype(np.float64))
+    np.testing.assert_allclose(d2, od2, rtol=D2_RTOL)
+    diff = a != oa
+    gap = (osnd - od2) / np.maximum(od2, 1e-300)
+    assert np.all(gap[diff] <= O.fp32_band(d)), "argmin differs outside the band"
+    assert phi.item() == pytest.approx(O.total(od2), rel=D2_RTOL)
+
+
+def test_lloyd_steps(ctx):
+    X = synth.gauss_mixture(20000, 15, 50, 10.0, seed=2)
+    X64 = X.astype(np.float64)
+    rng = np.random.default_rng(0)
+    C = torch.from_numpy(X[rng.choice(20000, 50, replace=False)].copy()).to("cuda:0")
+    for it in range(6):
+        Cin = C.cpu().numpy().astype(np.float64)
+        a, phi = ctx.lloyd_step(_dev(X), C, want_assign=True)
+        torch.cuda.synchronize()
+        oa, od2, osnd = O.nearest(X64, Cin)
+        a = a.cpu().numpy()
+        diff = a != oa
+        gap = (osnd - od2) / np.maximum(od2, 1e-300)
+        assert np.all(gap[diff] <= O.fp32_band(15))
+        assert phi.item() == pytest.approx(O.total(od2), rel=D2_RTOL)
+        Co, cnt = O.lloyd_update(X64, a, Cin)      # follow the GPU's assignment
+        np.testing.assert_allclose(C.cpu().numpy(), Co.astype(np.float32), rtol=1e-6, atol=1e-6)
+
+
+def test_lloyd_empty_cluster_and_bf16(ctx):
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [10.0, 0.0], [11.0, 0.0]], np.float32)
+    C = torch.tensor([[0.5, 0.0], [10.5, 0.0], [100.0, 100.0]], device="cuda:0")
+    a, phi = ctx.lloyd_step(_dev(X), C, want_assign=True)
+    torch.cuda.synchronize()
+    assert a.cpu().tolist() == [0, 0, 1, 1]
+    assert C.cpu().tolist() == [[0.5, 0.0], [10.5, 0.0], [100.0, 100.0]]
+    Xs = synth.gauss_mixture_sigma(7000, 64, 30, seed=4)
+    Xb = to_bf16_bits(Xs)
+    X64 = decoded_fp64(Xb, "bf16")
+    C0 = X64[:30].astype(np.float32)
+    C = torch.from_numpy(C0.copy()).to("cuda:0")
+    a, phi = ctx.lloyd_step(_dev(Xb).view(torch.bfloat16), C, want_assign=True)
+    torch.cuda.synchronize()
+    Co, _ = O.lloyd_update(X64, a.cpu().numpy(), C0.astype(np.float64))
+    np.testing.assert_allclose(C.cpu().numpy(), Co.astype(np.float32), rtol=1e-6, atol=1e-6)
