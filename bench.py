@@ -25,6 +25,7 @@ METRIC = "k-means|| init pt·ctr evals/s + %roofline; BF16-refined vs FP32 at Δ
 UNIT = "pt·ctr evals/s"
 # MI355X published peaks.
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
@@ -104,23 +105,35 @@ def main():
     value = evals / (ms / 1e3)
     log(f"{ms:.3f} ms/step, |C|={ncand}, {value:.3e} evals/s")
 
-    # Dominant kernel: the distance fold, timed live with HIP events on the
-    # stream it runs on, over one further step.
+    # Dominant kernel: the distance pass (direct-form fold in PLAIN mode, the
+    # MFMA screen in REFINED mode), timed live with HIP events on the stream
+    # it runs on, over one further step.
     ctx.profile(True)
-    ctx.init(Xd, k=k, ell=ell, rounds=rounds, seed=args.seed, check=False)
+    rp = ctx.init(Xd, k=k, ell=ell, rounds=rounds, seed=args.seed)
     torch.cuda.synchronize()
-    prof = ctx.profile_read(kmpar.SLOT_FOLD_DIRECT)
+    slots = {name: ctx.profile_read(slot) for name, slot in
+             (("k_fold_direct", kmpar.SLOT_FOLD_DIRECT), ("k_screen", kmpar.SLOT_SCREEN),
+              ("k_fold_direct(rescan)", kmpar.SLOT_RESCAN))}
     ctx.profile(False)
+    for name, p in slots.items():
+        if p["launches"]:
+            log(f"{name}: {p['launches']} launches, {p['ms']:.3f} ms, {p['pairs']:.3e} pairs")
+    dom = max(slots, key=lambda nm: slots[nm]["ms"])
+    prof = slots[dom]
     flops_per_launch = 2.0 * d * prof["pairs"] / prof["launches"]
     dur_per_launch = prof["ms"] / prof["launches"] / 1e3
     achieved = flops_per_launch / dur_per_launch / 1e12
-    roofline = {"bound": "alu", "kernel": "k_fold_direct", "achieved": achieved,
-                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+    if dom == "k_screen":
+        bound, peak = "mfma", PEAK_BF16_MFMA_TFLOPS
+    else:
+        bound, peak = "alu", PEAK_FP32_VECTOR_TFLOPS
+    roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                 "launches": prof["launches"], "avg_launch_us": dur_per_launch * 1e6,
-                "flops_per_launch": flops_per_launch}
-    log(f"fold: {prof['launches']} launches, avg {dur_per_launch*1e6:.1f} us, "
-        f"{achieved:.2f} TFLOP/s algorithmic")
+                "flops_per_launch": flops_per_launch,
+                "distance_kernels_ms": {nm: p["ms"] for nm, p in slots.items() if p["launches"]}}
+    log(f"dominant {dom}: avg {dur_per_launch*1e6:.1f} us, {achieved:.2f} TFLOP/s algorithmic "
+        f"({100*achieved/peak:.1f}% of {peak})")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -134,6 +147,7 @@ def main():
            "config": {"workload": "KDDCup1999-shaped heavy-tailed mixture (synthetic)",
                       "n": n, "d": d, "k": k, "ell": ell, "rounds": rounds,
                       "mode": args.mode, "n_candidates": ncand, "evals_per_step": evals,
+                      "rescanned_points": rp.stats["n_rescanned"],
                       "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)

@@ -26,6 +26,7 @@ struct ProfRec {
 
 struct kmpar_ctx {
   int device = -1;
+  int num_cu = 1;
   kmpar_mode mode = KMPAR_MODE_PLAIN_FP32;
   std::string err;
   bool prof = false;
@@ -39,6 +40,9 @@ using namespace kmpar;
 
 constexpr int kMaxD = 256;
 constexpr int kMaxK = 16384;
+// Below these candidate counts the direct form is at least as fast.
+constexpr double kScreenMinEll = 32.0;
+constexpr int kScreenMinM = 32;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -85,15 +89,33 @@ struct InitLayout {
   int* scan_total;
   int* cand_point;
   float* Call;
-  float* CallT;
   int* w;
-  float* E;
+  double* rpart;
+  float* prow;
+  unsigned* bar;
   int* picks;
   kmpar_stats* st;
+  float* norms;
+  int* list;
+  int* list_len;
+  void* B;
+  float* ncg;
+  void* Apre;
   size_t bytes;
 };
 
-InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds) {
+// Screen operand buffers for up to `tiles` tiles of 16 candidates.
+size_t screen_b_bytes(int tiles, int d) { return (size_t)tiles * 8 * 64 * 16 + 0 * d; }
+
+// Bytes of prepared A operands for the screen of this dtype (0 if unused).
+size_t a_bytes(kmpar_dtype dt, bool rows, int64_t n, int d) {
+  if (!screen_supported(dt, rows, d)) return 0;
+  const int sp = screen_split(dt, rows);
+  if (screen_a_direct(dt, sp, d)) return 0;
+  return screen_a_bytes((int)n, screen_ksteps(sp, d));
+}
+
+InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds, kmpar_dtype dt) {
   const int DP = padded_dim(d);
   const int64_t capT = 1 + (int64_t)rounds * cap_round_of(n, ell);
   Carver c(ws);
@@ -106,11 +128,19 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.scan_total = c.take<int>(4);
   L.cand_point = c.take<int>(capT);
   L.Call = c.take<float>(capT * DP);
-  L.CallT = c.take<float>(capT * DP);
   L.w = c.take<int>(capT);
-  L.E = c.take<float>(capT);
+  L.rpart = c.take<double>(2 * kReclMaxBlocks);
+  L.prow = c.take<float>(2 * (size_t)DP);
+  L.bar = c.take<unsigned>(4);
   L.picks = c.take<int>(k);
   L.st = c.take<kmpar_stats>(1);
+  const int tiles = (int)((cap_round_of(n, ell) + 15) / 16);
+  L.norms = c.take<float>(n);
+  L.list = c.take<int>(n);
+  L.list_len = c.take<int>(4);
+  L.B = c.take<char>(screen_b_bytes(tiles, d));
+  L.ncg = c.take<float>((size_t)tiles * 16);
+  L.Apre = c.take<char>(a_bytes(dt, true, n, d));
   L.bytes = c.off;
   return L;
 }
@@ -122,10 +152,16 @@ struct AssignLayout {
   double* phi_tmp;
   float* Cpad;
   LloydWs lw;
+  float* norms;
+  int* list;
+  int* list_len;
+  void* B;
+  float* ncg;
+  void* Apre;
   size_t bytes;
 };
 
-AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op) {
+AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op, kmpar_dtype dt) {
   const int DP = padded_dim(d);
   Carver c(ws);
   AssignLayout L{};
@@ -144,6 +180,13 @@ AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op) {
     L.lw.coff = c.take<int>(k + 1);
     L.lw.part = c.take<double>(((n + kSegChunk - 1) / kSegChunk + k) * (int64_t)d);
   }
+  const int tiles = (k + 15) / 16;
+  L.norms = c.take<float>(n);
+  L.list = c.take<int>(n);
+  L.list_len = c.take<int>(4);
+  L.B = c.take<char>(screen_b_bytes(tiles, d));
+  L.ncg = c.take<float>((size_t)tiles * 16);
+  L.Apre = c.take<char>(a_bytes(dt, false, n, d));
   L.bytes = c.off;
   return L;
 }
@@ -204,24 +247,77 @@ hipError_t prof_event(kmpar_ctx* ctx, hipEvent_t* e) {
   return hipEventCreate(e);
 }
 
-// Launches a distance pass, bracketed by events when profiling is on.
-hipError_t timed_fold(kmpar_ctx* ctx, int slot, kmpar_dtype dt, int DP, const FoldArgs& fa,
-                      hipStream_t s) {
-  if (!ctx->prof) return launch_fold_direct(dt, DP, fa, s);
+// Runs `launch`, bracketed by events when profiling is on.
+template <typename F>
+hipError_t timed(kmpar_ctx* ctx, int slot, int64_t npts, const int* npts_dev, const int* rs_dev,
+                 int m_host, hipStream_t s, F&& launch) {
+  if (!ctx->prof) return launch();
   ProfRec r{};
   r.slot = slot;
   hipError_t e;
   if ((e = prof_event(ctx, &r.a)) != hipSuccess) return e;
   if ((e = prof_event(ctx, &r.b)) != hipSuccess) return e;
   if ((e = hipEventRecord(r.a, s)) != hipSuccess) return e;
-  if ((e = launch_fold_direct(dt, DP, fa, s)) != hipSuccess) return e;
+  if ((e = launch()) != hipSuccess) return e;
   if ((e = hipEventRecord(r.b, s)) != hipSuccess) return e;
-  r.npts = fa.list ? 0 : fa.n;
-  r.npts_dev = fa.list ? fa.list_len : nullptr;
-  r.rs_dev = fa.rs;
-  r.m_host = fa.m_host;
+  r.npts = npts;
+  r.npts_dev = npts_dev;
+  r.rs_dev = rs_dev;
+  r.m_host = m_host;
   ctx->recs.push_back(r);
   return hipSuccess;
+}
+
+// Slots of kmpar_profile_read.
+enum { kSlotDirect = 0, kSlotScreen = 1, kSlotRescan = 2 };
+
+hipError_t timed_fold(kmpar_ctx* ctx, int slot, kmpar_dtype dt, int DP, const FoldArgs& fa,
+                      hipStream_t s) {
+  return timed(ctx, slot, fa.list ? 0 : fa.n, fa.list ? fa.list_len : nullptr, fa.rs, fa.m_host, s,
+               [&] { return launch_fold_direct(dt, DP, fa, s); });
+}
+
+// One REFINED distance pass: B operands, screen, direct-form rescan of the
+// points the screen listed.  `fa` describes the same pass for the direct form.
+hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const FoldArgs& fa,
+                        int max_tiles, const float* norms, const void* Apre, void* B, float* ncg,
+                        int* list, int* list_len, kmpar_stats* st, hipStream_t s) {
+  const int KS = screen_ksteps(split, fa.d);
+  const float om2g = 1.0f - 2.0f * screen_g(split, fa.d);
+  hipError_t e = launch_prep_b(split, KS, fa.C, DP, fa.d, fa.rs, fa.m_host, max_tiles, om2g, B,
+                               ncg, s);
+  if (e != hipSuccess) return e;
+  ScreenArgs sa{};
+  sa.X = fa.X;
+  sa.row_scale = fa.row_scale;
+  sa.n = fa.n;
+  sa.d = fa.d;
+  sa.DP = DP;
+  sa.C = fa.C;
+  sa.rs = fa.rs;
+  sa.m_host = fa.m_host;
+  sa.id0_host = fa.id0_host;
+  sa.Apre = Apre;
+  sa.B = B;
+  sa.ncg = ncg;
+  sa.norms = norms;
+  sa.oneminus2g = om2g;
+  sa.D2 = fa.D2;
+  sa.A = fa.A;
+  sa.first = fa.first;
+  sa.list = list;
+  sa.list_len = list_len;
+  sa.stats = st;
+  e = timed(ctx, kSlotScreen, fa.n, nullptr, fa.rs, fa.m_host, s,
+            [&] { return launch_screen(dt, split, KS, sa, s); });
+  if (e != hipSuccess) return e;
+  FoldArgs rf = fa;
+  rf.list = list;
+  rf.list_len = list_len;
+  rf.list_cap = fa.n;
+  rf.norms = nullptr;
+  return timed(ctx, kSlotRescan, 0, list_len, fa.rs, fa.m_host, s,
+               [&] { return launch_rescan(dt, DP, rf, s); });
 }
 
 int device_ready(kmpar_ctx* ctx) {
@@ -242,7 +338,12 @@ int kmpar_create(int hip_device, kmpar_mode mode, kmpar_ctx** out) {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || hip_device >= count) return KMPAR_E_HIP;
   }
+  int cu = 1;
+  if (hip_device >= 0 &&
+      hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess)
+    return KMPAR_E_HIP;
   kmpar_ctx* c = new kmpar_ctx;
+  c->num_cu = cu;
   c->device = hip_device;
   c->mode = mode;
   *out = c;
@@ -344,13 +445,13 @@ int kmpar_workspace_size(const kmpar_ctx* cctx, kmpar_op op, int64_t n, int32_t 
         return set_err(ctx, KMPAR_E_INVAL, "k, ell or rounds out of range");
       const int64_t capT = 1 + (int64_t)rounds * cap_round_of(n, ell);
       if (capT >= (int64_t)1 << 31) return set_err(ctx, KMPAR_E_INVAL, "candidate capacity too large");
-      *bytes_out = init_layout(nullptr, n, d, k, ell, rounds).bytes;
+      *bytes_out = init_layout(nullptr, n, d, k, ell, rounds, dtype).bytes;
       return KMPAR_OK;
     }
     case KMPAR_OP_COST:
     case KMPAR_OP_ASSIGN:
     case KMPAR_OP_LLOYD:
-      *bytes_out = assign_layout(nullptr, n, d, k, op).bytes;
+      *bytes_out = assign_layout(nullptr, n, d, k, op, dtype).bytes;
       return KMPAR_OK;
   }
   return set_err(ctx, KMPAR_E_INVAL, "unknown op");
@@ -383,14 +484,13 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   const int N = (int)n, DP = padded_dim(d);
   const int cap_round = (int)cap_round_of(n, ell);
   const int capT = 1 + rounds * cap_round;
-  InitLayout L = init_layout(ws, n, d, k, ell, rounds);
+  InitLayout L = init_layout(ws, n, d, k, ell, rounds, dtype);
   kmpar_stats* st = stats ? stats : L.st;
   const uint64_t inst = 0;
 
   // Steps 1-2: first center, D2 against it, psi.
   KMPAR_HIP(launch_first(N, seed, inst, L.cand_point, L.rs, st, s));
-  KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, 0, 1, L.Call, L.CallT,
-                          capT, s));
+  KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, 0, 1, L.Call, s));
   FoldArgs fa{};
   fa.X = X;
   fa.row_scale = row_scale;
@@ -401,26 +501,48 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   fa.A = L.A;
   fa.rs = L.rs;
   fa.first = 1;
-  KMPAR_HIP(timed_fold(ctx, 0, dtype, DP, fa, s));
+  // The REFINED screen runs on the rounds (m_t ~ ell candidates); the first
+  // pass has m = 1 and stays in direct form, where it also writes ||x||^2.
+  const int split = screen_split(dtype, true);
+  const bool refined = ctx->mode == KMPAR_MODE_REFINED && screen_supported(dtype, true, d) &&
+                       ell >= kScreenMinEll;
+  fa.norms = refined ? L.norms : nullptr;
+  KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
+  fa.norms = nullptr;
   KMPAR_HIP(launch_phi(L.D2, N, L.phi_part, &st->phi[0], s));
+  const void* Apre = nullptr;
+  if (refined) {
+    KMPAR_HIP(launch_fill_i32(L.list_len, 0, 1, s));
+    if (!screen_a_direct(dtype, split, d)) {
+      KMPAR_HIP(launch_prep_a(dtype, split, screen_ksteps(split, d), X, row_scale, N, d, L.Apre, s));
+      Apre = L.Apre;
+    }
+  }
   // Steps 3-6: rounds.
   fa.first = 0;
   for (int t = 1; t <= rounds; ++t) {
     KMPAR_HIP(launch_draw(L.D2, N, &st->phi[t - 1], ell, seed, t, inst, L.cnt, L.scan_total, L.rs,
                           cap_round, L.cand_point, st, s));
     KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, t, cap_round, L.Call,
-                            L.CallT, capT, s));
+                            s));
     fa.rs = L.rs + t;
-    KMPAR_HIP(timed_fold(ctx, 0, dtype, DP, fa, s));
+    if (refined) {
+      KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (cap_round + 15) / 16, L.norms, Apre, L.B,
+                             L.ncg, L.list, L.list_len, st, s));
+    } else {
+      KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
+    }
     KMPAR_HIP(launch_phi(L.D2, N, L.phi_part, &st->phi[t], s));
   }
+  if (refined) KMPAR_HIP(launch_list_reset(L.list_len, st, s));
   KMPAR_HIP(launch_finish_rounds(L.rs, rounds, st, s));
   // Step 7: weights.
   KMPAR_HIP(launch_hist(L.A, N, L.w, capT, s));
   // Step 8: weighted k-means++.
   int* picks = (trace && trace->center_cand) ? trace->center_cand : L.picks;
-  KMPAR_HIP(launch_recluster(L.CallT, capT, d, L.w, L.rs + rounds + 1, k, seed, inst, L.E, picks,
-                             centers, st, s));
+  const int G = recluster_blocks(capT, DP, ctx->num_cu);
+  KMPAR_HIP(launch_recluster(L.Call, DP, capT, d, L.w, L.rs + rounds + 1, k, seed, inst, G, L.rpart,
+                             L.prow, L.bar, picks, centers, st, s));
   if (trace) {
     if (trace->cand_point) KMPAR_HIP(launch_copy_i32(L.cand_point, trace->cand_point, capT, s));
     if (trace->cand_weight) KMPAR_HIP(launch_copy_i32(L.w, trace->cand_weight, capT, s));
@@ -444,7 +566,7 @@ static int assign_common(kmpar_ctx* ctx, kmpar_op op, const void* X, const float
   if (ws_bytes < need)
     return set_err(ctx, KMPAR_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   if ((rc = device_ready(ctx))) return rc;
-  *L = assign_layout(ws, n, d, m, op);
+  *L = assign_layout(ws, n, d, m, op, dtype);
   *fa = FoldArgs{};
   fa->X = X;
   fa->row_scale = row_scale;
@@ -457,6 +579,28 @@ static int assign_common(kmpar_ctx* ctx, kmpar_op op, const void* X, const float
   fa->D2 = L->D2;
   fa->A = L->A;
   fa->first = 1;
+  return KMPAR_OK;
+}
+
+// Assignment pass against m FP32 centers (first = 1), REFINED when possible.
+static int assign_pass(kmpar_ctx* ctx, kmpar_dtype dtype, const AssignLayout& L, const FoldArgs& fa,
+                       int m, hipStream_t s) {
+  const int d = fa.d, DP = padded_dim(d);
+  if (ctx->mode == KMPAR_MODE_REFINED && screen_supported(dtype, false, d) && m >= kScreenMinM) {
+    const int split = screen_split(dtype, false);
+    KMPAR_HIP(launch_rownorm(dtype, fa.X, fa.row_scale, fa.n, d, L.norms, s));
+    KMPAR_HIP(launch_fill_i32(L.list_len, 0, 1, s));
+    const void* Apre = nullptr;
+    if (!screen_a_direct(dtype, split, d)) {
+      KMPAR_HIP(launch_prep_a(dtype, split, screen_ksteps(split, d), fa.X, fa.row_scale, fa.n, d,
+                              L.Apre, s));
+      Apre = L.Apre;
+    }
+    KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (m + 15) / 16, L.norms, Apre, L.B, L.ncg,
+                           L.list, L.list_len, nullptr, s));
+  } else {
+    KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
+  }
   return KMPAR_OK;
 }
 
@@ -473,7 +617,7 @@ int kmpar_cost(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   KMPAR_HIP(launch_pad_rows(C, m, d, padded_dim(d), L.Cpad, s));
-  KMPAR_HIP(timed_fold(ctx, 0, dtype, padded_dim(d), fa, s));
+  if ((rc = assign_pass(ctx, dtype, L, fa, m, s))) return rc;
   KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi, s));
   return KMPAR_OK;
 }
@@ -494,7 +638,7 @@ int kmpar_assign(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dt
   if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   KMPAR_HIP(launch_pad_rows(C, m, d, padded_dim(d), L.Cpad, s));
-  KMPAR_HIP(timed_fold(ctx, 0, dtype, padded_dim(d), fa, s));
+  if ((rc = assign_pass(ctx, dtype, L, fa, m, s))) return rc;
   return KMPAR_OK;
 }
 
@@ -514,7 +658,7 @@ int lloyd_step(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   KMPAR_HIP(launch_pad_rows(C, k, d, padded_dim(d), L.Cpad, s));
-  KMPAR_HIP(timed_fold(ctx, 0, dtype, padded_dim(d), fa, s));
+  if ((rc = assign_pass(ctx, dtype, L, fa, k, s))) return rc;
   if (phi) KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi, s));
   KMPAR_HIP(launch_lloyd_update(dtype, X, row_scale, (int)n, d, fa.A, k, C, L.lw, s));
   return KMPAR_OK;

@@ -33,12 +33,11 @@ hipError_t launch_first(int n, uint64_t seed, uint64_t inst, int* cand_point, in
 }
 
 // --------------------------------------------------------------------- gather
-// Copies the m_t rows kept in round t into the candidate buffers: row-major
-// Call[id][DP] (read by the fold) and dim-major CallT[e][capT] (read by the
-// recluster).  Pads with zeros beyond d.
+// Copies the m_t rows kept in round t into the row-major candidate buffer
+// Call[id][DP] (read by the folds and the recluster), zero-padded past d.
 template <typename T>
 __global__ void k_gather(const T* X, const float* row_scale, int d, int DP, const int* cand_point,
-                         const int* rs, int t, float* Call, float* CallT, int capT) {
+                         const int* rs, int t, float* Call) {
   const int id0 = rs[t];
   const int m = rs[t + 1] - id0;
   const int j = blockIdx.x;
@@ -49,26 +48,25 @@ __global__ void k_gather(const T* X, const float* row_scale, int d, int DP, cons
   for (int e = threadIdx.x; e < DP; e += blockDim.x) {
     const float v = (e < d) ? Elem<T>::get(X, (int64_t)p * d + e, sc) : 0.0f;
     Call[(int64_t)c * DP + e] = v;
-    CallT[(int64_t)e * capT + c] = v;
   }
 }
 
 hipError_t launch_gather(kmpar_dtype dt, const void* X, const float* row_scale, int d, int DP,
                          const int* cand_point, const int* rs, int t, int cap_round, float* Call,
-                         float* CallT, int capT, hipStream_t s) {
+                         hipStream_t s) {
   const dim3 grid(cap_round), block(64);
   switch (dt) {
     case KMPAR_F32:
       hipLaunchKernelGGL(k_gather<float>, grid, block, 0, s, (const float*)X, row_scale, d, DP,
-                         cand_point, rs, t, Call, CallT, capT);
+                         cand_point, rs, t, Call);
       break;
     case KMPAR_BF16:
       hipLaunchKernelGGL(k_gather<bf16_t>, grid, block, 0, s, (const bf16_t*)X, row_scale, d, DP,
-                         cand_point, rs, t, Call, CallT, capT);
+                         cand_point, rs, t, Call);
       break;
     case KMPAR_FP8_E4M3:
       hipLaunchKernelGGL(k_gather<fp8_t>, grid, block, 0, s, (const fp8_t*)X, row_scale, d, DP,
-                         cand_point, rs, t, Call, CallT, capT);
+                         cand_point, rs, t, Call);
       break;
   }
   KMPAR_RET_LAST();
@@ -277,127 +275,273 @@ hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s) {
 }
 
 // ---------------------------------------------------------- Step 8 recluster
-// Weighted k-means++ (Algorithm 1 with weights) on the candidates, one block.
-// Pick 0 has probability w_j / sum w (integer prefix, exact); pick s >= 1 has
-// probability w_j E_j / T with E_j the FP32 direct-form distance to the
-// nearest earlier pick and T accumulated in FP64.  Pick s takes the smallest
-// j whose running sum exceeds u*T, u = U(seed, RECL, (s, 0, inst)).  Each
-// thread owns a contiguous run of candidates for the running sums.
-constexpr int kReclBlock = 1024;
+// Weighted k-means++ (Algorithm 1 with weights) on the candidates, spread
+// over G workgroups.  Block b holds candidates [b*m/G, (b+1)*m/G) -- rows,
+// E and w -- in LDS.  Pick 0 has probability w_j / sum w (integer sums, exact
+// in FP64); pick s >= 1 has probability w_j E_j / T with E_j the FP32
+// direct-form distance to the nearest earlier pick and every sum in FP64.
+// Pick s takes the smallest j whose running sum (block order, then thread
+// runs, then candidate order) exceeds u*T, u = U(seed, RECL, (s, 0, inst)).
+//
+// Per pick: each block folds the previous pick into its E and publishes its
+// FP64 partial; grid barrier; every block derives the same block bounds from
+// the partials in block order; the block holding u*T finds the pick and
+// publishes it; grid barrier.  Barriers are agent-scope release/acquire
+// counters; a spin limit guarantees every wave exits (status KMPAR_E_HIP).
+constexpr int kReclBlock = 256;
+constexpr unsigned kSpinLimit = 1u << 22;
+constexpr size_t kReclLdsBudget = 120 * 1024;
 
-template <bool E_LDS>
-__global__ __launch_bounds__(kReclBlock) void k_recluster(const float* CallT, int capT, int d,
-                                                          const int* w, const int* rs_end, int k,
-                                                          uint64_t seed, uint64_t inst,
-                                                          float* E_glob, int* picks,
-                                                          float* centers, kmpar_stats* st) {
-  extern __shared__ float E_sh[];
-  __shared__ double bounds[kReclBlock + 1];
-  __shared__ double shd[kReclBlock / kWave + 1];
-  __shared__ long long shl[kReclBlock / kWave + 1];
-  __shared__ float cp[256];
-  __shared__ int pick_sh;
-  float* E = E_LDS ? E_sh : E_glob;
-  const int m = *rs_end;
-  const int tid = threadIdx.x;
-  const int R = (m + kReclBlock - 1) / kReclBlock;
-  const int lo = min(m, tid * R), hi = min(m, lo + R);
-
-  int made = 0;
-  for (int s = 0; s < k; ++s) {
-    const double u = philox_uniform(seed, kTagRecluster, (uint64_t)s, 0, inst);
-    if (tid == 0) pick_sh = 0x7fffffff;
-    double T;
-    if (s == 0) {
-      long long loc = 0;
-      for (int j = lo; j < hi; ++j) loc += w[j];
-      long long tot;
-      const long long ex = block_excl_scan<long long, kReclBlock>(loc, shl, &tot);
-      bounds[tid] = (double)ex;
-      if (tid == 0) bounds[kReclBlock] = (double)tot;
-      T = (double)tot;
-    } else {
-      double loc = 0.0;
-      for (int j = lo; j < hi; ++j) loc += (double)w[j] * (double)E[j];
-      double tot;
-      const double ex = block_excl_scan<double, kReclBlock>(loc, shd, &tot);
-      bounds[tid] = ex;
-      if (tid == 0) bounds[kReclBlock] = tot;
-      T = tot;
-    }
-    __syncthreads();
-    if (!(T > 0.0)) break;
-    const double thr = u * T;
-    const double b0 = bounds[tid], b1 = bounds[tid + 1];
-    if (b0 <= thr && thr < b1) {
-      double run = b0;
-      int pick = -1, last = -1;
-      for (int j = lo; j < hi; ++j) {
-        const double v = (s == 0) ? (double)w[j] : (double)w[j] * (double)E[j];
-        run += v;
-        if (v > 0.0) last = j;
-        if (v > 0.0 && run > thr) {
-          pick = j;
-          break;
-        }
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int* failed) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        *failed = 1;
+        break;
       }
-      // Bounds of neighbouring threads come from different FP64 association
-      // orders; should two runs claim thr, the lower candidate id wins.
-      atomicMin(&pick_sh, pick >= 0 ? pick : (last >= 0 ? last : 0x7fffffff));
     }
-    __syncthreads();
-    if (pick_sh == 0x7fffffff) {
-      // thr fell at or beyond the total by rounding: take the last candidate
-      // with positive mass (thread runs are ordered, so scan from the end).
-      if (tid == 0) {
-        pick_sh = -1;
-        for (int j = m - 1; j >= 0; --j) {
-          const double v = (s == 0) ? (double)w[j] : (double)w[j] * (double)E[j];
-          if (v > 0.0) {
-            pick_sh = j;
-            break;
-          }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void store_f64(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_f64(const double* p) {
+  return __longlong_as_double((long long)__hip_atomic_load(
+      reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+struct ReclArgs {
+  const float* Call;   // candidate rows, DP-padded
+  int DP;
+  int d;
+  const int* w;
+  const int* rs_end;   // device: number of candidates m
+  int k;
+  uint64_t seed;
+  uint64_t inst;
+  int slice_cap;       // LDS slice capacity (candidates per block)
+  double* part;        // [2][G] block partials
+  float* prow;         // [2][DP] row of the latest pick, published through memory
+  unsigned* bar;       // barrier counter, zero on entry
+  int* picks;          // [k] output: candidate ids
+  float* centers;      // [k][d] output rows
+  kmpar_stats* st;
+};
+
+__global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
+  extern __shared__ float lds[];
+  __shared__ double shd[kReclBlock / kWave + 1];
+  __shared__ double runb[kReclBlock + 1];
+  __shared__ double blockb[2];
+  __shared__ double gpart[kReclMaxBlocks];
+  __shared__ double sh_T;
+  __shared__ int sh_pick, sh_owner, sh_failed, sh_stop;
+  const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x, DP = a.DP, d = a.d;
+  const int m = *a.rs_end;
+  const int lo = (int)((int64_t)b * m / G), hi = (int)((int64_t)(b + 1) * m / G);
+  const int ns = hi - lo;
+  float* rows = lds;                                   // [slice_cap][DP]
+  float* E = rows + (size_t)a.slice_cap * DP;          // [slice_cap]
+  int* wl = reinterpret_cast<int*>(E + a.slice_cap);   // [slice_cap]
+  float* cp = reinterpret_cast<float*>(wl + a.slice_cap);  // [DP]
+  if (tid == 0) {
+    sh_failed = 0;
+    sh_stop = 0;
+  }
+  for (int idx = tid; idx < ns * DP; idx += kReclBlock) rows[idx] = a.Call[(int64_t)lo * DP + idx];
+  for (int j = tid; j < ns; j += kReclBlock) wl[j] = a.w[lo + j];
+  __syncthreads();
+  // contiguous thread runs inside the slice, for the running sums
+  const int R = (ns + kReclBlock - 1) / kReclBlock;
+  const int rlo = min(ns, tid * R), rhi = min(ns, rlo + R);
+  unsigned nbar = 0;
+  int made = 0;
+  for (int s = 0; s < a.k; ++s) {
+    if (s > 0) {
+      for (int e = tid; e < DP; e += kReclBlock)
+        cp[e] = __uint_as_float(__hip_atomic_load(
+            reinterpret_cast<const unsigned*>(&a.prow[((s - 1) & 1) * DP + e]), __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT));
+      __syncthreads();
+      for (int j = tid; j < ns; j += kReclBlock) {
+        const float* r = rows + (size_t)j * DP;
+        float acc = 0.0f;
+        for (int e = 0; e < d; ++e) {
+          const float t = r[e] - cp[e];
+          acc = fmaf(t, t, acc);
         }
+        E[j] = (s == 1) ? acc : fminf(E[j], acc);
       }
       __syncthreads();
     }
-    const int pick = pick_sh;
-    if (pick < 0) break;
-    for (int e = tid; e < d; e += kReclBlock) {
-      const float v = CallT[(int64_t)e * capT + pick];
-      cp[e] = v;
-      centers[(int64_t)s * d + e] = v;
+    double loc = 0.0;
+    for (int j = rlo; j < rhi; ++j) loc += (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+    double tot;
+    const double ex = block_excl_scan<double, kReclBlock>(loc, shd, &tot);
+    runb[tid] = ex;
+    if (tid == 0) {
+      runb[kReclBlock] = tot;
+      store_f64(&a.part[(s & 1) * G + b], tot);
     }
-    if (tid == 0) picks[s] = pick;
+    grid_barrier(a.bar, (++nbar) * (unsigned)G, &sh_failed);
+    // every block: block bounds from the partials in block order (loaded in
+    // parallel, summed in order by one thread)
+    for (int q = tid; q < G; q += kReclBlock) gpart[q] = load_f64(&a.part[(s & 1) * G + q]);
     __syncthreads();
-    for (int j = tid; j < m; j += kReclBlock) {
-      float acc = 0.0f;
-      for (int e = 0; e < d; ++e) {
-        const float t = CallT[(int64_t)e * capT + j] - cp[e];
-        acc = fmaf(t, t, acc);
+    if (tid == 0) {
+      double run = 0.0, lo_b = 0.0, hi_b = 0.0;
+      int owner = -1, last_pos = -1;
+      double T = 0.0;
+      for (int q = 0; q < G; ++q) T += gpart[q];
+      sh_T = T;
+      const double u = philox_uniform(a.seed, kTagRecluster, (uint64_t)s, 0, a.inst);
+      const double thr = u * T;
+      for (int q = 0; q < G; ++q) {
+        const double v = gpart[q];
+        const double nxt = (q + 1 < G) ? run + v : T;
+        if (v > 0.0) last_pos = q;
+        if (owner < 0 && run <= thr && thr < nxt && v > 0.0) {
+          owner = q;
+          lo_b = run;
+          hi_b = nxt;
+        }
+        run += v;
       }
-      E[j] = (s == 0) ? acc : fminf(E[j], acc);
+      if (!(T > 0.0) || sh_failed) {
+        sh_stop = 1;
+      } else if (owner < 0) {  // thr at or past the total by rounding
+        owner = last_pos;
+        lo_b = hi_b = INFINITY;
+      }
+      sh_owner = owner;
+      blockb[0] = lo_b;
+      blockb[1] = hi_b;
+      sh_pick = 0x7fffffff;
     }
     __syncthreads();
+    if (sh_stop) break;
+    if (sh_owner == b) {
+      const double u = philox_uniform(a.seed, kTagRecluster, (uint64_t)s, 0, a.inst);
+      const double thr = u * sh_T;
+      const double base = blockb[0];
+      const double b0 = base + runb[tid];
+      const double b1 = (tid + 1 < kReclBlock) ? base + runb[tid + 1] : blockb[1];
+      if (isinf(base)) {
+        // rounding fallback: the last candidate with positive mass
+        if (tid == 0) {
+          for (int j = ns - 1; j >= 0; --j) {
+            const double v = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+            if (v > 0.0) {
+              sh_pick = j;
+              break;
+            }
+          }
+        }
+      } else if (b0 <= thr && thr < b1) {
+        double run = b0;
+        int pick = -1, last = -1;
+        for (int j = rlo; j < rhi; ++j) {
+          const double v = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+          run += v;
+          if (v > 0.0) last = j;
+          if (v > 0.0 && run > thr) {
+            pick = j;
+            break;
+          }
+        }
+        if (pick < 0) pick = last;
+        if (pick >= 0) atomicMin(&sh_pick, pick);
+      }
+      __syncthreads();
+      if (sh_pick == 0x7fffffff) {
+        // Thread-run bounds and the block bound come from different FP64
+        // association orders; if no run claimed u*T, walk the slice in order.
+        if (tid == 0) {
+          double run = base;
+          int last = -1;
+          for (int j = 0; j < ns; ++j) {
+            const double v = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+            run += v;
+            if (v > 0.0) last = j;
+            if (v > 0.0 && run > thr) {
+              sh_pick = j;
+              break;
+            }
+          }
+          if (sh_pick == 0x7fffffff) sh_pick = last;
+        }
+        __syncthreads();
+      }
+      const int jl = sh_pick;
+      for (int e = tid; e < d; e += kReclBlock) a.centers[(int64_t)s * d + e] = rows[(size_t)jl * DP + e];
+      for (int e = tid; e < DP; e += kReclBlock)
+        __hip_atomic_store(reinterpret_cast<unsigned*>(&a.prow[(s & 1) * DP + e]),
+                           __float_as_uint(rows[(size_t)jl * DP + e]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) a.picks[s] = lo + jl;
+    }
+    grid_barrier(a.bar, (++nbar) * (unsigned)G, &sh_failed);
     made = s + 1;
   }
-  if (tid == 0) {
-    st->n_centers = made;
-    if (made < k && st->status == KMPAR_OK) st->status = KMPAR_E_TOOFEW;
+  if (b == 0 && tid == 0) {
+    a.st->n_centers = made;
+    if (sh_failed) a.st->status = KMPAR_E_HIP;
+    else if (made < a.k && a.st->status == KMPAR_OK) a.st->status = KMPAR_E_TOOFEW;
   }
 }
 
-hipError_t launch_recluster(const float* CallT, int capT, int d, const int* w, const int* rs_end,
-                            int k, uint64_t seed, uint64_t inst, float* E_global, int* picks,
-                            float* centers, kmpar_stats* st, hipStream_t s) {
-  const size_t e_bytes = (size_t)capT * sizeof(float);
-  if (e_bytes <= 48 * 1024) {
-    hipLaunchKernelGGL(k_recluster<true>, dim3(1), dim3(kReclBlock), e_bytes, s, CallT, capT, d, w,
-                       rs_end, k, seed, inst, E_global, picks, centers, st);
-  } else {
-    hipLaunchKernelGGL(k_recluster<false>, dim3(1), dim3(kReclBlock), 0, s, CallT, capT, d, w,
-                       rs_end, k, seed, inst, E_global, picks, centers, st);
-  }
+int recluster_blocks(int capT, int DP, int num_cu) {
+  // Slices of about 512 candidates (a grid barrier costs ~0.8 us at 8-16
+  // workgroups and grows with their number); each slice must fit the LDS budget.
+  const size_t per = (size_t)DP * 4 + 8;
+  int G = (capT + 511) / 512;
+  const int min_g = (int)((capT * per + kReclLdsBudget - 1) / kReclLdsBudget);
+  if (G < min_g) G = min_g;
+  if (G > num_cu) G = num_cu;
+  if (G > kReclMaxBlocks) G = kReclMaxBlocks;
+  if (G < 1) G = 1;
+  return G;
+}
+
+size_t recluster_lds(int capT, int DP, int G) {
+  const int slice = (capT + G - 1) / G + 1;
+  return (size_t)slice * ((size_t)DP * 4 + 8) + (size_t)DP * 4;
+}
+
+hipError_t launch_recluster(const float* Call, int DP, int capT, int d, const int* w,
+                            const int* rs_end, int k, uint64_t seed, uint64_t inst, int G,
+                            double* part, float* prow, unsigned* bar, int* picks, float* centers,
+                            kmpar_stats* st, hipStream_t s) {
+  hipError_t e = launch_fill_i32(reinterpret_cast<int*>(bar), 0, 1, s);
+  if (e != hipSuccess) return e;
+  ReclArgs a;
+  a.Call = Call;
+  a.DP = DP;
+  a.d = d;
+  a.w = w;
+  a.rs_end = rs_end;
+  a.k = k;
+  a.seed = seed;
+  a.inst = inst;
+  a.slice_cap = (capT + G - 1) / G + 1;
+  a.part = part;
+  a.prow = prow;
+  a.bar = bar;
+  a.picks = picks;
+  a.centers = centers;
+  a.st = st;
+  const size_t lds = recluster_lds(capT, DP, G);
+  e = hipFuncSetAttribute((const void*)k_recluster_grid, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_recluster_grid, dim3(G), dim3(kReclBlock), lds, s, a);
   KMPAR_RET_LAST();
 }
 

@@ -34,16 +34,59 @@ struct FoldArgs {
   int first;             // 1: previous D2/A are ignored
   const int* list;       // nullable: only points list[0 .. *list_len)
   const int* list_len;
-  int list_cap;          // grid bound when list != nullptr
+  int list_cap;          // upper bound of *list_len
+  float* norms;          // nullable: also write ||x||^2 (FP32) of every point
 };
 
 hipError_t launch_fold_direct(kmpar_dtype dt, int DP, const FoldArgs& a, hipStream_t s);
+// Listed points only (a.list, a.list_len, a.list_cap), one wave per point.
+hipError_t launch_rescan(kmpar_dtype dt, int DP, const FoldArgs& a, hipStream_t s);
+
+// REFINED screen (see screen_mfma.hip).
+struct ScreenArgs {
+  const void* X;
+  const float* row_scale;
+  int n;
+  int d;
+  int DP;
+  const float* C;        // FP32 candidate rows (DP-padded) used for refinement
+  const int* rs;         // device: id0 = rs[0], m = rs[1] - rs[0]  (nullable)
+  int m_host;
+  int id0_host;
+  const void* Apre;      // bf16 A operands from launch_prep_a (nullptr: read X directly)
+  const void* B;         // bf16 B operands from launch_prep_b
+  const float* ncg;      // (1 - 2G) ||c||^2 per candidate, +inf past m
+  const float* norms;    // ||x||^2 per point
+  float oneminus2g;
+  float* D2;
+  int* A;
+  int first;
+  int* list;             // points the screen could not settle
+  int* list_len;
+  kmpar_stats* stats;    // nullable: receives the listed counts
+};
+
+int screen_split(kmpar_dtype dt, bool centers_are_rows);
+int screen_ksteps(int split, int d);
+bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d);
+float screen_g(int split, int d);
+hipError_t launch_prep_b(int split, int KS, const float* C, int DP, int d, const int* rs,
+                         int m_host, int max_tiles, float om2g, void* B, float* ncg,
+                         hipStream_t s);
+hipError_t launch_screen(kmpar_dtype dt, int split, int KS, const ScreenArgs& a, hipStream_t s);
+bool screen_a_direct(kmpar_dtype dt, int split, int d);
+size_t screen_a_bytes(int n, int KS);
+hipError_t launch_prep_a(kmpar_dtype dt, int split, int KS, const void* X, const float* rsc, int n,
+                         int d, void* Apre, hipStream_t s);
+hipError_t launch_list_reset(int* list_len, kmpar_stats* st, hipStream_t s);
+hipError_t launch_rownorm(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
+                          float* norms, hipStream_t s);
 
 hipError_t launch_first(int n, uint64_t seed, uint64_t inst, int* cand_point, int* rs,
                         kmpar_stats* st, hipStream_t s);
 hipError_t launch_gather(kmpar_dtype dt, const void* X, const float* row_scale, int d, int DP,
                          const int* cand_point, const int* rs, int t, int cap_round, float* Call,
-                         float* CallT, int capT, hipStream_t s);
+                         hipStream_t s);
 hipError_t launch_phi(const float* D2, int n, double* part, double* out, hipStream_t s);
 hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, uint64_t seed, int t,
                        uint64_t inst, int* cnt, int* scan_total, int* rs, int cap_round,
@@ -51,9 +94,14 @@ hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, ui
 hipError_t launch_finish_rounds(const int* rs, int rounds, kmpar_stats* st, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s);
 hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s);
-hipError_t launch_recluster(const float* CallT, int capT, int d, const int* w, const int* rs_end,
-                            int k, uint64_t seed, uint64_t inst, float* E_global, int* picks,
-                            float* centers, kmpar_stats* st, hipStream_t s);
+// Step-8 recluster over G workgroups (see aux_kernels.hip).
+int recluster_blocks(int capT, int DP, int num_cu);
+size_t recluster_lds(int capT, int DP, int G);
+constexpr int kReclMaxBlocks = 512;
+hipError_t launch_recluster(const float* Call, int DP, int capT, int d, const int* w,
+                            const int* rs_end, int k, uint64_t seed, uint64_t inst, int G,
+                            double* part, float* prow, unsigned* bar, int* picks, float* centers,
+                            kmpar_stats* st, hipStream_t s);
 hipError_t launch_pad_rows(const float* C, int m, int d, int DP, float* Cpad, hipStream_t s);
 hipError_t launch_copy_i32(const int* src, int* dst, int64_t count, hipStream_t s);
 

@@ -1,0 +1,524 @@
+// REFINED distance pass: an MFMA screen with a rigorous lower bound, then an
+// FP32 direct-form refinement of the screen winner; points the bound cannot
+// settle are listed and recomputed by the direct-form fold.
+//
+// For point x and candidate c, t = ||x - c||^2 = ||x||^2 + ||c||^2 - 2 x.c.
+// The screen forms x.c on the matrix cores from bf16 operands (exact bf16
+// inputs, or a two/three-term bf16 split of FP32 values, products exact and
+// summed in FP32) and the lower bound
+//   lb = (1 - 2G)(||x||^2 + ||c||^2) - 2 x.c   <=  t  - (direct-form error),
+// where 2G (||x||^2 + ||c||^2) bounds every rounding error of the screen and of
+// the FP32 direct form (host code derives G from d, K and the split).  Per
+// point the kernel keeps the smallest and second smallest lb and the argmin
+// j1, refines t(j1) = r1 exactly as the plain kernel would, and then:
+//   lb_min >= D2                      -> no candidate can be strictly closer;
+//   r1 <  D2 and lb_2nd >  r1         -> j1 is the unique nearest: fold it in;
+//   r1 >= D2 and lb_2nd >= D2         -> no candidate is strictly closer;
+//   otherwise                         -> the point is listed for a full
+//                                        direct-form pass over the candidates.
+// Every decision is therefore the decision of the FP32 direct-form path.
+#include <math.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace kmpar {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// FP32 -> bf16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Operand k of the screen's K axis.  SPLIT 1: A = x, B = c (both exact in
+// bf16).  SPLIT 2: A = [x | x], B = [hi(c) | lo(c)].  SPLIT 3: A = [hi(x) |
+// lo(x) | hi(x)], B = [hi(c) | hi(c) | lo(c)].  k >= SPLIT*d is zero.
+template <int SPLIT>
+__device__ __forceinline__ uint16_t a_elem(float x, int part) {
+  if constexpr (SPLIT == 3) {
+    const uint16_t h = bf16_rne(x);
+    return part == 1 ? bf16_rne(x - bf16_val(h)) : h;
+  } else {
+    return bf16_rne(x);
+  }
+}
+template <int SPLIT>
+__device__ __forceinline__ uint16_t b_elem(float c, int part) {
+  const uint16_t h = bf16_rne(c);
+  if constexpr (SPLIT == 1) return h;
+  const uint16_t l = bf16_rne(c - bf16_val(h));
+  if constexpr (SPLIT == 2) return part == 0 ? h : l;
+  return part == 2 ? l : h;
+}
+
+// --------------------------------------------------------------- B operands
+// One wave per tile of 16 candidates: writes KS k-steps of 64 lanes x 8 bf16
+// in the lane order the MFMA B operand uses (lane l: candidate l%16,
+// k = s*32 + (l/16)*8 + e), plus ncg_j = (1 - 2G) ||c_j||^2 (+inf past m).
+template <int SPLIT, int KS>
+__global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, const int* rs,
+                                               int m_host, float oneminus2g, u16x8* B,
+                                               float* ncg) {
+  int id0 = 0, m = m_host;
+  if (rs) {
+    id0 = rs[0];
+    m = rs[1] - id0;
+  }
+  const int q = blockIdx.x;
+  if (q * 16 >= m) return;
+  const int lane = threadIdx.x;
+  const int j = q * 16 + (lane % 16);
+  const bool valid = j < m;
+  const float* c = C + (int64_t)(id0 + (valid ? j : 0)) * DP;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    u16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = s * 32 + (lane / 16) * 8 + e;
+      const int part = k / d, coord = k - part * d;
+      v[e] = (valid && part < SPLIT) ? b_elem<SPLIT>(c[coord], part) : (uint16_t)0;
+    }
+    B[((int64_t)q * KS + s) * 64 + lane] = v;
+  }
+  if (lane < 16) {
+    float nc = 0.0f;
+    if (valid)
+      for (int e = 0; e < d; ++e) nc = fmaf(c[e], c[e], nc);
+    ncg[j] = valid ? oneminus2g * nc : INFINITY;
+  }
+}
+
+// --------------------------------------------------------------- A operands
+// The point side of the screen, built once per call: for every tile of 16
+// points and k-step s, 64 lanes x 8 bf16 in the lane order of the MFMA A
+// operand (lane l: point l%16, k = s*32 + (l/16)*8 + e).  Rows are staged
+// through LDS as FP32 with coalesced loads.  Tiles past n are zero.
+template <int SPLIT, int KS, typename T>
+__global__ __launch_bounds__(256) void k_prep_a(const T* X, const float* row_scale, int n, int d,
+                                                u16x8* Apre) {
+  extern __shared__ float xs[];  // [64][d]
+  const int p0 = blockIdx.x * 64;
+  const int np = max(0, min(64, n - p0));
+  for (int idx = threadIdx.x; idx < np * d; idx += 256)
+    xs[idx] = Elem<T>::get(X, (int64_t)p0 * d + idx, row_scale_of<T>(row_scale, p0 + idx / d));
+  __syncthreads();
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int row = w * 16 + (lane % 16);
+  const bool valid = row < np;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    u16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = s * 32 + (lane / 16) * 8 + e;
+      const int part = k / d, coord = k - part * d;
+      v[e] = (valid && part < SPLIT) ? a_elem<SPLIT>(xs[row * d + coord], part) : (uint16_t)0;
+    }
+    Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
+  }
+}
+
+// --------------------------------------------------------------- the screen
+// Block = kWaves waves; wave w owns kRT tiles of 16 points (A operands held in
+// registers for the pass).  Candidate tiles stream through two LDS buffers:
+// while the waves compute on chunk c, the direct global->LDS loads of chunk
+// c+1 are in flight.  Each accumulator starts at -ncg_j/2, so it ends as
+// acc = x.c - ncg_j/2 = -(lb - (1-2G)||x||^2)/2, and the smallest lb is the
+// largest acc.
+constexpr int kRT = 4;                 // 16-point row tiles per wave
+constexpr int kWaves = 4;              // waves per block
+constexpr int kWavePts = kRT * 16;     // points per wave
+constexpr int kBlockPts = kWaves * kWavePts;
+constexpr int kStageBytes = 32 * 1024; // LDS per staging buffer
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef const __attribute__((address_space(1))) void gbl_void;
+
+// acc[r] = A[r] . B(tile q) - ncg_j / 2, for the wave's kRT row tiles.
+template <int KS>
+__device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[kRT][KS], const u16x8* buf,
+                                          const float* ncs, int q, int lane, f32x4 (&acc)[kRT]) {
+  const float cj = ncs[q * 16 + (lane % 16)];
+  const f32x4 cinit = {cj, cj, cj, cj};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const bf16x8 b = __builtin_bit_cast(bf16x8, buf[(q * KS + s) * 64 + lane]);
+#pragma unroll
+    for (int r = 0; r < kRT; ++r)
+      acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[r][s], b, s == 0 ? cinit : acc[r], 0, 0, 0);
+  }
+}
+
+// One merge step of (largest, second largest, argmax) with the lane CTRL
+// positions away in the same 16-lane row (DPP row_ror).
+template <int CTRL>
+__device__ __forceinline__ void merge_row_ror(float& s1, float& s2, int& ix) {
+  const float o1 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s1), CTRL, 0xF, 0xF, false));
+  const float o2 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s2), CTRL, 0xF, 0xF, false));
+  const int oi = __builtin_amdgcn_update_dpp(0, ix, CTRL, 0xF, 0xF, false);
+  const bool take = (o1 > s1) || (o1 == s1 && (unsigned)oi < (unsigned)ix);
+  s2 = fmaxf(fminf(s1, o1), fmaxf(s2, o2));
+  ix = take ? oi : ix;
+  s1 = fmaxf(s1, o1);
+}
+
+// Largest / second largest acc and the argmax of each (row tile, row).
+__device__ __forceinline__ void epilogue(const f32x4 (&acc)[kRT], int j, float (&s1)[kRT][4],
+                                         float (&s2)[kRT][4], int (&ix)[kRT][4]) {
+#pragma unroll
+  for (int r = 0; r < kRT; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float v = acc[r][i];
+      const bool gt = v > s1[r][i];
+      s2[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], s2[r][i], v);
+      ix[r][i] = gt ? j : ix[r][i];
+      s1[r][i] = fmaxf(s1[r][i], v);
+    }
+}
+
+template <int SPLIT, int KS, typename T, bool DIRECT>
+__global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
+  constexpr int CT = kStageBytes / (KS * 64 * 16);  // candidate tiles per chunk
+  constexpr int CHUNK_V = CT * KS * 64;             // 16-byte vectors per chunk
+  __shared__ u16x8 sB[2][CHUNK_V];
+  __shared__ float sN[2][CT * 16];
+  __shared__ float sRes[kWaves][kWavePts][2];
+  __shared__ int sIdx[kWaves][kWavePts];
+
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int d = a.d;
+  int id0 = a.id0_host, m = a.m_host;
+  if (a.rs) {
+    id0 = a.rs[0];
+    m = a.rs[1] - id0;
+  }
+  const int ntiles = (m + 15) / 16;
+  const int nchunks = (ntiles + CT - 1) / CT;
+  const int wbase = blockIdx.x * kBlockPts + wave * kWavePts;
+  const T* __restrict__ X = static_cast<const T*>(a.X);
+  const u16x8* __restrict__ Bg = static_cast<const u16x8*>(a.B);
+
+  // Issues the direct loads of chunk c into buffer c & 1 (each wave moves
+  // 1 KB per instruction; lane i lands at base + 16 i).
+  auto stage = [&](int c) {
+    const int nt = min(CT, ntiles - c * CT);
+    const int nv = nt * KS * 64;
+    u16x8* dst = sB[c & 1];
+    const u16x8* src = Bg + (int64_t)c * CHUNK_V;
+    for (int v0 = wave * 64; v0 < nv; v0 += kWaves * 64)
+      __builtin_amdgcn_global_load_lds((gbl_void*)(src + v0 + lane), (lds_void*)(dst + v0), 16, 0, 0);
+  };
+  auto stage_ncg = [&](int c) -> float {
+    const int idx = c * CT * 16 + threadIdx.x;
+    return (threadIdx.x < CT * 16 && idx < ntiles * 16) ? a.ncg[idx] : INFINITY;
+  };
+
+  if (nchunks > 0) stage(0);
+  float ncg_next = nchunks > 0 ? stage_ncg(0) : INFINITY;
+
+  // A operands of this wave's points, kept in registers for the pass: from
+  // the prepared buffer, or straight from X when X is bf16 with d % 8 == 0
+  // (its rows then already hold the operand bytes).
+  bf16x8 Aop[kRT][KS];
+#pragma unroll
+  for (int r = 0; r < kRT; ++r) {
+    const int tile = wbase / 16 + r;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+      if constexpr (DIRECT) {
+        const int p = wbase + r * 16 + (lane % 16);
+        const int k0 = s * 32 + (lane / 16) * 8;
+        if (p < a.n && k0 < d)
+          v = *reinterpret_cast<const u16x8*>(static_cast<const uint16_t*>(a.X) + (int64_t)p * d + k0);
+      } else {
+        v = static_cast<const u16x8*>(a.Apre)[((int64_t)tile * KS + s) * 64 + lane];
+      }
+      Aop[r][s] = __builtin_bit_cast(bf16x8, v);
+    }
+  }
+
+  // Largest and second largest acc, and the argmax, per (row tile, row).
+  float s1[kRT][4], s2[kRT][4];
+  int ix[kRT][4];
+#pragma unroll
+  for (int r = 0; r < kRT; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      s1[r][i] = -INFINITY;
+      s2[r][i] = -INFINITY;
+      ix[r][i] = -1;
+    }
+
+  for (int c = 0; c < nchunks; ++c) {
+    if (threadIdx.x < CT * 16) sN[c & 1][threadIdx.x] = -0.5f * ncg_next;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();  // chunk c is in LDS; everyone is done with chunk c-1
+    if (c + 1 < nchunks) {
+      stage(c + 1);
+      ncg_next = stage_ncg(c + 1);
+    }
+    const int nt = min(CT, ntiles - c * CT);
+    const u16x8* buf = sB[c & 1];
+    const float* ncs = sN[c & 1];
+    // Software pipeline: the MFMAs of tile q+1 are issued before the
+    // epilogue of tile q, so matrix and vector units overlap within a wave.
+    f32x4 acc[kRT];
+    mfma_tile<KS>(Aop, buf, ncs, 0, lane, acc);
+    for (int q = 0; q + 1 < nt; ++q) {
+      f32x4 nxt[kRT];
+      mfma_tile<KS>(Aop, buf, ncs, q + 1, lane, nxt);
+      epilogue(acc, (c * CT + q) * 16 + (lane % 16), s1, s2, ix);
+#pragma unroll
+      for (int r = 0; r < kRT; ++r) acc[r] = nxt[r];
+    }
+    epilogue(acc, (c * CT + nt - 1) * 16 + (lane % 16), s1, s2, ix);
+  }
+
+  // Merge the 16 lanes that share a point row group (lane / 16): rotations
+  // by 8, 4, 2, 1 inside each 16-lane DPP row leave every lane with the
+  // merge of all 16 (the top-2 merge with lowest-id ties is commutative and
+  // associative).
+#pragma unroll
+  for (int r = 0; r < kRT; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      merge_row_ror<0x128>(s1[r][i], s2[r][i], ix[r][i]);
+      merge_row_ror<0x124>(s1[r][i], s2[r][i], ix[r][i]);
+      merge_row_ror<0x122>(s1[r][i], s2[r][i], ix[r][i]);
+      merge_row_ror<0x121>(s1[r][i], s2[r][i], ix[r][i]);
+    }
+  if (lane % 16 == 0) {
+#pragma unroll
+    for (int r = 0; r < kRT; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pl = r * 16 + (lane / 16) * 4 + i;
+        sRes[wave][pl][0] = s1[r][i];
+        sRes[wave][pl][1] = s2[r][i];
+        sIdx[wave][pl] = ix[r][i];
+      }
+  }
+  __syncthreads();
+
+  // One lane per point: decide, refine, fold or list.  The refinement
+  // reads the wave's rows from LDS (staged with coalesced loads into the
+  // now idle staging buffers, 16 KB per wave) and candidate rows as float4.
+  const int p = wbase + lane;
+  const bool valid = p < a.n;
+  const int j1 = sIdx[wave][lane];
+  const float nxg = valid ? a.oneminus2g * a.norms[p] : 0.0f;
+  const float lbmin = fmaf(sRes[wave][lane][0], -2.0f, nxg);
+  const float lb2 = fmaf(sRes[wave][lane][1], -2.0f, nxg);
+  const float D = (a.first || !valid) ? INFINITY : a.D2[p];
+  const bool refine = valid && j1 >= 0 && lbmin < D;
+  float r1 = 0.0f;
+  float* xw = reinterpret_cast<float*>(&sB[0][0]) + wave * (kStageBytes * 2 / kWaves / 4);
+  const int R = min(64, (kStageBytes * 2 / kWaves / 4) / d);
+  const int nvalid = __ballot(refine) ? max(0, min(64, a.n - wbase)) : 0;
+  for (int c0 = 0; c0 < nvalid; c0 += R) {
+    const int nr = min(R, nvalid - c0);
+    const int64_t base = (int64_t)(wbase + c0) * d;
+    for (int idx = lane; idx < nr * d; idx += 64)
+      xw[idx] = Elem<T>::get(X, base + idx, row_scale_of<T>(a.row_scale, wbase + c0 + idx / d));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (refine && lane >= c0 && lane < c0 + nr) {
+      const float* xr = xw + (lane - c0) * d;
+      const float4* cr = reinterpret_cast<const float4*>(a.C + (int64_t)(id0 + j1) * a.DP);
+      for (int e4 = 0; e4 * 4 < d; ++e4) {
+        const float4 cv = cr[e4];
+        const float cc[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = 4 * e4 + q;
+          if (e < d) {
+            const float t = xr[e] - cc[q];
+            r1 = fmaf(t, t, r1);
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (!valid) return;
+  if (!refine) {
+    if (a.first) {  // m == 0 (never on the paths that call the screen)
+      a.D2[p] = INFINITY;
+      a.A[p] = -1;
+    }
+    return;
+  }
+  bool listed = false;
+  if (r1 < D) {
+    if (lb2 > r1) {
+      a.D2[p] = r1;
+      a.A[p] = id0 + j1;
+    } else {
+      listed = true;
+    }
+  } else if (!(lb2 >= D)) {
+    listed = true;
+  }
+  if (listed) {
+    const int pos = atomicAdd(a.list_len, 1);
+    a.list[pos] = p;
+  }
+}
+
+// Adds the previous pass's listed count to the stats and clears it.
+__global__ void k_list_reset(int* list_len, kmpar_stats* st) {
+  if (threadIdx.x == 0) {
+    if (st) st->n_rescanned += *list_len;
+    *list_len = 0;
+  }
+}
+
+template <int SPLIT, int KS, typename T>
+static void launch_one(const ScreenArgs& a, hipStream_t s) {
+  const int blocks = (a.n + kBlockPts - 1) / kBlockPts;
+  if (a.Apre)
+    hipLaunchKernelGGL((k_screen<SPLIT, KS, T, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_screen<SPLIT, KS, T, true>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+}
+
+template <int SPLIT, typename T>
+static hipError_t launch_split(int KS, const ScreenArgs& a, hipStream_t s) {
+  switch (KS) {
+    case 1: launch_one<SPLIT, 1, T>(a, s); break;
+    case 2: launch_one<SPLIT, 2, T>(a, s); break;
+    case 3: launch_one<SPLIT, 3, T>(a, s); break;
+    case 4: launch_one<SPLIT, 4, T>(a, s); break;
+    case 5: launch_one<SPLIT, 5, T>(a, s); break;
+    case 6: launch_one<SPLIT, 6, T>(a, s); break;
+    case 7: launch_one<SPLIT, 7, T>(a, s); break;
+    case 8: launch_one<SPLIT, 8, T>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int SPLIT, int KS, typename T>
+static void launch_prep_a_one(const void* X, const float* rsc, int n, int d, void* Apre,
+                              hipStream_t s) {
+  const int blocks = (n + kBlockPts - 1) / kBlockPts * (kBlockPts / 64);
+  hipLaunchKernelGGL((k_prep_a<SPLIT, KS, T>), dim3(blocks), dim3(256), (size_t)64 * d * 4, s,
+                     static_cast<const T*>(X), rsc, n, d, static_cast<u16x8*>(Apre));
+}
+
+template <int SPLIT, typename T>
+static hipError_t launch_prep_a_split(int KS, const void* X, const float* rsc, int n, int d,
+                                      void* Apre, hipStream_t s) {
+  switch (KS) {
+#define KMPAR_PA(V) \
+  case V: launch_prep_a_one<SPLIT, V, T>(X, rsc, n, d, Apre, s); break;
+    KMPAR_PA(1) KMPAR_PA(2) KMPAR_PA(3) KMPAR_PA(4) KMPAR_PA(5) KMPAR_PA(6) KMPAR_PA(7)
+    KMPAR_PA(8)
+#undef KMPAR_PA
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool screen_a_direct(kmpar_dtype dt, int split, int d) {
+  return dt == KMPAR_BF16 && split == 1 && d % 8 == 0;
+}
+
+size_t screen_a_bytes(int n, int KS) {
+  const size_t tiles = (size_t)(n + kBlockPts - 1) / kBlockPts * (kBlockPts / 16);
+  return tiles * KS * 64 * 16;
+}
+
+hipError_t launch_prep_a(kmpar_dtype dt, int split, int KS, const void* X, const float* rsc, int n,
+                         int d, void* Apre, hipStream_t s) {
+  if (dt == KMPAR_F32 && split == 3) return launch_prep_a_split<3, float>(KS, X, rsc, n, d, Apre, s);
+  if (dt == KMPAR_BF16 && split == 1) return launch_prep_a_split<1, bf16_t>(KS, X, rsc, n, d, Apre, s);
+  if (dt == KMPAR_BF16 && split == 2) return launch_prep_a_split<2, bf16_t>(KS, X, rsc, n, d, Apre, s);
+  return hipErrorInvalidValue;
+}
+
+template <int SPLIT>
+static hipError_t launch_prep_split(int KS, const float* C, int DP, int d, const int* rs, int m_host,
+                                    int max_tiles, float om2g, void* B, float* ncg, hipStream_t s) {
+  u16x8* b = static_cast<u16x8*>(B);
+  switch (KS) {
+#define KMPAR_PREP(V)                                                                           \
+  case V:                                                                                       \
+    hipLaunchKernelGGL((k_prep_b<SPLIT, V>), dim3(max_tiles), dim3(64), 0, s, C, DP, d, rs,    \
+                       m_host, om2g, b, ncg);                                                   \
+    break;
+    KMPAR_PREP(1) KMPAR_PREP(2) KMPAR_PREP(3) KMPAR_PREP(4) KMPAR_PREP(5) KMPAR_PREP(6)
+    KMPAR_PREP(7) KMPAR_PREP(8)
+#undef KMPAR_PREP
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int screen_split(kmpar_dtype dt, bool centers_are_rows) {
+  if (dt == KMPAR_F32) return 3;
+  if (dt == KMPAR_BF16) return centers_are_rows ? 1 : 2;
+  return 0;  // FP8: no screen (direct form)
+}
+
+int screen_ksteps(int split, int d) { return split ? (split * d + 31) / 32 : 0; }
+
+bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d) {
+  const int sp = screen_split(dt, centers_are_rows);
+  return sp != 0 && screen_ksteps(sp, d) <= 8;
+}
+
+// Relative error budget of the screen, as a multiple of ||x||^2 + ||c||^2:
+// bf16 split truncation (twice the dot), FP32 accumulation of K products,
+// FP32 norms, the roundings of the lower-bound arithmetic, and the FP32
+// direct-form error of the distances it is compared with; times 2 for margin.
+float screen_g(int split, int d) {
+  const double u = 0x1.0p-24;
+  const int K = 32 * screen_ksteps(split, d);
+  double split_err = 0.0;
+  if (split == 3) split_err = 3.2 * 0x1.0p-16;
+  if (split == 2) split_err = 1.1 * 0x1.0p-16;
+  // K products plus the -ncg/2 bias, summed in FP32: |sum of terms| <=
+  // 1.01 (||x||^2 + ||c||^2), doubled by the -2 that turns acc into lb.
+  const double acc_err = 2.05 * (K + 1) * u;
+  const double misc = (d + 8) * u + 2.0 * (d + 2) * u;
+  const double safety = 2.0;  // 2G = safety * budget
+  return (float)(safety * (split_err + acc_err + misc) / 2.0);
+}
+
+hipError_t launch_prep_b(int split, int KS, const float* C, int DP, int d, const int* rs,
+                         int m_host, int max_tiles, float om2g, void* B, float* ncg,
+                         hipStream_t s) {
+  if (max_tiles <= 0) return hipSuccess;
+  switch (split) {
+    case 1: return launch_prep_split<1>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, s);
+    case 2: return launch_prep_split<2>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, s);
+    case 3: return launch_prep_split<3>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_screen(kmpar_dtype dt, int split, int KS, const ScreenArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_list_reset, dim3(1), dim3(64), 0, s, a.list_len, a.stats);
+  if (dt == KMPAR_F32 && split == 3) return launch_split<3, float>(KS, a, s);
+  if (dt == KMPAR_BF16 && split == 1) return launch_split<1, bf16_t>(KS, a, s);
+  if (dt == KMPAR_BF16 && split == 2) return launch_split<2, bf16_t>(KS, a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_list_reset(int* list_len, kmpar_stats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_list_reset, dim3(1), dim3(64), 0, s, list_len, st);
+  return hipGetLastError();
+}
+
+}  // namespace kmpar

@@ -71,7 +71,7 @@ EXPORTED = ["kmpar_create", "kmpar_destroy", "kmpar_strerror", "kmpar_last_error
             "kmpar_sizeof_stats", "kmpar_max_candidates", "kmpar_workspace_size", "kmpar_init",
             "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_profile_enable",
             "kmpar_profile_read"]
-SLOT_FOLD_DIRECT = 0
+SLOT_FOLD_DIRECT, SLOT_SCREEN, SLOT_RESCAN = 0, 1, 2
 
 
 class KmparError(RuntimeError):

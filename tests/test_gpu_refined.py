@@ -1,0 +1,123 @@
+"""REFINED mode: MFMA screen + FP32 direct-form refinement.
+
+The screen's lower bound includes the FP32 direct-form error, so every
+decision it takes is the decision the plain FP32 path takes: the two modes
+must agree bit for bit (candidates, D^2, assignment, weights, picks,
+centers, phi), and the refined run must pass the same oracle replay."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1203_6402_amd import synth
+from tests.gpu_util import compare_init, decoded_fp64, gpu_init, to_bf16_bits
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_1203_6402_amd import kmpar
+    assert torch.cuda.is_available()
+    return kmpar
+
+
+@pytest.fixture(scope="module")
+def plain(K):
+    return K.Context(0, K.MODE_PLAIN_FP32)
+
+
+@pytest.fixture(scope="module")
+def refined(K):
+    return K.Context(0, K.MODE_REFINED)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _same_init(a, b):
+    assert torch.equal(a.centers, b.centers)
+    for key in a.trace:
+        assert torch.equal(a.trace[key], b.trace[key]), key
+    sa, sb = dict(a.stats), dict(b.stats)
+    sa.pop("n_rescanned")
+    sb.pop("n_rescanned")
+    assert sa == sb
+
+
+@pytest.mark.parametrize("n,d,k,ell,rounds,kind", [
+    (10000, 15, 50, 100.0, 5, "gauss"),     # GaussMixture, split-3 screen, K = 64
+    (20011, 42, 60, 120.0, 5, "heavy"),     # KDD-shaped heavy tails, K = 128
+    (5003, 85, 40, 80.0, 4, "sigma"),       # largest split-3 row (K = 256)
+    (3001, 3, 20, 40.0, 5, "gauss"),        # tiny d
+])
+def test_refined_equals_plain_f32(plain, refined, n, d, k, ell, rounds, kind):
+    if kind == "gauss":
+        X = synth.gauss_mixture(n, d, k, 10.0, seed=n)
+    elif kind == "heavy":
+        X = synth.heavy_tailed(n, d, seed=n)
+    else:
+        X = synth.gauss_mixture_sigma(n, d, 60, seed=n)
+    Xd = _dev(X)
+    a = plain.init(Xd, k=k, ell=ell, rounds=rounds, seed=5, trace=True)
+    b = refined.init(Xd, k=k, ell=ell, rounds=rounds, seed=5, trace=True)
+    torch.cuda.synchronize()
+    _same_init(a, b)
+    tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
+    compare_init(X.astype(np.float64), b, tr, k, ell, rounds, 5)
+    # Most points are settled by the screen.
+    assert b.stats["n_rescanned"] <= 0.05 * n * rounds
+
+
+@pytest.mark.parametrize("d", [16, 64, 128, 256])
+def test_refined_equals_plain_bf16(plain, refined, d):
+    X = synth.gauss_mixture_sigma(6007, d, 80, seed=d)
+    Xb = to_bf16_bits(X)
+    Xd = _dev(Xb).view(torch.bfloat16)
+    a = plain.init(Xd, k=60, ell=120.0, rounds=5, seed=2, trace=True)
+    b = refined.init(Xd, k=60, ell=120.0, rounds=5, seed=2, trace=True)
+    torch.cuda.synchronize()
+    _same_init(a, b)
+    tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
+    compare_init(decoded_fp64(Xb, "bf16"), b, tr, 60, 120.0, 5, 2)
+
+
+@pytest.mark.parametrize("dt,d,m", [("f32", 42, 500), ("f32", 15, 37), ("bf16", 128, 300),
+                                    ("bf16", 64, 33)])
+def test_refined_assign_cost_lloyd_equal_plain(plain, refined, dt, d, m):
+    X = synth.gauss_mixture_sigma(9001, d, 200, seed=m)
+    if dt == "bf16":
+        Xh = to_bf16_bits(X)
+        Xd = _dev(Xh).view(torch.bfloat16)
+        X64 = decoded_fp64(Xh, "bf16")
+    else:
+        Xd = _dev(X)
+        X64 = X.astype(np.float64)
+    rng = np.random.default_rng(m)
+    C = (X64[rng.choice(9001, m, replace=False)] + rng.normal(size=(m, d)) * 0.1).astype(np.float32)
+    a1, d1 = plain.assign(Xd, _dev(C))
+    a2, d2 = refined.assign(Xd, _dev(C))
+    p1, p2 = plain.cost(Xd, _dev(C)), refined.cost(Xd, _dev(C))
+    torch.cuda.synchronize()
+    assert torch.equal(a1, a2) and torch.equal(d1, d2) and torch.equal(p1, p2)
+    oa, od2, _ = O.nearest(X64, C.astype(np.float64))
+    np.testing.assert_allclose(d2.cpu().numpy(), od2, rtol=1e-5)
+    C1, C2 = _dev(C), _dev(C)
+    for _ in range(3):
+        x1, q1 = plain.lloyd_step(Xd, C1, want_assign=True)
+        x2, q2 = refined.lloyd_step(Xd, C2, want_assign=True)
+        torch.cuda.synchronize()
+        assert torch.equal(x1, x2) and torch.equal(q1, q2) and torch.equal(C1, C2)
+
+
+def test_refined_heavy_tailed_large_norm_gap(plain, refined):
+    # Rows whose norms differ by many orders of magnitude from their nearest
+    # candidates: the screen must hand the hard cases to the direct form.
+    X = synth.heavy_tailed(30000, 42, seed=99)
+    X[::97] *= 1e4
+    Xd = _dev(X)
+    a = plain.init(Xd, k=100, ell=200.0, rounds=5, seed=7, trace=True)
+    b = refined.init(Xd, k=100, ell=200.0, rounds=5, seed=7, trace=True)
+    torch.cuda.synchronize()
+    _same_init(a, b)
