@@ -47,6 +47,45 @@ def cpu_baseline(X, k, ell, rounds, seed, rows):
                       f"(k={k}, ell={ell:g}, r={rounds}); {evals:.3e} evals in {dt:.1f} s"}
 
 
+def precision_compare(kmpar, synth, torch, seed, steps=2):
+    """BF16-refined vs plain FP32 on the precision workload: n = 16M, d = 128,
+    1,000 Gaussian components (centers N(0, 25 I), sigma logU[0.5, 4]), X in
+    bf16, k = 1000, ell = 2k, r = 5."""
+    n, d, k, rounds = 16_000_000, 128, 1000, 5
+    ell = 2.0 * k
+    log("precision workload: generating 16M x 128 bf16 on the device")
+    Xb = synth.gauss_mixture_sigma_torch(n, d, 1000, seed=seed, device="cuda:0",
+                                         out_dtype=torch.bfloat16)
+    out = {"workload": "Gaussian mixture, 1,000 components, bf16 storage (synthetic)", "n": n,
+           "d": d, "k": k, "ell": ell, "rounds": rounds}
+    res = {}
+    for name, mode in (("refined_bf16", kmpar.MODE_REFINED), ("plain_fp32", kmpar.MODE_PLAIN_FP32)):
+        ctx = kmpar.Context(0, mode)
+        r = ctx.init(Xb, k=k, ell=ell, rounds=rounds, seed=seed)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ctx.init(Xb, k=k, ell=ell, rounds=rounds, seed=seed, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = (ms, r)
+        out[f"{name}_ms"] = ms
+        out[f"{name}_evals_per_s"] = float(n) * r.stats["n_candidates"] / (ms / 1e3)
+        log(f"precision {name}: {ms:.2f} ms/init, |C|={r.stats['n_candidates']}")
+        del ctx
+    (mr, rr), (mp, rp) = res["refined_bf16"], res["plain_fp32"]
+    phi_r, phi_p = rr.stats["phi"][-1], rp.stats["phi"][-1]
+    out["speedup_refined_vs_plain"] = mp / mr
+    out["final_phi_rel_diff"] = abs(phi_r - phi_p) / max(abs(phi_p), 1e-300)
+    out["centers_bitwise_equal"] = bool(torch.equal(rr.centers, rp.centers))
+    out["rescanned_points"] = rr.stats["n_rescanned"]
+    del Xb
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,9 +97,11 @@ def main():
     ap.add_argument("--ell-mult", type=float, default=2.0)
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", choices=["plain", "refined"], default="plain")
-    ap.add_argument("--cpu-rows", type=int, default=200_000)
+    ap.add_argument("--mode", choices=["plain", "refined"], default="refined")
+    ap.add_argument("--cpu-rows", type=int, default=2_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the BF16-refined vs FP32-plain comparison on the precision workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -135,6 +176,10 @@ def main():
     log(f"dominant {dom}: avg {dur_per_launch*1e6:.1f} us, {achieved:.2f} TFLOP/s algorithmic "
         f"({100*achieved/peak:.1f}% of {peak})")
 
+    precision = None
+    if not args.no_precision:
+        precision = precision_compare(kmpar, synth, torch, args.seed)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline on {args.cpu_rows} rows")
@@ -149,7 +194,7 @@ def main():
                       "mode": args.mode, "n_candidates": ncand, "evals_per_step": evals,
                       "rescanned_points": rp.stats["n_rescanned"],
                       "parallelism": "single GPU"},
-           "roofline": roofline, "cpu_baseline": cpu}
+           "roofline": roofline, "cpu_baseline": cpu, "precision": precision}
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,122 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times, on outputs the oracle can compute one by one:
+
+* D^2 and the nearest candidate of sampled points against the GPU's final
+  candidate set (FP64 oracle);
+* every round's keep/drop decision of the sampled points: the oracle's own
+  D^2 of the point against the candidates kept before that round, the
+  Philox draw, and phi_{t-1} as the GPU reports it (the oracle cannot sum n
+  distances at this size within the test's budget; phi's own parity is
+  covered at smaller sizes);
+* Step 7 weights exactly (a bincount of the GPU's assignment);
+* Step 8 by oracle replay on the GPU's weighted candidates;
+* REFINED and PLAIN bit-identical.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1203_6402_amd import synth
+from tests.gpu_util import decoded_fp64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_1203_6402_amd import kmpar
+    assert torch.cuda.is_available()
+    return kmpar
+
+
+def _check_sampled(X64_rows, sample, cand_rows, tr, st, ell, seed, band):
+    """X64_rows: FP64 rows of the sampled points; cand_rows: FP64 rows of
+    every candidate in id order."""
+    cp = tr["cand_point"]
+    # final D^2 / argmin against the whole candidate set
+    a, d2, snd = O.nearest(X64_rows, cand_rows)
+    g_d2 = tr["d2"][sample].astype(np.float64)
+    pos = d2 > 0
+    assert np.all(g_d2[~pos] == 0)
+    np.testing.assert_allclose(g_d2[pos], d2[pos], rtol=1e-5)
+    diff = tr["assign"][sample] != a
+    gap = (snd - d2) / np.maximum(d2, 1e-300)
+    assert np.all(gap[diff] <= band), "argmin differs outside the band"
+    # round-by-round draws of the sampled points
+    bounds = np.cumsum([0] + st["round_count"])
+    flagged = 0
+    for t in range(1, len(st["round_count"])):
+        _, d2t, _ = O.nearest(X64_rows, cand_rows[:bounds[t]])
+        phi = st["phi"][t - 1]
+        p = np.minimum(1.0, ell * d2t / phi)
+        u = np.array([O.uniform(seed, O.TAG_ROUND, int(i), t, 0) for i in sample])
+        mine = u < p
+        kept = np.isin(sample, cp[bounds[t]:bounds[t + 1]])
+        dis = mine != kept
+        ok = np.abs(u[dis] - p[dis]) <= band * p[dis] + 1e-300
+        assert np.all(ok), f"round {t}: draw differs outside the band"
+        flagged += int(dis.sum())
+    return flagged
+
+
+def test_c1_kdd_shaped_full_size(K):
+    n, d, k, ell, rounds, seed = 4_800_000, 42, 500, 1000.0, 5, 0
+    X = synth.heavy_tailed(n, d, seed=seed)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    plain = K.Context(0, K.MODE_PLAIN_FP32)
+    refined = K.Context(0, K.MODE_REFINED)
+    b = refined.init(Xd, k=k, ell=ell, rounds=rounds, seed=seed, trace=True)
+    a = plain.init(Xd, k=k, ell=ell, rounds=rounds, seed=seed, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a.centers, b.centers)
+    for key in a.trace:
+        assert torch.equal(a.trace[key], b.trace[key]), key
+    st = b.stats
+    assert st["status"] == 0 and st["n_centers"] == k
+    tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
+    cp = tr["cand_point"]
+    assert len(np.unique(cp)) == cp.size == st["n_candidates"]
+    assert np.all(np.diff(st["phi"]) <= 0)
+    assert np.array_equal(np.bincount(tr["assign"], minlength=cp.size), tr["cand_weight"])
+    assert tr["cand_weight"].sum() == n
+    # Table 5's qualitative effect: clamped probabilities keep |C| below 1 + r*ell.
+    assert cp.size < 1 + rounds * ell
+    rng = np.random.default_rng(1)
+    sample = np.sort(np.concatenate([rng.choice(n, 1500, replace=False), cp[:200]]))
+    cand_rows = X[cp].astype(np.float64)
+    _check_sampled(X[sample].astype(np.float64), sample, cand_rows, tr, st, ell, seed,
+                   O.fp32_band(d))
+    picks, nf, nb = O.kpp_weighted(cand_rows, tr["cand_weight"], k, seed, follow=tr["center_cand"],
+                                   tol=O.fp32_band(d))
+    assert nb == 0
+    np.testing.assert_array_equal(b.centers.cpu().numpy(), X[cp[tr["center_cand"]]])
+
+
+def test_c2_precision_full_size(K):
+    n, d, k, ell, rounds, seed = 16_000_000, 128, 1000, 2000.0, 5, 0
+    Xb = synth.gauss_mixture_sigma_torch(n, d, 1000, seed=seed, device="cuda:0",
+                                         out_dtype=torch.bfloat16)
+    plain = K.Context(0, K.MODE_PLAIN_FP32)
+    refined = K.Context(0, K.MODE_REFINED)
+    b = refined.init(Xb, k=k, ell=ell, rounds=rounds, seed=seed, trace=True)
+    a = plain.init(Xb, k=k, ell=ell, rounds=rounds, seed=seed, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a.centers, b.centers)
+    for key in a.trace:
+        assert torch.equal(a.trace[key], b.trace[key]), key
+    st = b.stats
+    assert st["status"] == 0 and st["n_centers"] == k
+    tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
+    cp = tr["cand_point"]
+    assert np.array_equal(np.bincount(tr["assign"], minlength=cp.size), tr["cand_weight"])
+    rng = np.random.default_rng(2)
+    sample = np.sort(rng.choice(n, 1000, replace=False))
+    bits = Xb.view(torch.int16)
+    rows = lambda idx: decoded_fp64(bits[torch.from_numpy(idx).to("cuda:0")].cpu().numpy()
+                                    .view(np.uint16), "bf16")
+    cand_rows = rows(cp)
+    _check_sampled(rows(sample), sample, cand_rows, tr, st, ell, seed, O.fp32_band(d))
+    picks, nf, nb = O.kpp_weighted(cand_rows, tr["cand_weight"], k, seed, follow=tr["center_cand"],
+                                   tol=O.fp32_band(d))
+    assert nb == 0
