@@ -171,6 +171,43 @@ int lloyd_step(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
                int64_t n, int32_t d, float* C, int32_t k, int32_t* assign, double* phi, void* ws,
                size_t ws_bytes, void* stream);
 
+/* One independent clustering instance of kmpar_init_batched (64 bytes). */
+typedef struct kmpar_instance {
+  const void* X;          /* device: n x d rows, the call's dtype            */
+  const float* row_scale; /* device: FP8 row scales, else NULL               */
+  float* centers;         /* device: k x d output, pick order                */
+  kmpar_stats* stats;     /* device, nullable                                */
+  int64_t n;
+  int32_t d;
+  int32_t k;
+  double ell;
+  int32_t rounds;
+  int32_t reserved;
+} kmpar_instance;
+
+/* Workspace bytes of kmpar_init_batched for these instances (host array). */
+int kmpar_workspace_size_batched(const kmpar_ctx* ctx, const kmpar_instance* inst_host,
+                                 int32_t count, kmpar_dtype dtype, size_t* bytes_out);
+
+/* Algorithm 2 for `count` independent instances in grouped launches: every
+ * kernel covers all instances at once (work lists built on the device), so
+ * the whole batch is a fixed sequence of about 8 + 9*rounds launches.
+ * Instance i draws from Philox with inst = i (same keys and counters as
+ * kmpar_init otherwise), so each instance is reproducible on its own.
+ * `inst_host` and `inst_dev` hold the same table: the host copy sizes the
+ * launches, the device copy is what the kernels read (the library copies
+ * nothing between host and device).  All instances share `dtype`; the
+ * distance pass runs in the context's mode (PLAIN_FP32 direct form).
+ * Limits per instance as for kmpar_init; rounds must be equal across the
+ * batch.  Per-instance stats are written when inst[i].stats is not NULL.
+ * `traces_dev` (nullable) is a DEVICE array of `count` kmpar_trace records
+ * whose non-NULL fields receive instance i's candidates, weights, picks,
+ * assignment and D^2 as kmpar_init's trace does. */
+int kmpar_init_batched(kmpar_ctx* ctx, const kmpar_instance* inst_host,
+                       const kmpar_instance* inst_dev, int32_t count, kmpar_dtype dtype,
+                       uint64_t seed, void* ws, size_t ws_bytes, const kmpar_trace* traces_dev,
+                       void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,10 +62,7 @@ int set_err(kmpar_ctx* ctx, int code, const char* fmt, ...) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-int64_t cap_round_of(int64_t n, double ell) {
-  const double c = ceil(ell + 12.0 * sqrt(ell) + 64.0);
-  return c >= (double)n ? n : (int64_t)c;
-}
+int64_t cap_round_of(int64_t n, double ell) { return cap_round_hd(n, ell); }
 
 // Sequential carve-up of the caller's workspace.
 struct Carver {
@@ -661,6 +658,55 @@ int lloyd_step(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   if ((rc = assign_pass(ctx, dtype, L, fa, k, s))) return rc;
   if (phi) KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi, s));
   KMPAR_HIP(launch_lloyd_update(dtype, X, row_scale, (int)n, d, fa.A, k, C, L.lw, s));
+  return KMPAR_OK;
+}
+
+int kmpar_workspace_size_batched(const kmpar_ctx* cctx, const kmpar_instance* inst_host,
+                                 int32_t count, kmpar_dtype dtype, size_t* bytes_out) {
+  kmpar_ctx* ctx = const_cast<kmpar_ctx*>(cctx);
+  if (!bytes_out || !inst_host || count < 1) return set_err(ctx, KMPAR_E_INVAL, "bad batch arguments");
+  if (dtype != KMPAR_F32 && dtype != KMPAR_BF16 && dtype != KMPAR_FP8_E4M3)
+    return set_err(ctx, KMPAR_E_INVAL, "unknown dtype");
+  const int rounds = inst_host[0].rounds;
+  for (int i = 0; i < count; ++i) {
+    const kmpar_instance& I = inst_host[i];
+    if (I.n < 1 || I.n >= (int64_t)1 << 31 || I.d < 1 || I.d > kMaxD || I.k < 1 || I.k > I.n ||
+        I.k > kMaxK || !ell_ok(I.ell) || I.rounds != rounds || rounds < 0 ||
+        rounds > KMPAR_MAX_ROUNDS)
+      return set_err(ctx, KMPAR_E_INVAL, "instance %d out of range", i);
+  }
+  int G = 0, dps[kBatchMaxGroups];
+  *bytes_out = batched_workspace(inst_host, count, rounds, &G, dps);
+  return KMPAR_OK;
+}
+
+int kmpar_init_batched(kmpar_ctx* ctx, const kmpar_instance* inst_host,
+                       const kmpar_instance* inst_dev, int32_t count, kmpar_dtype dtype,
+                       uint64_t seed, void* ws, size_t ws_bytes, const kmpar_trace* traces_dev,
+                       void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  if (!inst_dev || !aligned16(inst_dev)) return set_err(ctx, KMPAR_E_INVAL, "inst_dev NULL/misaligned");
+  size_t need = 0;
+  int rc = kmpar_workspace_size_batched(ctx, inst_host, count, dtype, &need);
+  if (rc) return rc;
+  for (int i = 0; i < count; ++i) {
+    const kmpar_instance& I = inst_host[i];
+    if ((rc = check_common(ctx, I.X, I.row_scale, dtype, I.n, I.d))) return rc;
+    if (!I.centers || !aligned16(I.centers))
+      return set_err(ctx, KMPAR_E_INVAL, "instance %d: centers NULL/misaligned", i);
+    if (I.stats && ((uintptr_t)I.stats & 7u))
+      return set_err(ctx, KMPAR_E_INVAL, "instance %d: stats misaligned", i);
+  }
+  if (!ws) return set_err(ctx, KMPAR_E_INVAL, "workspace is NULL");
+  if (ws_bytes < need)
+    return set_err(ctx, KMPAR_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  if ((rc = device_ready(ctx))) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  if (traces_dev && ((uintptr_t)traces_dev & 7u))
+    return set_err(ctx, KMPAR_E_INVAL, "traces_dev misaligned");
+  KMPAR_HIP(launch_batched(dtype, inst_host, inst_dev, count, inst_host[0].rounds, seed, ws,
+                           traces_dev, (hipStream_t)stream));
   return KMPAR_OK;
 }
 

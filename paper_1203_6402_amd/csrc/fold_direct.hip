@@ -13,12 +13,6 @@
 
 namespace kmpar {
 
-int padded_dim(int d) {
-  if (d <= 64) return (d + 3) / 4 * 4;
-  if (d <= 128) return (d + 15) / 16 * 16;
-  return (d + 31) / 32 * 32;
-}
-
 // Rows longer than 128 are processed in two halves so a point never needs
 // more than 128 registers; the sum order over coordinates is the same.
 // One thread per point (or per listed point).  The early exits keep the

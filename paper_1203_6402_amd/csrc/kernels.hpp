@@ -9,7 +9,32 @@
 namespace kmpar {
 
 // Padded row length used for candidate / center rows (zeros past d).
-int padded_dim(int d);
+__host__ __device__ inline int padded_dim_hd(int d) {
+  if (d <= 64) return (d + 3) / 4 * 4;
+  if (d <= 128) return (d + 15) / 16 * 16;
+  return (d + 31) / 32 * 32;
+}
+inline int padded_dim(int d) { return padded_dim_hd(d); }
+
+// Integer square root (floor), identical on host and device.
+__host__ __device__ inline int64_t isqrt64(int64_t v) {
+  int64_t r = 0;
+  for (int64_t b = (int64_t)1 << 31; b > 0; b >>= 1)
+    if ((r + b) * (r + b) <= v) r += b;
+  return r;
+}
+
+// Per-round candidate capacity min(n, L + 12 isqrt(L) + 76), L = ceil(ell):
+// at least ell + 12 sqrt(ell) + 64, i.e. more than 12 standard deviations
+// above the expected ell kept points (Section 3.3).  Integer arithmetic, so
+// host planning and device kernels agree exactly.
+__host__ __device__ inline int64_t cap_round_hd(int64_t n, double ell) {
+  const double c = ceil(ell);
+  if (!(c < 4.0e18)) return n;
+  const int64_t L = (int64_t)c;
+  const int64_t cap = L + 12 * isqrt64(L) + 76;
+  return cap < n ? cap : n;
+}
 
 // Point tile of the direct-form distance pass and the other chunked passes.
 constexpr int kFoldBlock = 256;
@@ -117,5 +142,12 @@ struct LloydWs {
 constexpr int kScanTile = 4096;
 hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
                                const int* A, int k, float* C, const LloydWs& w, hipStream_t s);
+
+// Batched k-means|| (batched.hip).
+constexpr int kBatchMaxGroups = 24;
+size_t batched_workspace(const kmpar_instance* inst, int count, int rounds, int* G_out, int* dps);
+hipError_t launch_batched(kmpar_dtype dt, const kmpar_instance* ih, const kmpar_instance* idev,
+                          int count, int rounds, uint64_t seed, void* ws, const kmpar_trace* tr,
+                          hipStream_t s);
 
 }  // namespace kmpar

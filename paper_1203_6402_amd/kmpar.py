@@ -62,6 +62,8 @@ _lib.kmpar_assign.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32
                               _sz, _vp]
 _lib.lloyd_step.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _vp, _vp, _vp,
                             _sz, _vp]
+_lib.kmpar_workspace_size_batched.argtypes = [_vp, _vp, _i32, ctypes.c_int, ctypes.POINTER(_sz)]
+_lib.kmpar_init_batched.argtypes = [_vp, _vp, _vp, _i32, ctypes.c_int, _u64, _vp, _sz, _vp, _vp]
 _lib.kmpar_profile_enable.argtypes = [_vp, ctypes.c_int]
 _lib.kmpar_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i64),
                                     ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]
@@ -70,7 +72,13 @@ assert _lib.kmpar_sizeof_stats() == ctypes.sizeof(Stats), "kmpar_stats layout mi
 EXPORTED = ["kmpar_create", "kmpar_destroy", "kmpar_strerror", "kmpar_last_error",
             "kmpar_sizeof_stats", "kmpar_max_candidates", "kmpar_workspace_size", "kmpar_init",
             "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_profile_enable",
-            "kmpar_profile_read"]
+            "kmpar_profile_read", "kmpar_workspace_size_batched", "kmpar_init_batched"]
+
+# kmpar_instance (include/kmpar.h), 64 bytes.
+INSTANCE_DTYPE = np.dtype([("X", "<u8"), ("row_scale", "<u8"), ("centers", "<u8"), ("stats", "<u8"),
+                           ("n", "<i8"), ("d", "<i4"), ("k", "<i4"), ("ell", "<f8"),
+                           ("rounds", "<i4"), ("reserved", "<i4")])
+assert INSTANCE_DTYPE.itemsize == 64
 SLOT_FOLD_DIRECT, SLOT_SCREEN, SLOT_RESCAN = 0, 1, 2
 
 
@@ -230,6 +238,29 @@ class Context:
                                       ws.data_ptr(), ws.numel(), _stream(stream)), "kmpar_assign")
         return a, d2
 
+    def init_batched(self, Xs, ks, ells, rounds: int, seed: int = 0, row_scales=None,
+                     stream=None, check: bool = True, trace: bool = False):
+        """kmpar_init_batched: instance i uses Philox inst = i.  Returns
+        (list of k_i x d_i center tensors, list of stats dicts, list of traces
+        or None)."""
+        centers, offs, stats, keep, traces = _batched_impl(self, Xs, ks, ells, rounds, seed,
+                                                           row_scales, stream, trace)
+        self._batch_keep = keep                   # device tables live until the next call
+        views = [centers[offs[i]:offs[i] + int(ks[i]) * Xs[i].shape[1]].view(int(ks[i]),
+                                                                              Xs[i].shape[1])
+                 for i in range(len(Xs))]
+        if not check:
+            return views, stats, traces
+        ssz = ctypes.sizeof(Stats)
+        raw = stats.cpu()
+        st = [parse_stats(raw[i * ssz:(i + 1) * ssz], rounds) for i in range(len(Xs))]
+        if traces is not None:
+            for t, s_ in zip(traces, st):
+                t["cand_point"] = t["cand_point"][:s_["n_candidates"]]
+                t["cand_weight"] = t["cand_weight"][:s_["n_candidates"]]
+                t["center_cand"] = t["center_cand"][:s_["n_centers"]]
+        return [v[:s_["n_centers"]] for v, s_ in zip(views, st)], st, traces
+
     def lloyd_step(self, X, C, row_scale=None, want_assign=False, stream=None):
         """Updates C (k x d FP32, contiguous) in place; returns (assign|None, phi)."""
         dt = self._x(X, row_scale)
@@ -244,6 +275,54 @@ class Context:
                                     C.data_ptr(), k, _ptr(a), phi.data_ptr(), ws.data_ptr(),
                                     ws.numel(), _stream(stream)), "lloyd_step")
         return a, phi
+
+
+def _batched_impl(ctx, Xs, ks, ells, rounds, seed, row_scales, stream, trace=False):
+    count = len(Xs)
+    dev = Xs[0].device
+    dt = ctx._x(Xs[0], row_scales[0] if row_scales else None)
+    desc = np.zeros(count, dtype=INSTANCE_DTYPE)
+    offs = np.zeros(count + 1, dtype=np.int64)
+    for i, X in enumerate(Xs):      # each instance's centers start 16-byte aligned
+        offs[i + 1] = offs[i] + (int(ks[i]) * X.shape[1] + 3) // 4 * 4
+    centers = torch.empty(max(1, int(offs[-1])), dtype=torch.float32, device=dev)
+    ssz = ctypes.sizeof(Stats)
+    stats = torch.zeros(count * ssz, dtype=torch.uint8, device=dev)
+    for i, X in enumerate(Xs):
+        if ctx._x(X, row_scales[i] if row_scales else None) != dt:
+            raise ValueError("all instances must share one dtype")
+        desc[i]["X"] = X.data_ptr()
+        desc[i]["row_scale"] = row_scales[i].data_ptr() if row_scales else 0
+        desc[i]["centers"] = centers.data_ptr() + 4 * int(offs[i])
+        desc[i]["stats"] = stats.data_ptr() + i * ssz
+        desc[i]["n"], desc[i]["d"], desc[i]["k"] = X.shape[0], X.shape[1], int(ks[i])
+        desc[i]["ell"], desc[i]["rounds"] = float(ells[i]), int(rounds)
+    desc_dev = torch.from_numpy(desc.view(np.uint8).copy()).to(dev)
+    traces, tr_dev = None, None
+    if trace:
+        traces = []
+        tarr = np.zeros((count, 5), dtype=np.uint64)
+        for i, X in enumerate(Xs):
+            cap = max_candidates(X.shape[0], float(ells[i]), int(rounds))
+            i32 = dict(dtype=torch.int32, device=dev)
+            t = {"cand_point": torch.empty(cap, **i32), "cand_weight": torch.empty(cap, **i32),
+                 "center_cand": torch.full((int(ks[i]),), -1, **i32),
+                 "assign": torch.empty(X.shape[0], **i32),
+                 "d2": torch.empty(X.shape[0], dtype=torch.float32, device=dev)}
+            traces.append(t)
+            tarr[i] = [t[f].data_ptr() for f in ("cand_point", "cand_weight", "center_cand",
+                                                 "assign", "d2")]
+        tr_dev = torch.from_numpy(tarr.view(np.uint8).reshape(-1).copy()).to(dev)
+    out = _sz(0)
+    ctx._check(_lib.kmpar_workspace_size_batched(ctx._h, desc.ctypes.data, count, dt,
+                                                 ctypes.byref(out)), "kmpar_workspace_size_batched")
+    ws = ctx._workspace(int(out.value), dev)
+    ctx._check(_lib.kmpar_init_batched(ctx._h, desc.ctypes.data, desc_dev.data_ptr(), count, dt,
+                                       seed, ws.data_ptr(), ws.numel(),
+                                       tr_dev.data_ptr() if tr_dev is not None else None,
+                                       _stream(stream)),
+               "kmpar_init_batched")
+    return centers, offs, stats, (desc_dev, tr_dev), traces
 
 
 def parse_stats(st: torch.Tensor, rounds: int) -> dict:

@@ -111,3 +111,27 @@ def batch_instances(count: int, seed: int, n_lo: int = 2000, n_hi: int = 200000,
     d = rng.choice(np.asarray(dims), size=count)
     k = np.ceil(np.sqrt(n) / 2.0).astype(np.int64)
     return n, d, k
+
+
+def batch_gauss_mixture(ns, ds, ks, seed: int, R: float = 10.0, dtype=np.float32):
+    """One GaussMixture instance per (n, d, k): k true centers N(0, R I), n
+    unit-variance points (host, for small batches)."""
+    return [gauss_mixture(int(n), int(d), int(k), R, seed=seed * 1_000_003 + i, dtype=dtype)
+            for i, (n, d, k) in enumerate(zip(ns, ds, ks))]
+
+
+def batch_gauss_mixture_torch(ns, ds, ks, seed: int, device="cuda", R: float = 10.0,
+                              out_dtype=None):
+    """Device variant of ``batch_gauss_mixture`` for thousands of instances."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = []
+    for n, d, k in zip(ns, ds, ks):
+        n, d, k = int(n), int(d), int(k)
+        centers = torch.randn(k, d, generator=g, device=device) * math.sqrt(R)
+        lab = torch.randint(0, k, (n,), generator=g, device=device)
+        x = centers[lab] + torch.randn(n, d, generator=g, device=device)
+        out.append(x.to(out_dtype) if out_dtype is not None else x)
+    return out

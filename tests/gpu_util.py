@@ -60,14 +60,14 @@ def gpu_init(ctx, Xdev, k, ell, rounds, seed, row_scale=None):
     return r, tr
 
 
-def compare_init(X64, r, tr, k, ell, rounds, seed):
+def compare_init(X64, r, tr, k, ell, rounds, seed, inst=0):
     """Oracle replay of the GPU run; returns the oracle result after checking
     every part of the run against it."""
     d = X64.shape[1]
     st = r.stats
     follow = {"rounds": split_rounds(tr["cand_point"], st["round_count"]),
               "assign": tr["assign"], "picks": tr["center_cand"]}
-    o = O.kmeans_parallel_init(X64, k, ell, rounds, seed, follow=follow)
+    o = O.kmeans_parallel_init(X64, k, ell, rounds, seed, inst=inst, follow=follow)
     assert sum(o.bad.values()) == 0, (o.bad, o.flags)
     assert o.round_count == st["round_count"]
     assert np.array_equal(o.cand_point, tr["cand_point"])

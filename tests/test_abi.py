@@ -47,7 +47,11 @@ def test_strerror(K):
 
 
 def test_max_candidates(K):
-    assert K.max_candidates(10**6, 1000.0, 5) == 1 + 5 * math.ceil(1000 + 12 * math.sqrt(1000) + 64)
+    # capacity min(n, L + 12 isqrt(L) + 76), L = ceil(ell): >= ell + 12 sqrt(ell) + 64
+    assert K.max_candidates(10**6, 1000.0, 5) == 1 + 5 * (1000 + 12 * math.isqrt(1000) + 76)
+    assert K.max_candidates(10**6, 999.5, 1) == 1 + (1000 + 12 * math.isqrt(1000) + 76)
+    for ell in (1.0, 7.3, 250.0, 4000.0):
+        assert K.max_candidates(10**9, ell, 1) - 1 >= ell + 12 * math.sqrt(ell) + 64
     assert K.max_candidates(50, 1e12, 1) == 51              # capped at n per round
     assert K.max_candidates(50, 3.0, 0) == 1
     with pytest.raises(K.KmparError):
@@ -110,6 +114,29 @@ def test_assign_cost_lloyd_validation(K):
     assert L.lloyd_step(h, 16, None, K.F32, 100, 8, 32, 5, None, 12, 8192, 1 << 30, None) == K.E_INVAL
     assert L.lloyd_step(h, 16, None, K.F32, 100, 8, 32, 5, None, None, 8192, 1 << 30, None) == K.E_NODEVICE
     assert L.kmpar_last_error(h).decode() != ""
+
+
+def test_batched_validation(K):
+    import numpy as np
+    ctx = K.Context(None)
+    desc = np.zeros(3, dtype=K.INSTANCE_DTYPE)
+    for i in range(3):
+        desc[i]["X"], desc[i]["centers"] = 4096 * (i + 1), 8192 * (i + 1)
+        desc[i]["n"], desc[i]["d"], desc[i]["k"], desc[i]["ell"], desc[i]["rounds"] = 1000, 32, 10, 20.0, 5
+    out = ctypes.c_size_t(0)
+    L = K._lib
+    assert L.kmpar_workspace_size_batched(ctx._h, desc.ctypes.data, 3, K.F32, ctypes.byref(out)) == 0
+    assert out.value > 3 * 1000 * 8
+    assert L.kmpar_init_batched(ctx._h, desc.ctypes.data, 4096, 3, K.F32, 0, 64, out.value, None, None) == K.E_NODEVICE
+    assert L.kmpar_init_batched(ctx._h, desc.ctypes.data, 4096, 3, K.F32, 0, 64, 10, None, None) == K.E_WORKSPACE
+    bad = desc.copy(); bad[1]["rounds"] = 4          # rounds must agree across the batch
+    assert L.kmpar_workspace_size_batched(ctx._h, bad.ctypes.data, 3, K.F32, ctypes.byref(out)) == K.E_INVAL
+    bad = desc.copy(); bad[2]["k"] = 1001             # k > n
+    assert L.kmpar_workspace_size_batched(ctx._h, bad.ctypes.data, 3, K.F32, ctypes.byref(out)) == K.E_INVAL
+    bad = desc.copy(); bad[0]["X"] = 4100             # misaligned X
+    assert L.kmpar_init_batched(ctx._h, bad.ctypes.data, 4096, 3, K.F32, 0, 64, 1 << 40, None, None) == K.E_INVAL
+    assert L.kmpar_init_batched(ctx._h, desc.ctypes.data, 4100, 3, K.F32, 0, 64, 1 << 40, None, None) == K.E_INVAL
+    assert L.kmpar_workspace_size_batched(ctx._h, desc.ctypes.data, 0, K.F32, ctypes.byref(out)) == K.E_INVAL
 
 
 def test_create_rejects_bad_arguments(K):

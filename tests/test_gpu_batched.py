@@ -1,0 +1,66 @@
+"""Batched k-means|| (many independent instances in grouped launches): each
+instance is replayed by the FP64 oracle with its own Philox instance index."""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1203_6402_amd import synth
+from tests.gpu_util import compare_init, decoded_fp64, to_bf16_bits
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1203_6402_amd import kmpar
+    assert torch.cuda.is_available()
+    return kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _replay_all(Xs64, cs, sts, trs, ks, ells, rounds, seed):
+    for i, X64 in enumerate(Xs64):
+        st = sts[i]
+        assert st["status"] == 0, (i, st)
+        tr = {key: v.cpu().numpy() for key, v in trs[i].items()}
+        r = SimpleNamespace(stats=st, centers=cs[i])
+        compare_init(X64, r, tr, int(ks[i]), float(ells[i]), rounds, seed, inst=i)
+        assert tr["cand_weight"].sum() == X64.shape[0]
+
+
+def test_batched_f32_matches_oracle_per_instance(ctx):
+    ns, ds, ks = synth.batch_instances(48, seed=3, n_lo=500, n_hi=20000)
+    Xs = synth.batch_gauss_mixture(ns, ds, ks, seed=3)
+    ells = 2.0 * ks
+    cs, sts, trs = ctx.init_batched([_dev(X) for X in Xs], ks, ells, 5, seed=11, trace=True)
+    torch.cuda.synchronize()
+    _replay_all([X.astype(np.float64) for X in Xs], cs, sts, trs, ks, ells, 5, 11)
+
+
+def test_batched_bf16_and_ragged_dims(ctx):
+    ns = np.array([300, 4097, 999, 1, 2600])
+    ds = np.array([128, 42, 7, 5, 256])
+    ks = np.array([12, 30, 9, 1, 25])
+    Xb = [to_bf16_bits(X) for X in synth.batch_gauss_mixture(ns, ds, np.maximum(ks, 2), seed=5)]
+    ells = np.array([24.0, 60.0, 18.0, 3.0, 50.0])
+    cs, sts, trs = ctx.init_batched([_dev(X).view(torch.bfloat16) for X in Xb], ks, ells, 4,
+                                    seed=2, trace=True)
+    torch.cuda.synchronize()
+    _replay_all([decoded_fp64(X, "bf16") for X in Xb], cs, sts, trs, ks, ells, 4, 2)
+
+
+def test_batch_of_one_equals_single_instance(ctx):
+    X = synth.heavy_tailed(30011, 42, seed=4)
+    Xd = _dev(X)
+    single = ctx.init(Xd, k=60, ell=120.0, rounds=5, seed=9, trace=True)
+    cs, sts, trs = ctx.init_batched([Xd], [60], [120.0], 5, seed=9, trace=True)
+    torch.cuda.synchronize()
+    for key in ("cand_point", "cand_weight", "assign", "d2"):
+        assert torch.equal(single.trace[key], trs[0][key]), key
+    assert sts[0]["round_count"] == single.stats["round_count"]
+    assert sts[0]["phi"] == single.stats["phi"]
