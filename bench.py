@@ -86,6 +86,45 @@ def precision_compare(kmpar, synth, torch, seed, steps=2):
     return out
 
 
+def batched_bench(kmpar, synth, torch, seed, count, steps=2):
+    """Many independent instances in one kmpar_init_batched call: n_i
+    log-uniform in [2,000, 200,000], d_i uniform in {32, 64, 128},
+    k_i = ceil(sqrt(n_i)/2), GaussMixture data (R = 10), ell = 2k_i, r = 5;
+    FP32 and BF16 storage."""
+    import numpy as np
+    ns, ds, ks = synth.batch_instances(count, seed=seed)
+    ells = 2.0 * ks
+    log(f"batched: generating {count} instances, sum n = {int(ns.sum())}")
+    Xs = synth.batch_gauss_mixture_torch(ns, ds, ks, seed=seed, device="cuda:0")
+    out = {"workload": f"{count} independent GaussMixture instances (synthetic)",
+           "instances": count, "sum_n": int(ns.sum()), "mean_d": float(ds.mean()),
+           "k_range": [int(ks.min()), int(ks.max())], "rounds": 5}
+    ctx = kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
+    for name, conv in (("fp32", None), ("bf16", torch.bfloat16)):
+        Xv = Xs if conv is None else [X.to(conv) for X in Xs]
+        _, sts, _ = ctx.init_batched(Xv, ks, ells, 5, seed=seed)
+        bad = sum(1 for s_ in sts if s_["status"] != 0)
+        evals = float(sum(int(n) * s_["n_candidates"] for n, s_ in zip(ns, sts)))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ctx.init_batched(Xv, ks, ells, 5, seed=seed, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[f"{name}_ms"] = ms
+        out[f"{name}_evals_per_s"] = evals / (ms / 1e3)
+        out[f"{name}_instances_not_ok"] = bad
+        log(f"batched {name}: {ms:.1f} ms per batch, {evals / (ms / 1e3):.3e} evals/s, "
+            f"{bad} instances with a non-OK status")
+        if conv is not None:
+            del Xv
+    del Xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +141,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16-refined vs FP32-plain comparison on the precision workload")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 4,096-instance batched workload")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--recluster-path", type=int, default=0, choices=[0, 1, 2])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -120,6 +163,7 @@ def main():
     Xd = torch.from_numpy(X).to("cuda:0")
     mode = kmpar.MODE_REFINED if args.mode == "refined" else kmpar.MODE_PLAIN_FP32
     ctx = kmpar.Context(0, mode)
+    ctx.set_option(kmpar.OPT_RECLUSTER_PATH, args.recluster_path)
     stream = torch.cuda.current_stream()
 
     log(f"warmup {args.warmup}")
@@ -180,6 +224,10 @@ def main():
     if not args.no_precision:
         precision = precision_compare(kmpar, synth, torch, args.seed)
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_bench(kmpar, synth, torch, args.seed, args.batch_count)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline on {args.cpu_rows} rows")
@@ -194,7 +242,8 @@ def main():
                       "mode": args.mode, "n_candidates": ncand, "evals_per_step": evals,
                       "rescanned_points": rp.stats["n_rescanned"],
                       "parallelism": "single GPU"},
-           "roofline": roofline, "cpu_baseline": cpu, "precision": precision}
+           "roofline": roofline, "cpu_baseline": cpu, "precision": precision,
+           "batched": batched}
     print(json.dumps(out), flush=True)
 
 

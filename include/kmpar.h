@@ -94,6 +94,16 @@ typedef struct kmpar_trace {
   float* d2;            /* [n] D^2(x, C) after the last round (FP32)             */
 } kmpar_trace;
 
+/* Tuning options of a context. */
+typedef enum kmpar_option {
+  /* Step-8 recluster of kmpar_init: 0 = automatic, 1 = one workgroup
+   * (candidate E values in LDS, rows streamed), 2 = several workgroups with
+   * LDS-resident row slices and grid barriers.  All give the same picks up
+   * to FP64 summation order. */
+  KMPAR_OPT_RECLUSTER_PATH = 0
+} kmpar_option;
+int kmpar_set_option(kmpar_ctx* ctx, kmpar_option opt, int64_t value);
+
 /* Kernel timing for measurement: while enabled, every launch of a distance
  * kernel (the fold of Algorithm 2 steps 4-5 and of the assignment passes) is
  * bracketed by two hipEvents recorded on the call's stream.

@@ -30,6 +30,7 @@ struct kmpar_ctx {
   kmpar_mode mode = KMPAR_MODE_PLAIN_FP32;
   std::string err;
   bool prof = false;
+  int recl_path = 0;  // KMPAR_OPT_RECLUSTER_PATH
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
 };
@@ -86,6 +87,7 @@ struct InitLayout {
   int* scan_total;
   int* cand_point;
   float* Call;
+  float* CallT;
   int* w;
   double* rpart;
   float* prow;
@@ -125,6 +127,7 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.scan_total = c.take<int>(4);
   L.cand_point = c.take<int>(capT);
   L.Call = c.take<float>(capT * DP);
+  L.CallT = c.take<float>(capT * d);
   L.w = c.take<int>(capT);
   L.rpart = c.take<double>(2 * kReclMaxBlocks);
   L.prow = c.take<float>(2 * (size_t)DP);
@@ -357,6 +360,17 @@ void kmpar_destroy(kmpar_ctx* ctx) {
   delete ctx;
 }
 
+int kmpar_set_option(kmpar_ctx* ctx, kmpar_option opt, int64_t value) {
+  if (!ctx) return KMPAR_E_INVAL;
+  switch (opt) {
+    case KMPAR_OPT_RECLUSTER_PATH:
+      if (value < 0 || value > 2) return set_err(ctx, KMPAR_E_INVAL, "recluster path %lld", (long long)value);
+      ctx->recl_path = (int)value;
+      return KMPAR_OK;
+  }
+  return set_err(ctx, KMPAR_E_INVAL, "unknown option %d", (int)opt);
+}
+
 int kmpar_profile_enable(kmpar_ctx* ctx, int on) {
   if (!ctx) return KMPAR_E_INVAL;
   ctx->prof = on != 0;
@@ -487,7 +501,8 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
 
   // Steps 1-2: first center, D2 against it, psi.
   KMPAR_HIP(launch_first(N, seed, inst, L.cand_point, L.rs, st, s));
-  KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, 0, 1, L.Call, s));
+  KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, 0, 1, L.Call, L.CallT,
+                          capT, s));
   FoldArgs fa{};
   fa.X = X;
   fa.row_scale = row_scale;
@@ -521,7 +536,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
     KMPAR_HIP(launch_draw(L.D2, N, &st->phi[t - 1], ell, seed, t, inst, L.cnt, L.scan_total, L.rs,
                           cap_round, L.cand_point, st, s));
     KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, t, cap_round, L.Call,
-                            s));
+                            L.CallT, capT, s));
     fa.rs = L.rs + t;
     if (refined) {
       KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (cap_round + 15) / 16, L.norms, Apre, L.B,
@@ -537,9 +552,20 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   KMPAR_HIP(launch_hist(L.A, N, L.w, capT, s));
   // Step 8: weighted k-means++.
   int* picks = (trace && trace->center_cand) ? trace->center_cand : L.picks;
-  const int G = recluster_blocks(capT, DP, ctx->num_cu);
-  KMPAR_HIP(launch_recluster(L.Call, DP, capT, d, L.w, L.rs + rounds + 1, k, seed, inst, G, L.rpart,
-                             L.prow, L.bar, picks, centers, st, s));
+  // Automatic: several workgroups (measured faster for a single instance at
+  // the benchmark shapes: the one-workgroup pick loop is bound by its
+  // 1024-thread FP64 scan and barriers); one workgroup only on request.
+  bool one_wg = false;
+  if (ctx->recl_path == 1) one_wg = recluster_block_lds(capT, k) <= kReclBlockLdsMax;
+  if (ctx->recl_path == 2) one_wg = false;
+  if (one_wg) {
+    KMPAR_HIP(launch_recluster_block(L.CallT, capT, d, L.w, L.rs + rounds + 1, k, seed, inst,
+                                     picks, centers, st, s));
+  } else {
+    const int G = recluster_blocks(capT, DP, ctx->num_cu);
+    KMPAR_HIP(launch_recluster(L.Call, DP, capT, d, L.w, L.rs + rounds + 1, k, seed, inst, G,
+                               L.rpart, L.prow, L.bar, picks, centers, st, s));
+  }
   if (trace) {
     if (trace->cand_point) KMPAR_HIP(launch_copy_i32(L.cand_point, trace->cand_point, capT, s));
     if (trace->cand_weight) KMPAR_HIP(launch_copy_i32(L.w, trace->cand_weight, capT, s));

@@ -7,6 +7,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "recluster_block.hpp"
 
 namespace kmpar {
 
@@ -37,7 +38,7 @@ hipError_t launch_first(int n, uint64_t seed, uint64_t inst, int* cand_point, in
 // Call[id][DP] (read by the folds and the recluster), zero-padded past d.
 template <typename T>
 __global__ void k_gather(const T* X, const float* row_scale, int d, int DP, const int* cand_point,
-                         const int* rs, int t, float* Call) {
+                         const int* rs, int t, float* Call, float* CallT, int ldT) {
   const int id0 = rs[t];
   const int m = rs[t + 1] - id0;
   const int j = blockIdx.x;
@@ -48,25 +49,26 @@ __global__ void k_gather(const T* X, const float* row_scale, int d, int DP, cons
   for (int e = threadIdx.x; e < DP; e += blockDim.x) {
     const float v = (e < d) ? Elem<T>::get(X, (int64_t)p * d + e, sc) : 0.0f;
     Call[(int64_t)c * DP + e] = v;
+    if (CallT && e < d) CallT[(int64_t)e * ldT + c] = v;
   }
 }
 
 hipError_t launch_gather(kmpar_dtype dt, const void* X, const float* row_scale, int d, int DP,
                          const int* cand_point, const int* rs, int t, int cap_round, float* Call,
-                         hipStream_t s) {
+                         float* CallT, int ldT, hipStream_t s) {
   const dim3 grid(cap_round), block(64);
   switch (dt) {
     case KMPAR_F32:
       hipLaunchKernelGGL(k_gather<float>, grid, block, 0, s, (const float*)X, row_scale, d, DP,
-                         cand_point, rs, t, Call);
+                         cand_point, rs, t, Call, CallT, ldT);
       break;
     case KMPAR_BF16:
       hipLaunchKernelGGL(k_gather<bf16_t>, grid, block, 0, s, (const bf16_t*)X, row_scale, d, DP,
-                         cand_point, rs, t, Call);
+                         cand_point, rs, t, Call, CallT, ldT);
       break;
     case KMPAR_FP8_E4M3:
       hipLaunchKernelGGL(k_gather<fp8_t>, grid, block, 0, s, (const fp8_t*)X, row_scale, d, DP,
-                         cand_point, rs, t, Call);
+                         cand_point, rs, t, Call, CallT, ldT);
       break;
   }
   KMPAR_RET_LAST();
@@ -495,6 +497,30 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
     if (sh_failed) a.st->status = KMPAR_E_HIP;
     else if (made < a.k && a.st->status == KMPAR_OK) a.st->status = KMPAR_E_TOOFEW;
   }
+}
+
+// Single-instance recluster in one 1024-thread workgroup (no grid barriers).
+__global__ __launch_bounds__(1024) void k_recluster_block(const float* CallT, int ldT, int d,
+                                                          const int* w, const int* rs_end, int k,
+                                                          uint64_t seed, uint64_t inst, int* picks,
+                                                          float* centers, kmpar_stats* st,
+                                                          int cap_lds) {
+  extern __shared__ float lds[];
+  recluster_block<1024>(CallT, ldT, d, w, *rs_end, k, seed, inst, picks, centers, st, lds, cap_lds);
+}
+
+size_t recluster_block_lds(int capT, int k) { return (size_t)capT * 8 + (size_t)k * 8; }
+
+hipError_t launch_recluster_block(const float* CallT, int capT, int d, const int* w,
+                                  const int* rs_end, int k, uint64_t seed, uint64_t inst,
+                                  int* picks, float* centers, kmpar_stats* st, hipStream_t s) {
+  const size_t lds = recluster_block_lds(capT, k);
+  hipError_t e = hipFuncSetAttribute((const void*)k_recluster_block,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_recluster_block, dim3(1), dim3(1024), lds, s, CallT, capT, d, w, rs_end, k,
+                     seed, inst, picks, centers, st, capT);
+  KMPAR_RET_LAST();
 }
 
 int recluster_blocks(int capT, int DP, int num_cu) {

@@ -10,6 +10,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "recluster_block.hpp"
 
 namespace kmpar {
 
@@ -22,7 +23,8 @@ __host__ __device__ inline int64_t al256(int64_t v) { return (v + 255) / 256 * 2
 
 // Sub-buffers of one instance's workspace region (byte offsets).
 struct Region {
-  int64_t D2, A, phi_part, cnt, rs, tot, cand, Call, w, picks, st, bytes;
+  int64_t D2, A, phi_part, cnt, rs, tot, cand, Call, CallT, w, picks, st, bytes;
+  int64_t capT;
 };
 
 __host__ __device__ inline Region region_of(int64_t n, int d, int k, double ell, int rounds) {
@@ -38,6 +40,8 @@ __host__ __device__ inline Region region_of(int64_t n, int d, int k, double ell,
   r.tot = o;      o = al256(o + 16);
   r.cand = o;     o = al256(o + 4 * capT);
   r.Call = o;     o = al256(o + 4 * capT * DP);
+  r.CallT = o;    o = al256(o + 4 * capT * DP);
+  r.capT = capT;
   r.w = o;        o = al256(o + 4 * capT);
   r.picks = o;    o = al256(o + 4 * k);
   r.st = o;       o = al256(o + (int64_t)sizeof(kmpar_stats));
@@ -198,12 +202,16 @@ __global__ __launch_bounds__(256) void kb_gather(const kmpar_instance* inst, int
   const int id0 = rs[t], m = rs[t + 1] - id0;
   const int* cand = v.at<int>(v.r.cand);
   float* Call = v.at<float>(v.r.Call);
+  float* CallT = v.at<float>(v.r.CallT);
+  const int64_t ldT = v.r.capT;
   const T* X = static_cast<const T*>(v.I->X);
   for (int idx = threadIdx.x; idx < m * DP; idx += 256) {
     const int j = idx / DP, e = idx - j * DP;
     const int pt = cand[id0 + j];
-    Call[(int64_t)(id0 + j) * DP + e] =
+    const float x =
         e < d ? Elem<T>::get(X, (int64_t)pt * d + e, row_scale_of<T>(v.I->row_scale, pt)) : 0.0f;
+    Call[(int64_t)(id0 + j) * DP + e] = x;
+    CallT[(int64_t)e * ldT + id0 + j] = x;
   }
 }
 
@@ -432,133 +440,16 @@ __global__ __launch_bounds__(256) void kb_hist(const kmpar_instance* inst, int c
 }
 
 // --------------------------------------------------------------- recluster
-// Weighted k-means++ for one instance per workgroup (same draws and order as
-// the single-instance recluster).  E_j and the nearest pick a_j live in LDS.
-// A candidate's row is read only when the new pick can improve it: with
-// D_pa = ||c_pick - c_a(j)||^2, the triangle inequality gives
-// ||c_j - c_pick|| >= sqrt(D_pa) - sqrt(E_j), so D_pa > 4 E_j (1 + eps)
-// implies ||c_j - c_pick||^2 > E_j and E_j cannot change (eps covers the
-// FP32 rounding of both sides).
 __global__ __launch_bounds__(kBRecl) void kb_recluster(const kmpar_instance* inst, int rounds,
                                                        PlanPtrs p, uint64_t seed, int cap_lds) {
   extern __shared__ float lds[];
-  __shared__ double shd[kBRecl / kWave + 1];
-  __shared__ long long shl[kBRecl / kWave + 1];
-  __shared__ double bounds[kBRecl + 1];
-  __shared__ float cp[256];
-  __shared__ int pick_sh;
   const int ii = blockIdx.x;
   const BView v = bview(inst, ii, p, rounds);
-  const int d = v.I->d, DP = padded_dim_hd(d), k = v.I->k;
-  const int m = v.at<int>(v.r.rs)[rounds + 1];
-  const float* Call = v.at<float>(v.r.Call);
-  const int* w = v.at<int>(v.r.w);
-  int* picks = v.at<int>(v.r.picks);  // written once per pick, never read back
-  kmpar_stats* st = v.at<kmpar_stats>(v.r.st);
-  float* E = lds;                                         // [cap_lds]
-  int* near = reinterpret_cast<int*>(lds + cap_lds);      // [cap_lds] index into picks
-  float* pd = reinterpret_cast<float*>(near + cap_lds);   // [k] D_pa of the current pick
-  int* pk = reinterpret_cast<int*>(pd + k);                // [k] picks so far (LDS copy)
-  const float eps = 8.0f * (float)(d + 2) * 0x1.0p-24f;
-  const int tid = threadIdx.x;
-  const int R = (m + kBRecl - 1) / kBRecl;
-  const int lo = min(m, tid * R), hi = min(m, lo + R);
-  int made = 0;
-  for (int s = 0; s < k; ++s) {
-    const double u = philox_uniform(seed, kTagRecluster, (uint64_t)s, 0, (uint64_t)ii);
-    if (tid == 0) pick_sh = 0x7fffffff;
-    double T;
-    if (s == 0) {
-      long long loc = 0;
-      for (int j = lo; j < hi; ++j) loc += w[j];
-      long long tot;
-      const long long ex = block_excl_scan<long long, kBRecl>(loc, shl, &tot);
-      bounds[tid] = (double)ex;
-      if (tid == 0) bounds[kBRecl] = (double)tot;
-      T = (double)tot;
-    } else {
-      double loc = 0.0;
-      for (int j = lo; j < hi; ++j) loc += (double)w[j] * (double)E[j];
-      double tot;
-      const double ex = block_excl_scan<double, kBRecl>(loc, shd, &tot);
-      bounds[tid] = ex;
-      if (tid == 0) bounds[kBRecl] = tot;
-      T = tot;
-    }
-    __syncthreads();
-    if (!(T > 0.0)) break;
-    const double thr = u * T;
-    if (bounds[tid] <= thr && thr < bounds[tid + 1]) {
-      double run = bounds[tid];
-      int pick = -1, last = -1;
-      for (int j = lo; j < hi; ++j) {
-        const double vv = (s == 0) ? (double)w[j] : (double)w[j] * (double)E[j];
-        run += vv;
-        if (vv > 0.0) last = j;
-        if (vv > 0.0 && run > thr) {
-          pick = j;
-          break;
-        }
-      }
-      atomicMin(&pick_sh, pick >= 0 ? pick : (last >= 0 ? last : 0x7fffffff));
-    }
-    __syncthreads();
-    if (pick_sh == 0x7fffffff) {
-      if (tid == 0) {
-        pick_sh = -1;
-        for (int j = m - 1; j >= 0; --j) {
-          const double vv = (s == 0) ? (double)w[j] : (double)w[j] * (double)E[j];
-          if (vv > 0.0) {
-            pick_sh = j;
-            break;
-          }
-        }
-      }
-      __syncthreads();
-    }
-    const int pick = pick_sh;
-    if (pick < 0) break;
-    for (int e = tid; e < DP; e += kBRecl) {
-      const float x = Call[(int64_t)pick * DP + e];
-      cp[e] = x;
-      if (e < d) v.I->centers[(int64_t)s * d + e] = x;
-    }
-    if (tid == 0) {
-      picks[s] = pick;
-      pk[s] = pick;
-    }
-    __syncthreads();
-    // D_pa for every earlier pick a (distance of the new pick to pick a)
-    for (int q = tid; q < s; q += kBRecl) {
-      const float* cr = Call + (int64_t)pk[q] * DP;
-      float acc = 0.0f;
-      for (int e = 0; e < d; ++e) {
-        const float t = cr[e] - cp[e];
-        acc = fmaf(t, t, acc);
-      }
-      pd[q] = acc;
-    }
-    __syncthreads();
-    for (int j = tid; j < m; j += kBRecl) {
-      if (s > 0 && pd[near[j]] > 4.0f * E[j] * (1.0f + eps)) continue;
-      const float* cr = Call + (int64_t)j * DP;
-      float acc = 0.0f;
-      for (int e = 0; e < d; ++e) {
-        const float t = cr[e] - cp[e];
-        acc = fmaf(t, t, acc);
-      }
-      if (s == 0 || acc < E[j]) {
-        E[j] = acc;
-        near[j] = s;
-      }
-    }
-    __syncthreads();
-    made = s + 1;
-  }
-  if (tid == 0) {
-    st->n_centers = made;
-    if (made < k && st->status == KMPAR_OK) st->status = KMPAR_E_TOOFEW;
-  }
+  const int d = v.I->d;
+  recluster_block<kBRecl>(v.at<const float>(v.r.CallT), (int)v.r.capT, d, v.at<const int>(v.r.w),
+                          v.at<int>(v.r.rs)[rounds + 1], v.I->k, seed, (uint64_t)ii,
+                          v.at<int>(v.r.picks), v.I->centers, v.at<kmpar_stats>(v.r.st), lds,
+                          cap_lds);
 }
 
 // Optional per-instance trace copies (one workgroup per instance).

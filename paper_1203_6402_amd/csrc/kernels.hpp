@@ -111,7 +111,7 @@ hipError_t launch_first(int n, uint64_t seed, uint64_t inst, int* cand_point, in
                         kmpar_stats* st, hipStream_t s);
 hipError_t launch_gather(kmpar_dtype dt, const void* X, const float* row_scale, int d, int DP,
                          const int* cand_point, const int* rs, int t, int cap_round, float* Call,
-                         hipStream_t s);
+                         float* CallT, int ldT, hipStream_t s);
 hipError_t launch_phi(const float* D2, int n, double* part, double* out, hipStream_t s);
 hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, uint64_t seed, int t,
                        uint64_t inst, int* cnt, int* scan_total, int* rs, int cap_round,
@@ -119,6 +119,12 @@ hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, ui
 hipError_t launch_finish_rounds(const int* rs, int rounds, kmpar_stats* st, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s);
 hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s);
+// Step-8 recluster in one workgroup when E and the nearest-pick ids fit LDS.
+constexpr size_t kReclBlockLdsMax = 140 * 1024;
+size_t recluster_block_lds(int capT, int k);
+hipError_t launch_recluster_block(const float* CallT, int capT, int d, const int* w,
+                                  const int* rs_end, int k, uint64_t seed, uint64_t inst,
+                                  int* picks, float* centers, kmpar_stats* st, hipStream_t s);
 // Step-8 recluster over G workgroups (see aux_kernels.hip).
 int recluster_blocks(int capT, int DP, int num_cu);
 size_t recluster_lds(int capT, int DP, int G);

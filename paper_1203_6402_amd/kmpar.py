@@ -64,6 +64,7 @@ _lib.lloyd_step.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, 
                             _sz, _vp]
 _lib.kmpar_workspace_size_batched.argtypes = [_vp, _vp, _i32, ctypes.c_int, ctypes.POINTER(_sz)]
 _lib.kmpar_init_batched.argtypes = [_vp, _vp, _vp, _i32, ctypes.c_int, _u64, _vp, _sz, _vp, _vp]
+_lib.kmpar_set_option.argtypes = [_vp, ctypes.c_int, _i64]
 _lib.kmpar_profile_enable.argtypes = [_vp, ctypes.c_int]
 _lib.kmpar_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i64),
                                     ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]
@@ -72,7 +73,9 @@ assert _lib.kmpar_sizeof_stats() == ctypes.sizeof(Stats), "kmpar_stats layout mi
 EXPORTED = ["kmpar_create", "kmpar_destroy", "kmpar_strerror", "kmpar_last_error",
             "kmpar_sizeof_stats", "kmpar_max_candidates", "kmpar_workspace_size", "kmpar_init",
             "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_profile_enable",
-            "kmpar_profile_read", "kmpar_workspace_size_batched", "kmpar_init_batched"]
+            "kmpar_profile_read", "kmpar_workspace_size_batched", "kmpar_init_batched",
+            "kmpar_set_option"]
+OPT_RECLUSTER_PATH = 0
 
 # kmpar_instance (include/kmpar.h), 64 bytes.
 INSTANCE_DTYPE = np.dtype([("X", "<u8"), ("row_scale", "<u8"), ("centers", "<u8"), ("stats", "<u8"),
@@ -167,6 +170,9 @@ class Context:
         if X.dim() != 2:
             raise ValueError("X must be 2-D")
         return dtype_code(X, row_scale)
+
+    def set_option(self, opt: int, value: int):
+        self._check(_lib.kmpar_set_option(self._h, opt, int(value)), "kmpar_set_option")
 
     def profile(self, on: bool = True):
         self._check(_lib.kmpar_profile_enable(self._h, 1 if on else 0), "kmpar_profile_enable")

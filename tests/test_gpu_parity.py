@@ -160,3 +160,22 @@ def test_lloyd_empty_cluster_and_bf16(ctx):
     torch.cuda.synchronize()
     Co, _ = O.lloyd_update(X64, a.cpu().numpy(), C0.astype(np.float64))
     np.testing.assert_allclose(C.cpu().numpy(), Co.astype(np.float32), rtol=1e-6, atol=1e-6)
+
+
+def test_init_large_candidate_set_multiworkgroup_recluster(ctx):
+    # ell = 4000 over 5 rounds gives a candidate capacity above what one
+    # workgroup's LDS holds, so the recluster runs over several workgroups.
+    X = synth.gauss_mixture(60000, 8, 40, 10.0, seed=6)
+    r, tr = gpu_init(ctx, _dev(X), 40, 4000.0, 5, 8)
+    compare_init(X.astype(np.float64), r, tr, 40, 4000.0, 5, 8)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_recluster_paths_match_oracle(K, path):
+    # Both Step-8 implementations (one workgroup with pruned updates; several
+    # workgroups with grid barriers) replay against the oracle.
+    c = K.Context(0, K.MODE_PLAIN_FP32)
+    c.set_option(K.OPT_RECLUSTER_PATH, path)
+    X = synth.heavy_tailed(30000, 42, seed=21)
+    r, tr = gpu_init(c, _dev(X), 100, 200.0, 5, 4)
+    compare_init(X.astype(np.float64), r, tr, 100, 200.0, 5, 4)
