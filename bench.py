@@ -190,6 +190,25 @@ def main():
     value = evals / (ms / 1e3)
     log(f"{ms:.3f} ms/step, |C|={ncand}, {value:.3e} evals/s")
 
+    # The same step replayed from a HIP graph (launch overhead removed).
+    graph_ms = None
+    try:
+        cap = kmpar.CapturedInit(ctx, Xd, k, ell, rounds, args.seed)
+        cap.replay()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record()                 # replay() launches on the current stream
+        for _ in range(args.steps):
+            cap.replay()
+        g1.record()
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1) / max(1, args.steps)
+        assert torch.equal(cap.centers, r.centers[:k]) or stats["n_centers"] < k
+        log(f"graph replay: {graph_ms:.3f} ms/step")
+        del cap
+    except Exception as exc:  # reported, not fatal: the eager number stands
+        log(f"graph capture unavailable: {exc!r}")
+
     # Dominant kernel: the distance pass (direct-form fold in PLAIN mode, the
     # MFMA screen in REFINED mode), timed live with HIP events on the stream
     # it runs on, over one further step.
@@ -241,6 +260,7 @@ def main():
                       "n": n, "d": d, "k": k, "ell": ell, "rounds": rounds,
                       "mode": args.mode, "n_candidates": ncand, "evals_per_step": evals,
                       "rescanned_points": rp.stats["n_rescanned"],
+                      "graph_replay_ms_per_step": graph_ms,
                       "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu, "precision": precision,
            "batched": batched}

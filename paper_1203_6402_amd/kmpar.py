@@ -283,6 +283,31 @@ class Context:
         return a, phi
 
 
+class CapturedInit:
+    """kmpar_init captured once into a HIP graph (torch.cuda.CUDAGraph) and
+    replayed; every replay rewrites `centers` and the raw stats record."""
+
+    def __init__(self, ctx, X, k, ell, rounds, seed, row_scale=None):
+        ctx.init(X, k=k, ell=ell, rounds=rounds, seed=seed, row_scale=row_scale)  # sizes the workspace
+        torch.cuda.synchronize()
+        self.rounds = rounds
+        self.graph = torch.cuda.CUDAGraph()
+        self.stream = torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            with torch.cuda.graph(self.graph, stream=self.stream):
+                r = ctx.init(X, k=k, ell=ell, rounds=rounds, seed=seed, row_scale=row_scale,
+                             stream=self.stream, check=False)
+        self.centers = r.centers
+        self.stats_raw = r.stats["_raw"]
+        self._keep = (ctx, X, row_scale)
+
+    def replay(self):
+        self.graph.replay()
+
+    def stats(self) -> dict:
+        return parse_stats(self.stats_raw, self.rounds)
+
+
 def _batched_impl(ctx, Xs, ks, ells, rounds, seed, row_scales, stream, trace=False):
     count = len(Xs)
     dev = Xs[0].device
