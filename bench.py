@@ -125,6 +125,41 @@ def batched_bench(kmpar, synth, torch, seed, count, steps=2):
     return out
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_screen_c1.json")
+SCREEN_SRC = os.path.join(ROOT, "paper_1203_6402_amd", "csrc", "screen_mfma.hip")
+
+
+def pmc_probe(kmpar, synth, torch, args):
+    """Counter-collection workload: a plain 1 GiB device copy of known size
+    (calibrates FETCH_SIZE / WRITE_SIZE), then one REFINED step."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    X = synth.heavy_tailed(args.n, args.d, seed=args.seed)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    ctx = kmpar.Context(0, kmpar.MODE_REFINED)
+    ctx.init(Xd, k=args.k, ell=args.ell_mult * args.k, rounds=args.rounds, seed=args.seed)
+    torch.cuda.synchronize()
+    log("pmc probe done")
+
+
+def screen_traffic():
+    """HBM bytes per k_screen launch from the committed counter summary, or
+    None when the summary is missing or the kernel source changed since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        with open(SCREEN_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if t.get("source_sha256") != sha:
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +180,8 @@ def main():
                     help="skip the 4,096-instance batched workload")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--recluster-path", type=int, default=0, choices=[0, 1, 2])
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run only a 1 GiB copy (counter calibration) and one step, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -158,6 +195,9 @@ def main():
 
     n, d, k, rounds = args.n, args.d, args.k, args.rounds
     ell = args.ell_mult * k
+    if args.pmc_probe:
+        pmc_probe(kmpar, synth, torch, args)
+        return
     log(f"generating heavy-tailed input n={n} d={d}")
     X = synth.heavy_tailed(n, d, seed=args.seed)
     Xd = torch.from_numpy(X).to("cuda:0")
@@ -231,8 +271,9 @@ def main():
         bound, peak = "mfma", PEAK_BF16_MFMA_TFLOPS
     else:
         bound, peak = "alu", PEAK_FP32_VECTOR_TFLOPS
+    traffic = screen_traffic() if dom == "k_screen" else None
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                 "launches": prof["launches"], "avg_launch_us": dur_per_launch * 1e6,
                 "flops_per_launch": flops_per_launch,
                 "distance_kernels_ms": {nm: p["ms"] for nm, p in slots.items() if p["launches"]}}
