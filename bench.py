@@ -43,7 +43,7 @@ def cpu_baseline(X, k, ell, rounds, seed, rows):
     dt = time.perf_counter() - t0
     evals = rows * len(r.cand_point)
     return {"value": evals / dt, "unit": UNIT, "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"oracle kmeans_parallel_init on the first {rows} rows of the same input "
+            "sample": f"oracle kmeans_parallel_init on rows [0, {rows}) of the same input "
                       f"(k={k}, ell={ell:g}, r={rounds}); {evals:.3e} evals in {dt:.1f} s"}
 
 
@@ -172,7 +172,8 @@ def main():
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", choices=["plain", "refined"], default="refined")
-    ap.add_argument("--cpu-rows", type=int, default=2_000_000)
+    ap.add_argument("--cpu-rows", type=int, default=0,
+                    help="rows of the input the oracle baseline runs on (0: all of them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16-refined vs FP32-plain comparison on the precision workload")
@@ -290,8 +291,9 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"cpu baseline on {args.cpu_rows} rows")
-        cpu = cpu_baseline(X, k, ell, rounds, args.seed, args.cpu_rows)
+        rows = args.cpu_rows if 0 < args.cpu_rows < n else n
+        log(f"cpu baseline on {rows} rows")
+        cpu = cpu_baseline(X, k, ell, rounds, args.seed, rows)
         log(f"cpu baseline {cpu['value']:.3e} evals/s on {cpu['cores']} threads")
 
     out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,

@@ -89,9 +89,9 @@ struct InitLayout {
   float* Call;
   float* CallT;
   int* w;
-  double* rpart;
-  float* prow;
-  unsigned* bar;
+  double* rpart;  // recluster partial slots [k][G]
+  double* udraw;  // recluster draws [k]
+  float* prow;    // recluster row slots [k][DP]
   int* picks;
   kmpar_stats* st;
   float* norms;
@@ -129,9 +129,12 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.Call = c.take<float>(capT * DP);
   L.CallT = c.take<float>(capT * d);
   L.w = c.take<int>(capT);
-  L.rpart = c.take<double>(2 * kReclMaxBlocks);
-  L.prow = c.take<float>(2 * (size_t)DP);
-  L.bar = c.take<unsigned>(4);
+  // one partial per (pick, block) and one row per pick: the recluster never
+  // reuses a slot (the grid at launch has at most this many blocks)
+  const int G_max = recluster_blocks((int)capT, DP, kReclMaxBlocks);
+  L.rpart = c.take<double>((size_t)k * G_max);
+  L.udraw = c.take<double>(k);
+  L.prow = c.take<float>((size_t)k * DP);
   L.picks = c.take<int>(k);
   L.st = c.take<kmpar_stats>(1);
   const int tiles = (int)((cap_round_of(n, ell) + 15) / 16);
@@ -564,7 +567,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   } else {
     const int G = recluster_blocks(capT, DP, ctx->num_cu);
     KMPAR_HIP(launch_recluster(L.Call, DP, capT, d, L.w, L.rs + rounds + 1, k, seed, inst, G,
-                               L.rpart, L.prow, L.bar, picks, centers, st, s));
+                               L.udraw, L.rpart, L.prow, picks, centers, st, s));
   }
   if (trace) {
     if (trace->cand_point) KMPAR_HIP(launch_copy_i32(L.cand_point, trace->cand_point, capT, s));

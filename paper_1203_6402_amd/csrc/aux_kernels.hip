@@ -5,6 +5,8 @@
 // results are bit-reproducible.
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "recluster_block.hpp"
@@ -285,38 +287,50 @@ hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s) {
 // Pick s takes the smallest j whose running sum (block order, then thread
 // runs, then candidate order) exceeds u*T, u = U(seed, RECL, (s, 0, inst)).
 //
-// Per pick: each block folds the previous pick into its E and publishes its
-// FP64 partial; grid barrier; every block derives the same block bounds from
-// the partials in block order; the block holding u*T finds the pick and
-// publishes it; grid barrier.  Barriers are agent-scope release/acquire
-// counters; a spin limit guarantees every wave exits (status KMPAR_E_HIP).
+// Per pick s, two hops between workgroups and no barrier counter:
+//  1. every block waits for the row of pick s-1 (polling the elements of its
+//     row slot), folds it into E, and publishes its FP64 partial in its
+//     partial slot of round s;
+//  2. every block polls the G partials of round s and derives T and the
+//     owner of u*T in block order; the owner finds the pick and publishes its
+//     row.
+// Every round has slots of its own, all-ones until written (partials are
+// finite, rows of finite inputs never have that bit pattern), so a slot is
+// written once and read by polling that word alone: agent-scope atomic
+// coherence is all the exchange needs, with no fences (on this chip an
+// agent-scope release or acquire writes back or invalidates the L2).  Every
+// wait has a spin limit, so every wave exits (status KMPAR_E_HIP).
 constexpr int kReclBlock = 256;
 constexpr unsigned kSpinLimit = 1u << 22;
 constexpr size_t kReclLdsBudget = 120 * 1024;
+constexpr unsigned long long kEmpty64 = ~0ull;
+constexpr unsigned kEmpty32 = ~0u;
 
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned target, int* failed) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) {
-        *failed = 1;
-        break;
-      }
+__device__ __forceinline__ unsigned long long poll64(const double* p, int* failed) {
+  const auto* q = reinterpret_cast<const unsigned long long*>(p);
+  unsigned long long v;
+  unsigned spins = 0;
+  while ((v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kEmpty64) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      *failed = 1;
+      break;
     }
   }
-  __syncthreads();
+  return v;
 }
-
-__device__ __forceinline__ void store_f64(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_f64(const double* p) {
-  return __longlong_as_double((long long)__hip_atomic_load(
-      reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+__device__ __forceinline__ unsigned poll32(const float* p, int* failed) {
+  const auto* q = reinterpret_cast<const unsigned*>(p);
+  unsigned v;
+  unsigned spins = 0;
+  while ((v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kEmpty32) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      *failed = 1;
+      break;
+    }
+  }
+  return v;
 }
 
 struct ReclArgs {
@@ -329,137 +343,191 @@ struct ReclArgs {
   uint64_t seed;
   uint64_t inst;
   int slice_cap;       // LDS slice capacity (candidates per block)
-  double* part;        // [2][G] block partials
-  float* prow;         // [2][DP] row of the latest pick, published through memory
-  unsigned* bar;       // barrier counter, zero on entry
+  const double* u;     // [k] the draws U(seed, RECL, (s, 0, inst))
+  double* part;        // [k][G] partial slots, all-ones on entry
+  float* prow;         // [k][DP] row slots of the picks, all-ones on entry
   int* picks;          // [k] output: candidate ids
   float* centers;      // [k][d] output rows
   kmpar_stats* st;
 };
 
+// The recluster's draws, one thread each, ahead of the sequential picks.
+__global__ void k_recl_draws(uint64_t seed, uint64_t inst, int k, double* u) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < k) u[s] = philox_uniform(seed, kTagRecluster, (uint64_t)s, 0, inst);
+}
+
 __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
-  extern __shared__ float lds[];
-  __shared__ double shd[kReclBlock / kWave + 1];
-  __shared__ double runb[kReclBlock + 1];
-  __shared__ double blockb[2];
+  extern __shared__ float4 lds4[];  // 16-byte aligned: cp is read as float4
+  float* lds = reinterpret_cast<float*>(lds4);
+  __shared__ double wtot[kReclBlock / kWave];
   __shared__ double gpart[kReclMaxBlocks];
-  __shared__ double sh_T;
+  __shared__ double sh_u, sh_base, sh_top;
   __shared__ int sh_pick, sh_owner, sh_failed, sh_stop;
+  constexpr int NW = kReclBlock / kWave;
   const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x, DP = a.DP, d = a.d;
+  const int lane = tid % kWave, wv = tid / kWave;
+  const int DL = DP + 1;  // odd LDS row stride: lanes reading different rows miss each other's banks
   const int m = *a.rs_end;
   const int lo = (int)((int64_t)b * m / G), hi = (int)((int64_t)(b + 1) * m / G);
   const int ns = hi - lo;
-  float* rows = lds;                                   // [slice_cap][DP]
-  float* E = rows + (size_t)a.slice_cap * DP;          // [slice_cap]
+  float* cp = lds;                                     // [DP] row of the latest pick
+  float* rows = cp + DP;                               // [slice_cap][DL]
+  float* E = rows + (size_t)a.slice_cap * DL;          // [slice_cap]
   int* wl = reinterpret_cast<int*>(E + a.slice_cap);   // [slice_cap]
-  float* cp = reinterpret_cast<float*>(wl + a.slice_cap);  // [DP]
   if (tid == 0) {
     sh_failed = 0;
     sh_stop = 0;
   }
-  for (int idx = tid; idx < ns * DP; idx += kReclBlock) rows[idx] = a.Call[(int64_t)lo * DP + idx];
+  for (int idx = tid; idx < ns * DP; idx += kReclBlock) {
+    const int j = idx / DP, e = idx - j * DP;
+    rows[j * DL + e] = a.Call[(int64_t)lo * DP + idx];
+  }
   for (int j = tid; j < ns; j += kReclBlock) wl[j] = a.w[lo + j];
-  __syncthreads();
-  // contiguous thread runs inside the slice, for the running sums
+  // each thread owns a contiguous run of the slice (one candidate when the
+  // slice fits the block), so thread order is candidate order
   const int R = (ns + kReclBlock - 1) / kReclBlock;
   const int rlo = min(ns, tid * R), rhi = min(ns, rlo + R);
-  unsigned nbar = 0;
   int made = 0;
   for (int s = 0; s < a.k; ++s) {
+    // the draw of this pick, loaded while the row of the previous one is in
+    // flight
+    const double u = a.u[s];
     if (s > 0) {
-      for (int e = tid; e < DP; e += kReclBlock)
-        cp[e] = __uint_as_float(__hip_atomic_load(
-            reinterpret_cast<const unsigned*>(&a.prow[((s - 1) & 1) * DP + e]), __ATOMIC_RELAXED,
-            __HIP_MEMORY_SCOPE_AGENT));
+      // hop 2 of round s-1: the row of pick s-1
+      if (tid < DP) cp[tid] = __uint_as_float(poll32(&a.prow[(int64_t)(s - 1) * DP + tid], &sh_failed));
       __syncthreads();
-      for (int j = tid; j < ns; j += kReclBlock) {
-        const float* r = rows + (size_t)j * DP;
+      if (sh_failed) break;
+      // Direct form over the DP-padded row (the padding adds fmaf(0, 0, acc)
+      // = acc), sixteen elements per step with the LDS reads issued first;
+      // reads past the row stay inside the block's LDS and are masked.
+      for (int j = rlo; j < rhi; ++j) {
+        const float* r = rows + (size_t)j * DL;
         float acc = 0.0f;
-        for (int e = 0; e < d; ++e) {
-          const float t = r[e] - cp[e];
-          acc = fmaf(t, t, acc);
+        for (int e0 = 0; e0 < DP; e0 += 16) {
+          float xr[16];
+          float4 c4[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) c4[q] = reinterpret_cast<const float4*>(cp + e0)[q];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) xr[q] = r[e0 + q];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const float cq = q % 4 == 0 ? c4[q / 4].x : q % 4 == 1 ? c4[q / 4].y
+                           : q % 4 == 2 ? c4[q / 4].z : c4[q / 4].w;
+            const float t = e0 + q < DP ? xr[q] - cq : 0.0f;
+            acc = fmaf(t, t, acc);
+          }
         }
         E[j] = (s == 1) ? acc : fminf(E[j], acc);
       }
-      __syncthreads();
     }
-    double loc = 0.0;
-    for (int j = rlo; j < rhi; ++j) loc += (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
-    double tot;
-    const double ex = block_excl_scan<double, kReclBlock>(loc, shd, &tot);
-    runb[tid] = ex;
-    if (tid == 0) {
-      runb[kReclBlock] = tot;
-      store_f64(&a.part[(s & 1) * G + b], tot);
-    }
-    grid_barrier(a.bar, (++nbar) * (unsigned)G, &sh_failed);
-    // every block: block bounds from the partials in block order (loaded in
-    // parallel, summed in order by one thread)
-    for (int q = tid; q < G; q += kReclBlock) gpart[q] = load_f64(&a.part[(s & 1) * G + q]);
+    // this thread's mass (candidate order), its exclusive prefix in the
+    // block and the block total, all in one fixed order
+    double v = 0.0;
+    for (int j = rlo; j < rhi; ++j) v += (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+    const double inc = wave_incl_scan(v);
+    double exw = __shfl_up(inc, 1, kWave);
+    if (lane == 0) exw = 0.0;
+    if (lane == kWave - 1) wtot[wv] = inc;
     __syncthreads();
-    if (tid == 0) {
-      double run = 0.0, lo_b = 0.0, hi_b = 0.0;
-      int owner = -1, last_pos = -1;
-      double T = 0.0;
-      for (int q = 0; q < G; ++q) T += gpart[q];
-      sh_T = T;
-      const double u = philox_uniform(a.seed, kTagRecluster, (uint64_t)s, 0, a.inst);
+    double wbase = 0.0, tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      if (q < wv) wbase += wtot[q];
+      tot += wtot[q];
+    }
+    const double ex = wbase + exw;
+    if (tid == 0)
+      __hip_atomic_store(reinterpret_cast<unsigned long long*>(&a.part[(int64_t)s * G + b]),
+                         (unsigned long long)__double_as_longlong(tot), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    // hop 1 of round s: all partials
+    for (int q = tid; q < G; q += kReclBlock)
+      gpart[q] = __longlong_as_double((long long)poll64(&a.part[(int64_t)s * G + q], &sh_failed));
+    __syncthreads();
+    if (wv == 0) {
+      // T and the owner of u*T in block order: lane l sums a contiguous run
+      // of partials, then a fixed-order wave scan (the same in every block)
+      const int RG = (G + kWave - 1) / kWave;
+      const int q0 = min(G, lane * RG), q1 = min(G, q0 + RG);
+      double ls = 0.0;
+      for (int q = q0; q < q1; ++q) ls += gpart[q];
+      const double linc = wave_incl_scan(ls);
+      const double T = __shfl(linc, kWave - 1, kWave);
+      double run = __shfl_up(linc, 1, kWave);
+      if (lane == 0) run = 0.0;
       const double thr = u * T;
-      for (int q = 0; q < G; ++q) {
-        const double v = gpart[q];
-        const double nxt = (q + 1 < G) ? run + v : T;
-        if (v > 0.0) last_pos = q;
-        if (owner < 0 && run <= thr && thr < nxt && v > 0.0) {
-          owner = q;
+      int own = -1, last_pos = -1;
+      double lo_b = 0.0, hi_b = 0.0;
+      for (int q = q0; q < q1; ++q) {
+        const double g = gpart[q];
+        const double nxt = (q + 1 < G) ? run + g : T;
+        if (g > 0.0) last_pos = q;
+        if (own < 0 && run <= thr && thr < nxt && g > 0.0) {
+          own = q;
           lo_b = run;
           hi_b = nxt;
         }
-        run += v;
+        run += g;
       }
-      if (!(T > 0.0) || sh_failed) {
-        sh_stop = 1;
-      } else if (owner < 0) {  // thr at or past the total by rounding
-        owner = last_pos;
-        lo_b = hi_b = INFINITY;
+      const uint64_t found = __ballot(own >= 0);
+      int last = last_pos;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) last = max(last, __shfl_xor(last, off, kWave));
+      if (found) {
+        const int fl = __ffsll((unsigned long long)found) - 1;
+        own = __shfl(own, fl, kWave);
+        lo_b = __shfl(lo_b, fl, kWave);
+        hi_b = __shfl(hi_b, fl, kWave);
       }
-      sh_owner = owner;
-      blockb[0] = lo_b;
-      blockb[1] = hi_b;
-      sh_pick = 0x7fffffff;
+      if (lane == 0) {
+        if (!(T > 0.0) || sh_failed) {
+          sh_stop = 1;
+        } else if (!found) {  // thr at or past the total by rounding
+          own = last;
+          lo_b = hi_b = INFINITY;
+        }
+        sh_owner = own;
+        sh_base = lo_b;
+        sh_top = hi_b;
+        sh_u = thr;
+        sh_pick = 0x7fffffff;
+      }
     }
     __syncthreads();
     if (sh_stop) break;
     if (sh_owner == b) {
-      const double u = philox_uniform(a.seed, kTagRecluster, (uint64_t)s, 0, a.inst);
-      const double thr = u * sh_T;
-      const double base = blockb[0];
-      const double b0 = base + runb[tid];
-      const double b1 = (tid + 1 < kReclBlock) ? base + runb[tid + 1] : blockb[1];
+      const double thr = sh_u, base = sh_base;
       if (isinf(base)) {
         // rounding fallback: the last candidate with positive mass
         if (tid == 0) {
           for (int j = ns - 1; j >= 0; --j) {
-            const double v = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
-            if (v > 0.0) {
+            const double g = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+            if (g > 0.0) {
               sh_pick = j;
               break;
             }
           }
         }
-      } else if (b0 <= thr && thr < b1) {
-        double run = b0;
-        int pick = -1, last = -1;
-        for (int j = rlo; j < rhi; ++j) {
-          const double v = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
-          run += v;
-          if (v > 0.0) last = j;
-          if (v > 0.0 && run > thr) {
-            pick = j;
-            break;
+      } else {
+        const double b0 = base + ex;
+        const double b1 = (tid + 1 < kReclBlock) ? b0 + v : sh_top;
+        if (v > 0.0 && b0 <= thr && thr < b1) {
+          double run = b0;
+          int pick = -1, last = -1;
+          for (int j = rlo; j < rhi; ++j) {
+            const double g = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+            run += g;
+            if (g > 0.0) last = j;
+            if (g > 0.0 && run > thr) {
+              pick = j;
+              break;
+            }
           }
+          if (pick < 0) pick = last;
+          if (pick >= 0) atomicMin(&sh_pick, pick);
         }
-        if (pick < 0) pick = last;
-        if (pick >= 0) atomicMin(&sh_pick, pick);
       }
       __syncthreads();
       if (sh_pick == 0x7fffffff) {
@@ -469,10 +537,10 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
           double run = base;
           int last = -1;
           for (int j = 0; j < ns; ++j) {
-            const double v = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
-            run += v;
-            if (v > 0.0) last = j;
-            if (v > 0.0 && run > thr) {
+            const double g = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+            run += g;
+            if (g > 0.0) last = j;
+            if (g > 0.0 && run > thr) {
               sh_pick = j;
               break;
             }
@@ -482,14 +550,14 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
         __syncthreads();
       }
       const int jl = sh_pick;
-      for (int e = tid; e < d; e += kReclBlock) a.centers[(int64_t)s * d + e] = rows[(size_t)jl * DP + e];
-      for (int e = tid; e < DP; e += kReclBlock)
-        __hip_atomic_store(reinterpret_cast<unsigned*>(&a.prow[(s & 1) * DP + e]),
-                           __float_as_uint(rows[(size_t)jl * DP + e]), __ATOMIC_RELAXED,
+      // hop 2 of round s: publish the row, then the outputs
+      if (tid < DP)
+        __hip_atomic_store(reinterpret_cast<unsigned*>(&a.prow[(int64_t)s * DP + tid]),
+                           __float_as_uint(rows[(size_t)jl * DL + tid]), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+      for (int e = tid; e < d; e += kReclBlock) a.centers[(int64_t)s * d + e] = rows[(size_t)jl * DL + e];
       if (tid == 0) a.picks[s] = lo + jl;
     }
-    grid_barrier(a.bar, (++nbar) * (unsigned)G, &sh_failed);
     made = s + 1;
   }
   if (b == 0 && tid == 0) {
@@ -524,12 +592,12 @@ hipError_t launch_recluster_block(const float* CallT, int capT, int d, const int
 }
 
 int recluster_blocks(int capT, int DP, int num_cu) {
-  // Slices of about 512 candidates (a grid barrier costs ~0.8 us at 8-16
-  // workgroups and grows with their number); each slice must fit the LDS budget.
-  const size_t per = (size_t)DP * 4 + 8;
-  int G = (capT + 511) / 512;
-  const int min_g = (int)((capT * per + kReclLdsBudget - 1) / kReclLdsBudget);
-  if (G < min_g) G = min_g;
+  // Slices of at most one candidate per thread (the per-pick work inside a
+  // block is then one row fold and one scan step), more when the LDS budget
+  // or the CU count binds; every block must be resident at once.
+  const size_t per = (size_t)(DP + 1) * 4 + 8;
+  const int fit = (int)std::min<size_t>(kReclBlock, kReclLdsBudget / per);
+  int G = (capT + fit - 1) / fit;
   if (G > num_cu) G = num_cu;
   if (G > kReclMaxBlocks) G = kReclMaxBlocks;
   if (G < 1) G = 1;
@@ -538,14 +606,19 @@ int recluster_blocks(int capT, int DP, int num_cu) {
 
 size_t recluster_lds(int capT, int DP, int G) {
   const int slice = (capT + G - 1) / G + 1;
-  return (size_t)slice * ((size_t)DP * 4 + 8) + (size_t)DP * 4;
+  return (size_t)slice * ((size_t)(DP + 1) * 4 + 8) + (size_t)DP * 4;
 }
 
 hipError_t launch_recluster(const float* Call, int DP, int capT, int d, const int* w,
                             const int* rs_end, int k, uint64_t seed, uint64_t inst, int G,
-                            double* part, float* prow, unsigned* bar, int* picks, float* centers,
-                            kmpar_stats* st, hipStream_t s) {
-  hipError_t e = launch_fill_i32(reinterpret_cast<int*>(bar), 0, 1, s);
+                            double* udraw, double* part, float* prow, int* picks,
+                            float* centers, kmpar_stats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_recl_draws, dim3((k + 255) / 256), dim3(256), 0, s, seed, inst, k, udraw);
+  // every slot starts empty (all-ones); fill kernels, not memsets, so the
+  // sequence can be captured in a graph
+  hipError_t e = launch_fill_i32(reinterpret_cast<int*>(part), -1, 2 * (int64_t)k * G, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_i32(reinterpret_cast<int*>(prow), -1, (int64_t)k * DP, s);
   if (e != hipSuccess) return e;
   ReclArgs a;
   a.Call = Call;
@@ -557,9 +630,9 @@ hipError_t launch_recluster(const float* Call, int DP, int capT, int d, const in
   a.seed = seed;
   a.inst = inst;
   a.slice_cap = (capT + G - 1) / G + 1;
+  a.u = udraw;
   a.part = part;
   a.prow = prow;
-  a.bar = bar;
   a.picks = picks;
   a.centers = centers;
   a.st = st;

@@ -94,6 +94,15 @@ struct ScreenArgs {
 int screen_split(kmpar_dtype dt, bool centers_are_rows);
 int screen_ksteps(int split, int d);
 bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d);
+// Candidate tiles per LDS chunk of the screen for KS k-steps, and the tag
+// bits that number a tile within its chunk.
+constexpr int screen_chunk_tiles(int KS) { return (32 * 1024) / (KS * 64 * 16); }
+constexpr int screen_tag_bits(int KS) {
+  int b = 0;
+  while ((1 << b) < screen_chunk_tiles(KS)) ++b;
+  return b;
+}
+// Error constant G of the screen's lower bound.
 float screen_g(int split, int d);
 hipError_t launch_prep_b(int split, int KS, const float* C, int DP, int d, const int* rs,
                          int m_host, int max_tiles, float om2g, void* B, float* ncg,
@@ -131,8 +140,8 @@ size_t recluster_lds(int capT, int DP, int G);
 constexpr int kReclMaxBlocks = 512;
 hipError_t launch_recluster(const float* Call, int DP, int capT, int d, const int* w,
                             const int* rs_end, int k, uint64_t seed, uint64_t inst, int G,
-                            double* part, float* prow, unsigned* bar, int* picks, float* centers,
-                            kmpar_stats* st, hipStream_t s);
+                            double* udraw, double* part, float* prow, int* picks,
+                            float* centers, kmpar_stats* st, hipStream_t s);
 hipError_t launch_pad_rows(const float* C, int m, int d, int DP, float* Cpad, hipStream_t s);
 hipError_t launch_copy_i32(const int* src, int* dst, int64_t count, hipStream_t s);
 

@@ -17,6 +17,18 @@
 //   otherwise                         -> the point is listed for a full
 //                                        direct-form pass over the candidates.
 // Every decision is therefore the decision of the FP32 direct-form path.
+//
+// Within a chunk of candidate tiles, the running maxima carry the tile's
+// position in the chunk in the low TB mantissa bits of the value itself (the
+// lane fixes the column within the tile), so the per-value work is one bit
+// insert and two med3; each chunk's maxima are then merged with explicit
+// ids.  Replacing those bits moves acc by less than 2^(TB-23) |acc| <=
+// 2^(TB-23) S, S = ||x||^2 + ||c||^2, which the budget of G includes.  The bound also
+// assumes no overflow and negligible underflow: points with ||x||^2 outside
+// [2^-100, 2^100] are always listed, and candidates with ||c||^2 > 2^100
+// get a trivial bound (every point refines or lists them).
+#include <float.h>
+#include <cmath>
 #include <math.h>
 
 #include "common.hpp"
@@ -27,6 +39,10 @@ namespace kmpar {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// Range of squared norms inside which the screen's error budget holds.
+constexpr float kNormMax = 0x1p100f;
+constexpr float kNormMin = 0x1p-100f;
 
 // FP32 -> bf16 bits, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
@@ -90,7 +106,9 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
     float nc = 0.0f;
     if (valid)
       for (int e = 0; e < d; ++e) nc = fmaf(c[e], c[e], nc);
-    ncg[j] = valid ? oneminus2g * nc : INFINITY;
+    // Past m: +inf (never the maximum).  Beyond 2^100 (or not finite): a
+    // bias that makes the candidate's lower bound -inf.
+    ncg[j] = !valid ? INFINITY : (nc <= kNormMax ? oneminus2g * nc : -FLT_MAX);
   }
 }
 
@@ -156,36 +174,89 @@ __device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[kRT][KS], const u1
 }
 
 // One merge step of (largest, second largest, argmax) with the lane CTRL
-// positions away in the same 16-lane row (DPP row_ror).
+// positions away in the same 16-lane row (DPP row_ror).  Values are finite or
+// -inf, so med3 with FLT_MAX is max; the second largest of the union is
+// med3(s1, o1, max(s2, o2)).  Equal maxima keep the lower candidate id.
 template <int CTRL>
 __device__ __forceinline__ void merge_row_ror(float& s1, float& s2, int& ix) {
-  const float o1 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s1), CTRL, 0xF, 0xF, false));
-  const float o2 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s2), CTRL, 0xF, 0xF, false));
-  const int oi = __builtin_amdgcn_update_dpp(0, ix, CTRL, 0xF, 0xF, false);
-  const bool take = (o1 > s1) || (o1 == s1 && (unsigned)oi < (unsigned)ix);
-  s2 = fmaxf(fminf(s1, o1), fmaxf(s2, o2));
+  const float o1 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s1), CTRL, 0xF, 0xF, true));
+  const float o2 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s2), CTRL, 0xF, 0xF, true));
+  const int oi = __builtin_amdgcn_mov_dpp(ix, CTRL, 0xF, 0xF, true);
+  const bool take = (o1 > s1) | ((o1 == s1) & ((unsigned)oi < (unsigned)ix));
+  s2 = __builtin_amdgcn_fmed3f(s1, o1, __builtin_amdgcn_fmed3f(s2, o2, FLT_MAX));
   ix = take ? oi : ix;
-  s1 = fmaxf(s1, o1);
+  s1 = __builtin_amdgcn_fmed3f(s1, o1, FLT_MAX);
 }
 
-// Largest / second largest acc and the argmax of each (row tile, row).
-__device__ __forceinline__ void epilogue(const f32x4 (&acc)[kRT], int j, float (&s1)[kRT][4],
-                                         float (&s2)[kRT][4], int (&ix)[kRT][4]) {
+// Largest and second largest tagged acc of each (row tile, row): the low
+// bits of each value are replaced by the tile's position tq first.  Tagged
+// values are finite, so med3 with FLT_MAX is their max, without the quieting
+// moves fmaxf would add.
+__device__ __forceinline__ void epilogue(const f32x4 (&acc)[kRT], uint32_t keep, uint32_t tq,
+                                         float (&s1)[kRT][4], float (&s2)[kRT][4]) {
 #pragma unroll
   for (int r = 0; r < kRT; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float v = acc[r][i];
-      const bool gt = v > s1[r][i];
+      const float v = __uint_as_float((__float_as_uint(acc[r][i]) & keep) | tq);
       s2[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], s2[r][i], v);
-      ix[r][i] = gt ? j : ix[r][i];
-      s1[r][i] = fmaxf(s1[r][i], v);
+      s1[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], v, FLT_MAX);
     }
+}
+
+constexpr int kWaveStage = kStageBytes * 2 / kWaves;  // LDS bytes per wave after the pass
+
+// Starts the copy of rows [row0, row0 + nr) of X (raw elements, rowb bytes
+// each, nr * rowb a multiple of 16) straight from global memory into dst:
+// lane i of each 1 KB step lands at dst + v0 + 16 i.  The copy is complete
+// after the next vmcnt(0) wait.
+template <typename T>
+__device__ __forceinline__ void stage_rows(char* dst, const T* X, int64_t row0, int nr, int rowb,
+                                           int lane) {
+  const int bytes = nr * rowb;
+  const char* src = reinterpret_cast<const char*>(X) + row0 * rowb;
+  for (int v0 = 0; v0 < bytes; v0 += 1024)
+    if (v0 + 16 * lane < bytes)
+      __builtin_amdgcn_global_load_lds((gbl_void*)(src + v0 + 16 * lane), (lds_void*)(dst + v0),
+                                       16, 0, 0);
+}
+
+// FP32 direct form sum_e (x_e - c_e)^2, e ascending, exactly as the plain
+// kernels compute it (the terms past d add fmaf(0, 0, r) = r).  x: a raw
+// row, staged in LDS (XLDS: read 32 elements at a time without guards; reads
+// past the row stay inside LDS) or in X (guarded); c: an FP32 candidate row
+// (16-byte aligned), read eight float4 at a time.
+template <typename T, bool XLDS>
+__device__ __forceinline__ float refine_dist(const T* x, const float* c, int d) {
+  float r = 0.0f;
+  for (int e0 = 0; e0 < d; e0 += 32) {
+    float4 cv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      cv[u] = (e0 + 4 * u < d) ? reinterpret_cast<const float4*>(c + e0)[u]
+                               : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float xv[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      xv[k] = (XLDS || e0 + k < d) ? Elem<T>::get(x, e0 + k, 1.0f) : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float cc[4] = {cv[u].x, cv[u].y, cv[u].z, cv[u].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + 4 * u + q;
+        const float t = e < d ? xv[4 * u + q] - cc[q] : 0.0f;
+        r = fmaf(t, t, r);
+      }
+    }
+  }
+  return r;
 }
 
 template <int SPLIT, int KS, typename T, bool DIRECT>
 __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
-  constexpr int CT = kStageBytes / (KS * 64 * 16);  // candidate tiles per chunk
+  constexpr int CT = screen_chunk_tiles(KS);        // candidate tiles per chunk
+  static_assert(CT * KS * 64 * 16 <= kStageBytes, "chunk exceeds its staging buffer");
   constexpr int CHUNK_V = CT * KS * 64;             // 16-byte vectors per chunk
   __shared__ u16x8 sB[2][CHUNK_V];
   __shared__ float sN[2][CT * 16];
@@ -245,7 +316,15 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
     }
   }
 
-  // Largest and second largest acc, and the argmax, per (row tile, row).
+  // Per chunk, the largest and second largest tagged acc of each (row tile,
+  // row), the tag being the tile's position in the chunk; after each chunk
+  // they are merged into the running largest, second largest and argmax.
+  // The mask lives in a VGPR so that the tag insert is one v_and_or_b32
+  // (VOP3 reads at most one SGPR, and the tile position is one).
+  constexpr int TB = screen_tag_bits(KS);
+  static_assert((1 << TB) >= CT, "tag too narrow for a chunk");
+  uint32_t keep;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(keep) : "s"(~((1u << TB) - 1u)));
   float s1[kRT][4], s2[kRT][4];
   int ix[kRT][4];
 #pragma unroll
@@ -258,7 +337,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
     }
 
   for (int c = 0; c < nchunks; ++c) {
-    if (threadIdx.x < CT * 16) sN[c & 1][threadIdx.x] = -0.5f * ncg_next;
+    if (threadIdx.x < CT * 16) sN[c & 1][threadIdx.x] = -0.5f * fminf(ncg_next, FLT_MAX);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();  // chunk c is in LDS; everyone is done with chunk c-1
     if (c + 1 < nchunks) {
@@ -268,19 +347,76 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
     const int nt = min(CT, ntiles - c * CT);
     const u16x8* buf = sB[c & 1];
     const float* ncs = sN[c & 1];
-    // Software pipeline: the MFMAs of tile q+1 are issued before the
-    // epilogue of tile q, so matrix and vector units overlap within a wave.
-    f32x4 acc[kRT];
-    mfma_tile<KS>(Aop, buf, ncs, 0, lane, acc);
-    for (int q = 0; q + 1 < nt; ++q) {
-      f32x4 nxt[kRT];
-      mfma_tile<KS>(Aop, buf, ncs, q + 1, lane, nxt);
-      epilogue(acc, (c * CT + q) * 16 + (lane % 16), s1, s2, ix);
+    float c1[kRT][4], c2[kRT][4];
 #pragma unroll
-      for (int r = 0; r < kRT; ++r) acc[r] = nxt[r];
+    for (int r = 0; r < kRT; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        c1[r][i] = -INFINITY;
+        c2[r][i] = -INFINITY;
+      }
+    // Software pipeline: the MFMAs of tile q+1 are issued before the
+    // epilogue of tile q, so matrix and vector units overlap within a wave
+    // (two accumulator sets, unrolled by two so no copies are needed).
+    f32x4 acc0[kRT], acc1[kRT];
+    mfma_tile<KS>(Aop, buf, ncs, 0, lane, acc0);
+    int q = 0;
+    for (; q + 2 < nt; q += 2) {
+      mfma_tile<KS>(Aop, buf, ncs, q + 1, lane, acc1);
+      epilogue(acc0, keep, q, c1, c2);
+      mfma_tile<KS>(Aop, buf, ncs, q + 2, lane, acc0);
+      epilogue(acc1, keep, q + 1, c1, c2);
+      // Issue order: the operand reads first, then every MFMA followed by
+      // three vector instructions, so that one wave keeps both the matrix
+      // and the vector pipes busy.
+      __builtin_amdgcn_sched_group_barrier(0x100, 2 * (KS + 1), 0);
+#pragma unroll
+      for (int g = 0; g < 2 * KS * kRT; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+      }
     }
-    epilogue(acc, (c * CT + nt - 1) * 16 + (lane % 16), s1, s2, ix);
+    if (q + 1 < nt) {
+      mfma_tile<KS>(Aop, buf, ncs, q + 1, lane, acc1);
+      epilogue(acc0, keep, q, c1, c2);
+      epilogue(acc1, keep, q + 1, c1, c2);
+    } else {
+      epilogue(acc0, keep, q, c1, c2);
+    }
+    // Chunk merge: candidate id from the tag and the lane's column; a tie
+    // with the running maximum keeps the earlier (lower) id.
+#pragma unroll
+    for (int r = 0; r < kRT; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float v1 = c1[r][i];
+        const int cj = ((int)(__float_as_uint(v1) & ((1u << TB) - 1u)) + c * CT) * 16 + (lane % 16);
+        const bool take = v1 > s1[r][i];
+        s2[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], v1,
+                                           __builtin_amdgcn_fmed3f(s2[r][i], c2[r][i], FLT_MAX));
+        ix[r][i] = take ? cj : ix[r][i];
+        s1[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], v1, FLT_MAX);
+      }
   }
+
+  // Once every wave is past its last chunk the staging buffers are idle:
+  // start copying this wave's rows (raw elements) into its quarter, and the
+  // per-point inputs of the decision, so that they land while the lanes
+  // merge.  From here on each wave only touches its own LDS.
+  __syncthreads();
+  const int p = wbase + lane;
+  const bool valid = p < a.n;
+  const float nx = valid ? a.norms[p] : 0.0f;
+  const float D = (a.first || !valid) ? INFINITY : a.D2[p];
+  const int nvalid = max(0, min(kWavePts, a.n - wbase));
+  const int rowb = d * (int)sizeof(T);  // <= 1 KB, so R >= 16
+  const int R = min(kWavePts, (kWaveStage / rowb) & ~15);  // rows per staging group
+  char* xw = reinterpret_cast<char*>(&sB[0][0]) + wave * kWaveStage;
+  // Full waves stage their rows in groups of R (a multiple of 16, so every
+  // group is whole 16-byte units); the one partial wave of X reads its rows
+  // from global memory instead.
+  const bool staged = nvalid == kWavePts;
+  if (staged) stage_rows<T>(xw, X, wbase, R, rowb, lane);
 
   // Merge the 16 lanes that share a point row group (lane / 16): rotations
   // by 8, 4, 2, 1 inside each 16-lane DPP row leave every lane with the
@@ -306,59 +442,47 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
         sIdx[wave][pl] = ix[r][i];
       }
   }
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
   // One lane per point: decide, refine, fold or list.  The refinement
-  // reads the wave's rows from LDS (staged with coalesced loads into the
-  // now idle staging buffers, 16 KB per wave) and candidate rows as float4.
-  const int p = wbase + lane;
-  const bool valid = p < a.n;
+  // reads the point's row from the staged copy and the candidate row as
+  // float4.
   const int j1 = sIdx[wave][lane];
-  const float nxg = valid ? a.oneminus2g * a.norms[p] : 0.0f;
+  const bool in_range = nx >= kNormMin && nx <= kNormMax;
+  const float nxg = a.oneminus2g * nx;
   const float lbmin = fmaf(sRes[wave][lane][0], -2.0f, nxg);
   const float lb2 = fmaf(sRes[wave][lane][1], -2.0f, nxg);
-  const float D = (a.first || !valid) ? INFINITY : a.D2[p];
-  const bool refine = valid && j1 >= 0 && lbmin < D;
+  const bool refine = valid && in_range && j1 >= 0 && lbmin < D;
+  const float* crow = a.C + (int64_t)(id0 + max(j1, 0)) * a.DP;
   float r1 = 0.0f;
-  float* xw = reinterpret_cast<float*>(&sB[0][0]) + wave * (kStageBytes * 2 / kWaves / 4);
-  const int R = min(64, (kStageBytes * 2 / kWaves / 4) / d);
-  const int nvalid = __ballot(refine) ? max(0, min(64, a.n - wbase)) : 0;
-  for (int c0 = 0; c0 < nvalid; c0 += R) {
-    const int nr = min(R, nvalid - c0);
-    const int64_t base = (int64_t)(wbase + c0) * d;
-    for (int idx = lane; idx < nr * d; idx += 64)
-      xw[idx] = Elem<T>::get(X, base + idx, row_scale_of<T>(a.row_scale, wbase + c0 + idx / d));
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (refine && lane >= c0 && lane < c0 + nr) {
-      const float* xr = xw + (lane - c0) * d;
-      const float4* cr = reinterpret_cast<const float4*>(a.C + (int64_t)(id0 + j1) * a.DP);
-      for (int e4 = 0; e4 * 4 < d; ++e4) {
-        const float4 cv = cr[e4];
-        const float cc[4] = {cv.x, cv.y, cv.z, cv.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = 4 * e4 + q;
-          if (e < d) {
-            const float t = xr[e] - cc[q];
-            r1 = fmaf(t, t, r1);
-          }
-        }
+  if (staged) {
+    for (int c0 = 0; c0 < kWavePts; c0 += R) {
+      const int nr = min(R, kWavePts - c0);
+      if (c0 > 0) {
+        __builtin_amdgcn_wave_barrier();  // the previous group has been read
+        stage_rows<T>(xw, X, wbase + c0, nr, rowb, lane);
       }
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __builtin_amdgcn_wave_barrier();
+      if (refine && lane >= c0 && lane < c0 + nr)
+        r1 = refine_dist<T, true>(reinterpret_cast<const T*>(xw + (lane - c0) * rowb), crow, d);
     }
-    __builtin_amdgcn_wave_barrier();
+  } else if (refine) {
+    r1 = refine_dist<T, false>(X + (int64_t)p * d, crow, d);
   }
   if (!valid) return;
-  if (!refine) {
+  bool listed = false;
+  if (!in_range) {
+    listed = D > 0.0f;  // outside the bound's range: the direct form decides
+  } else if (!refine) {
     if (a.first) {  // m == 0 (never on the paths that call the screen)
       a.D2[p] = INFINITY;
       a.A[p] = -1;
     }
     return;
-  }
-  bool listed = false;
-  if (r1 < D) {
+  } else if (r1 < D) {
     if (lb2 > r1) {
       a.D2[p] = r1;
       a.A[p] = id0 + j1;
@@ -477,10 +601,11 @@ bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d) {
   return sp != 0 && screen_ksteps(sp, d) <= 8;
 }
 
-// Relative error budget of the screen, as a multiple of ||x||^2 + ||c||^2:
+// Relative error budget of the screen, as a multiple of S = ||x||^2 + ||c||^2:
 // bf16 split truncation (twice the dot), FP32 accumulation of K products,
-// FP32 norms, the roundings of the lower-bound arithmetic, and the FP32
-// direct-form error of the distances it is compared with; times 2 for margin.
+// FP32 norms, the roundings of the lower-bound arithmetic, the FP32
+// direct-form error of the distances it is compared with, and the tile tag
+// in the low mantissa bits; times 2 for margin.
 float screen_g(int split, int d) {
   const double u = 0x1.0p-24;
   const int K = 32 * screen_ksteps(split, d);
@@ -488,11 +613,14 @@ float screen_g(int split, int d) {
   if (split == 3) split_err = 3.2 * 0x1.0p-16;
   if (split == 2) split_err = 1.1 * 0x1.0p-16;
   // K products plus the -ncg/2 bias, summed in FP32: |sum of terms| <=
-  // 1.01 (||x||^2 + ||c||^2), doubled by the -2 that turns acc into lb.
+  // 1.01 S, doubled by the -2 that turns acc into lb.
   const double acc_err = 2.05 * (K + 1) * u;
   const double misc = (d + 8) * u + 2.0 * (d + 2) * u;
+  // |acc| <= |x.c| + ||c||^2 / 2 <= 1.01 S; the tag moves it by less than
+  // 2^(TB-23) |acc|, and lb by twice that.
+  const double tag_err = 2.02 * std::ldexp(1.0, screen_tag_bits(screen_ksteps(split, d)) - 23);
   const double safety = 2.0;  // 2G = safety * budget
-  return (float)(safety * (split_err + acc_err + misc) / 2.0);
+  return (float)(safety * (split_err + acc_err + misc + tag_err) / 2.0);
 }
 
 hipError_t launch_prep_b(int split, int KS, const float* C, int DP, int d, const int* rs,
