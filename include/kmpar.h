@@ -128,9 +128,10 @@ const char* kmpar_last_error(const kmpar_ctx* ctx);
 size_t kmpar_sizeof_stats(void);
 
 /* Upper bound on |C| that kmpar_init keeps: 1 + rounds * per-round capacity,
- * where the capacity min(n, ceil(ell + 12 sqrt(ell) + 64)) sits more than
- * 12 standard deviations above the expected ell points per round (Section
- * 3.3: each round keeps ell points in expectation). */
+ * where the capacity min(n, L + 12 isqrt(L) + 76), L = ceil(ell), is at
+ * least ell + 12 sqrt(ell) + 64: more than 12 standard deviations above the
+ * expected ell points per round (Section 3.3: each round keeps ell points in
+ * expectation). */
 int kmpar_max_candidates(int64_t n, double ell, int32_t rounds, int64_t* out);
 
 /* Workspace bytes for `op` at the given sizes (k = number of centers m for

@@ -94,12 +94,16 @@ struct ScreenArgs {
 int screen_split(kmpar_dtype dt, bool centers_are_rows);
 int screen_ksteps(int split, int d);
 bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d);
-// Candidate tiles per LDS chunk of the screen for KS k-steps, and the tag
-// bits that number a tile within its chunk.
+// Candidate tiles per LDS chunk of the screen for KS k-steps, chunks per tag
+// group (groups of up to 16 tiles), and the tag bits that number a tile
+// within its group.
 constexpr int screen_chunk_tiles(int KS) { return (32 * 1024) / (KS * 64 * 16); }
+constexpr int screen_group_chunks(int KS) {
+  return screen_chunk_tiles(KS) >= 16 ? 1 : 16 / screen_chunk_tiles(KS);
+}
 constexpr int screen_tag_bits(int KS) {
   int b = 0;
-  while ((1 << b) < screen_chunk_tiles(KS)) ++b;
+  while ((1 << b) < screen_group_chunks(KS) * screen_chunk_tiles(KS)) ++b;
   return b;
 }
 // Error constant G of the screen's lower bound.

@@ -18,11 +18,11 @@
 //                                        direct-form pass over the candidates.
 // Every decision is therefore the decision of the FP32 direct-form path.
 //
-// Within a chunk of candidate tiles, the running maxima carry the tile's
-// position in the chunk in the low TB mantissa bits of the value itself (the
-// lane fixes the column within the tile), so the per-value work is one bit
-// insert and two med3; each chunk's maxima are then merged with explicit
-// ids.  Replacing those bits moves acc by less than 2^(TB-23) |acc| <=
+// Within a group of up to 16 candidate tiles (one or more LDS chunks), the
+// running maxima carry the tile's position in the group in the low TB
+// mantissa bits of the value itself (the lane fixes the column within the
+// tile), so the per-value work is one bit insert and two med3; each group's
+// maxima are then merged with explicit ids.  Replacing those bits moves acc by less than 2^(TB-23) |acc| <=
 // 2^(TB-23) S, S = ||x||^2 + ||c||^2, which the budget of G includes.  The bound also
 // assumes no overflow and negligible underflow: points with ||x||^2 outside
 // [2^-100, 2^100] are always listed, and candidates with ||c||^2 > 2^100
@@ -159,11 +159,18 @@ typedef __attribute__((address_space(3))) void lds_void;
 typedef const __attribute__((address_space(1))) void gbl_void;
 
 // acc[r] = A[r] . B(tile q) - ncg_j / 2, for the wave's kRT row tiles.
-template <int KS>
+template <int KS, bool BCAST>
 __device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[kRT][KS], const u16x8* buf,
                                           const float* ncs, int q, int lane, f32x4 (&acc)[kRT]) {
-  const float cj = ncs[q * 16 + (lane % 16)];
-  const f32x4 cinit = {cj, cj, cj, cj};
+  // ncs: -ncg/2 per candidate, four copies each when BCAST (one LDS read
+  // then yields the accumulator's initial value)
+  f32x4 cinit;
+  if constexpr (BCAST) {
+    cinit = reinterpret_cast<const f32x4*>(ncs)[q * 16 + (lane % 16)];
+  } else {
+    const float cj = ncs[q * 16 + (lane % 16)];
+    cinit = f32x4{cj, cj, cj, cj};
+  }
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     const bf16x8 b = __builtin_bit_cast(bf16x8, buf[(q * KS + s) * 64 + lane]);
@@ -171,21 +178,6 @@ __device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[kRT][KS], const u1
     for (int r = 0; r < kRT; ++r)
       acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[r][s], b, s == 0 ? cinit : acc[r], 0, 0, 0);
   }
-}
-
-// One merge step of (largest, second largest, argmax) with the lane CTRL
-// positions away in the same 16-lane row (DPP row_ror).  Values are finite or
-// -inf, so med3 with FLT_MAX is max; the second largest of the union is
-// med3(s1, o1, max(s2, o2)).  Equal maxima keep the lower candidate id.
-template <int CTRL>
-__device__ __forceinline__ void merge_row_ror(float& s1, float& s2, int& ix) {
-  const float o1 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s1), CTRL, 0xF, 0xF, true));
-  const float o2 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s2), CTRL, 0xF, 0xF, true));
-  const int oi = __builtin_amdgcn_mov_dpp(ix, CTRL, 0xF, 0xF, true);
-  const bool take = (o1 > s1) | ((o1 == s1) & ((unsigned)oi < (unsigned)ix));
-  s2 = __builtin_amdgcn_fmed3f(s1, o1, __builtin_amdgcn_fmed3f(s2, o2, FLT_MAX));
-  ix = take ? oi : ix;
-  s1 = __builtin_amdgcn_fmed3f(s1, o1, FLT_MAX);
 }
 
 // Largest and second largest tagged acc of each (row tile, row): the low
@@ -259,9 +251,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   static_assert(CT * KS * 64 * 16 <= kStageBytes, "chunk exceeds its staging buffer");
   constexpr int CHUNK_V = CT * KS * 64;             // 16-byte vectors per chunk
   __shared__ u16x8 sB[2][CHUNK_V];
-  __shared__ float sN[2][CT * 16];
-  __shared__ float sRes[kWaves][kWavePts][2];
-  __shared__ int sIdx[kWaves][kWavePts];
+  constexpr bool BCAST = CT <= 16;  // LDS for four copies of each bias
+  __shared__ __attribute__((aligned(16))) float sN[2][CT * 16 * (BCAST ? 4 : 1)];
 
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int d = a.d;
@@ -321,11 +312,12 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   // they are merged into the running largest, second largest and argmax.
   // The mask lives in a VGPR so that the tag insert is one v_and_or_b32
   // (VOP3 reads at most one SGPR, and the tile position is one).
+  constexpr int GC = screen_group_chunks(KS);  // chunks per tag group
   constexpr int TB = screen_tag_bits(KS);
-  static_assert((1 << TB) >= CT, "tag too narrow for a chunk");
+  static_assert((1 << TB) >= GC * CT, "tag too narrow for a group");
   uint32_t keep;
   asm volatile("v_mov_b32 %0, %1" : "=v"(keep) : "s"(~((1u << TB) - 1u)));
-  float s1[kRT][4], s2[kRT][4];
+  float s1[kRT][4], s2[kRT][4], c1[kRT][4], c2[kRT][4];
   int ix[kRT][4];
 #pragma unroll
   for (int r = 0; r < kRT; ++r)
@@ -337,7 +329,13 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
     }
 
   for (int c = 0; c < nchunks; ++c) {
-    if (threadIdx.x < CT * 16) sN[c & 1][threadIdx.x] = -0.5f * fminf(ncg_next, FLT_MAX);
+    if (threadIdx.x < CT * 16) {
+      const float nb = -0.5f * fminf(ncg_next, FLT_MAX);
+      if constexpr (BCAST)
+        reinterpret_cast<f32x4*>(sN[c & 1])[threadIdx.x] = f32x4{nb, nb, nb, nb};
+      else
+        sN[c & 1][threadIdx.x] = nb;
+    }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();  // chunk c is in LDS; everyone is done with chunk c-1
     if (c + 1 < nchunks) {
@@ -347,25 +345,28 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
     const int nt = min(CT, ntiles - c * CT);
     const u16x8* buf = sB[c & 1];
     const float* ncs = sN[c & 1];
-    float c1[kRT][4], c2[kRT][4];
+    const int cg = c % GC;         // position of the chunk in its tag group
+    const uint32_t t0 = cg * CT;   // tag of the chunk's first tile
+    if (cg == 0) {
 #pragma unroll
-    for (int r = 0; r < kRT; ++r)
+      for (int r = 0; r < kRT; ++r)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        c1[r][i] = -INFINITY;
-        c2[r][i] = -INFINITY;
-      }
+        for (int i = 0; i < 4; ++i) {
+          c1[r][i] = -INFINITY;
+          c2[r][i] = -INFINITY;
+        }
+    }
     // Software pipeline: the MFMAs of tile q+1 are issued before the
     // epilogue of tile q, so matrix and vector units overlap within a wave
     // (two accumulator sets, unrolled by two so no copies are needed).
     f32x4 acc0[kRT], acc1[kRT];
-    mfma_tile<KS>(Aop, buf, ncs, 0, lane, acc0);
+    mfma_tile<KS, BCAST>(Aop, buf, ncs, 0, lane, acc0);
     int q = 0;
     for (; q + 2 < nt; q += 2) {
-      mfma_tile<KS>(Aop, buf, ncs, q + 1, lane, acc1);
-      epilogue(acc0, keep, q, c1, c2);
-      mfma_tile<KS>(Aop, buf, ncs, q + 2, lane, acc0);
-      epilogue(acc1, keep, q + 1, c1, c2);
+      mfma_tile<KS, BCAST>(Aop, buf, ncs, q + 1, lane, acc1);
+      epilogue(acc0, keep, t0 + q, c1, c2);
+      mfma_tile<KS, BCAST>(Aop, buf, ncs, q + 2, lane, acc0);
+      epilogue(acc1, keep, t0 + q + 1, c1, c2);
       // Issue order: the operand reads first, then every MFMA followed by
       // three vector instructions, so that one wave keeps both the matrix
       // and the vector pipes busy.
@@ -377,83 +378,85 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
       }
     }
     if (q + 1 < nt) {
-      mfma_tile<KS>(Aop, buf, ncs, q + 1, lane, acc1);
-      epilogue(acc0, keep, q, c1, c2);
-      epilogue(acc1, keep, q + 1, c1, c2);
+      mfma_tile<KS, BCAST>(Aop, buf, ncs, q + 1, lane, acc1);
+      epilogue(acc0, keep, t0 + q, c1, c2);
+      epilogue(acc1, keep, t0 + q + 1, c1, c2);
     } else {
-      epilogue(acc0, keep, q, c1, c2);
+      epilogue(acc0, keep, t0 + q, c1, c2);
     }
-    // Chunk merge: candidate id from the tag and the lane's column; a tie
+    // Group merge: candidate id from the tag and the lane's column; a tie
     // with the running maximum keeps the earlier (lower) id.
+    if (cg == GC - 1 || c + 1 == nchunks) {
 #pragma unroll
     for (int r = 0; r < kRT; ++r)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float v1 = c1[r][i];
-        const int cj = ((int)(__float_as_uint(v1) & ((1u << TB) - 1u)) + c * CT) * 16 + (lane % 16);
+        const int cj = ((int)(__float_as_uint(v1) & ((1u << TB) - 1u)) + (c - cg) * CT) * 16 + (lane % 16);
         const bool take = v1 > s1[r][i];
         s2[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], v1,
                                            __builtin_amdgcn_fmed3f(s2[r][i], c2[r][i], FLT_MAX));
         ix[r][i] = take ? cj : ix[r][i];
         s1[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], v1, FLT_MAX);
       }
+    }
   }
 
-  // Once every wave is past its last chunk the staging buffers are idle:
-  // start copying this wave's rows (raw elements) into its quarter, and the
-  // per-point inputs of the decision, so that they land while the lanes
-  // merge.  From here on each wave only touches its own LDS.
+  // Once every wave is past its last chunk the staging buffers are idle and
+  // each wave works in its own quarter of them.
   __syncthreads();
   const int p = wbase + lane;
   const bool valid = p < a.n;
   const float nx = valid ? a.norms[p] : 0.0f;
   const float D = (a.first || !valid) ? INFINITY : a.D2[p];
-  const int nvalid = max(0, min(kWavePts, a.n - wbase));
-  const int rowb = d * (int)sizeof(T);  // <= 1 KB, so R >= 16
-  const int R = min(kWavePts, (kWaveStage / rowb) & ~15);  // rows per staging group
   char* xw = reinterpret_cast<char*>(&sB[0][0]) + wave * kWaveStage;
-  // Full waves stage their rows in groups of R (a multiple of 16, so every
-  // group is whole 16-byte units); the one partial wave of X reads its rows
-  // from global memory instead.
-  const bool staged = nvalid == kWavePts;
-  if (staged) stage_rows<T>(xw, X, wbase, R, rowb, lane);
 
-  // Merge the 16 lanes that share a point row group (lane / 16): rotations
-  // by 8, 4, 2, 1 inside each 16-lane DPP row leave every lane with the
-  // merge of all 16 (the top-2 merge with lowest-id ties is commutative and
-  // associative).
+  // Merge of the 16 columns of every point through LDS: lane l writes the
+  // (largest, second largest, id) of each (row tile, row) at [point][l % 16]
+  // (columns XOR-swizzled by the point to spread the banks), then lane p
+  // reads the 16 entries of point p and merges them in column order.  Of two
+  // equal maxima the earlier column is kept; no decision depends on which,
+  // since then lb2 = lbmin <= r1 and the point is listed.
+  f32x4* M = reinterpret_cast<f32x4*>(xw);  // [64 points][16 columns]
 #pragma unroll
   for (int r = 0; r < kRT; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      merge_row_ror<0x128>(s1[r][i], s2[r][i], ix[r][i]);
-      merge_row_ror<0x124>(s1[r][i], s2[r][i], ix[r][i]);
-      merge_row_ror<0x122>(s1[r][i], s2[r][i], ix[r][i]);
-      merge_row_ror<0x121>(s1[r][i], s2[r][i], ix[r][i]);
+      const int pl = r * 16 + (lane / 16) * 4 + i;
+      M[pl * 16 + ((lane % 16) ^ (pl & 15))] =
+          f32x4{s1[r][i], s2[r][i], __int_as_float(ix[r][i]), 0.0f};
     }
-  if (lane % 16 == 0) {
-#pragma unroll
-    for (int r = 0; r < kRT; ++r)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int pl = r * 16 + (lane / 16) * 4 + i;
-        sRes[wave][pl][0] = s1[r][i];
-        sRes[wave][pl][1] = s2[r][i];
-        sIdx[wave][pl] = ix[r][i];
-      }
-  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  float b1 = -INFINITY, b2 = -INFINITY;
+  int j1 = -1;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const f32x4 e = M[lane * 16 + (c ^ (lane & 15))];
+    const bool take = e.x > b1;
+    b2 = __builtin_amdgcn_fmed3f(b1, e.x, __builtin_amdgcn_fmed3f(b2, e.y, FLT_MAX));
+    j1 = take ? __float_as_int(e.z) : j1;
+    b1 = __builtin_amdgcn_fmed3f(b1, e.x, FLT_MAX);
+  }
+  __builtin_amdgcn_wave_barrier();  // the quarter is free again
+
+  // This wave's rows (raw elements) go to its quarter: full waves stage them
+  // in groups of R (a multiple of 16, so every group is whole 16-byte units);
+  // the one partial wave of X reads its rows from global memory instead.
+  const int nvalid = max(0, min(kWavePts, a.n - wbase));
+  const int rowb = d * (int)sizeof(T);  // <= 1 KB, so R >= 16
+  const int R = min(kWavePts, (kWaveStage / rowb) & ~15);  // rows per staging group
+  const bool staged = nvalid == kWavePts;
+  if (staged) stage_rows<T>(xw, X, wbase, R, rowb, lane);
 
   // One lane per point: decide, refine, fold or list.  The refinement
   // reads the point's row from the staged copy and the candidate row as
   // float4.
-  const int j1 = sIdx[wave][lane];
   const bool in_range = nx >= kNormMin && nx <= kNormMax;
   const float nxg = a.oneminus2g * nx;
-  const float lbmin = fmaf(sRes[wave][lane][0], -2.0f, nxg);
-  const float lb2 = fmaf(sRes[wave][lane][1], -2.0f, nxg);
+  const float lbmin = fmaf(b1, -2.0f, nxg);
+  const float lb2 = fmaf(b2, -2.0f, nxg);
   const bool refine = valid && in_range && j1 >= 0 && lbmin < D;
   const float* crow = a.C + (int64_t)(id0 + max(j1, 0)) * a.DP;
   float r1 = 0.0f;
