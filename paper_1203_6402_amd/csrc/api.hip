@@ -521,18 +521,17 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   const int split = screen_split(dtype, true);
   const bool refined = ctx->mode == KMPAR_MODE_REFINED && screen_supported(dtype, true, d) &&
                        ell >= kScreenMinEll;
-  fa.norms = refined ? L.norms : nullptr;
-  KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
-  fa.norms = nullptr;
+  // One coalesced read of X: D2 against the first center, and for REFINED
+  // ||x||^2 and (unless X rows are the operands) the screen's A operands.
+  const bool prep = refined && !screen_a_direct(dtype, split, d);
+  const void* Apre = prep ? L.Apre : nullptr;
+  KMPAR_HIP(timed(ctx, kSlotDirect, N, nullptr, L.rs, 1, s, [&] {
+    return launch_first_pass(dtype, split, refined ? screen_ksteps(split, d) : 1, prep, X,
+                             row_scale, N, d, DP, L.Call, L.rs, L.D2, L.A,
+                             refined ? L.norms : nullptr, prep ? L.Apre : nullptr, s);
+  }));
   KMPAR_HIP(launch_phi(L.D2, N, L.phi_part, &st->phi[0], s));
-  const void* Apre = nullptr;
-  if (refined) {
-    KMPAR_HIP(launch_fill_i32(L.list_len, 0, 1, s));
-    if (!screen_a_direct(dtype, split, d)) {
-      KMPAR_HIP(launch_prep_a(dtype, split, screen_ksteps(split, d), X, row_scale, N, d, L.Apre, s));
-      Apre = L.Apre;
-    }
-  }
+  if (refined) KMPAR_HIP(launch_fill_i32(L.list_len, 0, 1, s));
   // Steps 3-6: rounds.
   fa.first = 0;
   for (int t = 1; t <= rounds; ++t) {

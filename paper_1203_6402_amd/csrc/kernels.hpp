@@ -117,6 +117,12 @@ size_t screen_a_bytes(int n, int KS);
 hipError_t launch_prep_a(kmpar_dtype dt, int split, int KS, const void* X, const float* rsc, int n,
                          int d, void* Apre, hipStream_t s);
 hipError_t launch_list_reset(int* list_len, kmpar_stats* st, hipStream_t s);
+// The first pass against candidate rs[0] (D2, A, optional norms), fused with
+// the A operands of the screen when prep.
+hipError_t launch_first_pass(kmpar_dtype dt, int split, int KS, bool prep, const void* X,
+                             const float* rsc, int n, int d, int DP, const float* C,
+                             const int* rs, float* D2, int* A, float* norms, void* Apre,
+                             hipStream_t s);
 hipError_t launch_rownorm(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
                           float* norms, hipStream_t s);
 

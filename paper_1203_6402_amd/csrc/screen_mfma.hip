@@ -142,6 +142,75 @@ __global__ __launch_bounds__(256) void k_prep_a(const T* X, const float* row_sca
   }
 }
 
+// ------------------------------------------------------------ first pass
+// Algorithm 2 step 2 (the first pass, m = 1) fused with the preparation of
+// the A operands: one coalesced read of each block of 64 rows of X gives
+// D^2 to the first center (FP32 direct form, coordinates ascending, as the
+// fold computes it), A = its id, ||x||^2 (when norms != nullptr) and, when
+// PREP, the A operands exactly as k_prep_a writes them.
+template <int SPLIT, int KS, typename T, bool PREP>
+__global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row_scale, int n,
+                                                    int d, int DP, const float* C, const int* rs,
+                                                    float* D2, int* A, float* norms,
+                                                    u16x8* Apre) {
+  extern __shared__ float xs[];  // [64][d] rows, then the first center [DP]
+  float* c0 = xs + 64 * d;
+  const int p0 = blockIdx.x * 64;
+  const int np = max(0, min(64, n - p0));
+  const int id0 = rs[0];
+  for (int e = threadIdx.x; e < DP; e += 256) c0[e] = C[(int64_t)id0 * DP + e];
+  // coalesced, twelve loads in flight per thread before the LDS stores
+  constexpr int U = 12;
+  const int cnt = np * d;
+  for (int i0 = 0; i0 < cnt; i0 += U * 256) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * 256 + threadIdx.x;
+      v[u] = idx < cnt ? Elem<T>::get(X, (int64_t)p0 * d + idx,
+                                      row_scale_of<T>(row_scale, p0 + idx / d))
+                       : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * 256 + threadIdx.x;
+      if (idx < cnt) xs[idx] = v[u];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < np) {
+    const float* xr = xs + threadIdx.x * d;
+    float acc = 0.0f, nx = 0.0f;
+#pragma unroll 8
+    for (int e = 0; e < d; ++e) {
+      const float v = xr[e];
+      const float t = v - c0[e];
+      acc = fmaf(t, t, acc);
+      nx = fmaf(v, v, nx);
+    }
+    const int i = p0 + threadIdx.x;
+    if (norms) norms[i] = nx;
+    D2[i] = acc;
+    A[i] = id0;
+  }
+  if constexpr (PREP) {
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    const int row = w * 16 + (lane % 16);
+    const bool valid = row < np;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      u16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = s * 32 + (lane / 16) * 8 + e;
+        const int part = k / d, coord = k - part * d;
+        v[e] = (valid && part < SPLIT) ? a_elem<SPLIT>(xs[row * d + coord], part) : (uint16_t)0;
+      }
+      Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
+    }
+  }
+}
+
 // --------------------------------------------------------------- the screen
 // Block = kWaves waves; wave w owns kRT tiles of 16 points (A operands held in
 // registers for the pass).  Candidate tiles stream through two LDS buffers:
@@ -554,6 +623,61 @@ static hipError_t launch_prep_a_split(int KS, const void* X, const float* rsc, i
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int SPLIT, int KS, typename T, bool PREP>
+static hipError_t launch_first_one(const void* X, const float* rsc, int n, int d, int DP,
+                                   const float* C, const int* rs, float* D2, int* A,
+                                   float* norms, void* Apre, hipStream_t s) {
+  // grid: 64-row blocks; with PREP the A tiles of all ceil(n / 256) * 16
+  // tiles the screen reads are written (rows past n as zeros)
+  const int blocks = PREP ? (n + kBlockPts - 1) / kBlockPts * (kBlockPts / 64) : (n + 63) / 64;
+  const size_t lds = ((size_t)64 * d + DP) * 4;
+  hipError_t e = hipFuncSetAttribute((const void*)k_first_prep<SPLIT, KS, T, PREP>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_first_prep<SPLIT, KS, T, PREP>), dim3(blocks), dim3(256), lds, s,
+                     static_cast<const T*>(X), rsc, n, d, DP, C, rs, D2, A, norms,
+                     static_cast<u16x8*>(Apre));
+  return hipGetLastError();
+}
+
+template <int SPLIT, typename T>
+static hipError_t launch_first_split(int KS, const void* X, const float* rsc, int n, int d, int DP,
+                                     const float* C, const int* rs, float* D2, int* A,
+                                     float* norms, void* Apre, hipStream_t s) {
+  switch (KS) {
+#define KMPAR_FP(V) \
+  case V: return launch_first_one<SPLIT, V, T, true>(X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s);
+    KMPAR_FP(1) KMPAR_FP(2) KMPAR_FP(3) KMPAR_FP(4) KMPAR_FP(5) KMPAR_FP(6) KMPAR_FP(7)
+    KMPAR_FP(8)
+#undef KMPAR_FP
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_first_pass(kmpar_dtype dt, int split, int KS, bool prep, const void* X,
+                             const float* rsc, int n, int d, int DP, const float* C,
+                             const int* rs, float* D2, int* A, float* norms, void* Apre,
+                             hipStream_t s) {
+  if (prep) {
+    if (dt == KMPAR_F32 && split == 3)
+      return launch_first_split<3, float>(KS, X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s);
+    if (dt == KMPAR_BF16 && split == 1)
+      return launch_first_split<1, bf16_t>(KS, X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s);
+    if (dt == KMPAR_BF16 && split == 2)
+      return launch_first_split<2, bf16_t>(KS, X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s);
+    return hipErrorInvalidValue;
+  }
+  switch (dt) {
+    case KMPAR_F32:
+      return launch_first_one<1, 1, float, false>(X, rsc, n, d, DP, C, rs, D2, A, norms, nullptr, s);
+    case KMPAR_BF16:
+      return launch_first_one<1, 1, bf16_t, false>(X, rsc, n, d, DP, C, rs, D2, A, norms, nullptr, s);
+    case KMPAR_FP8_E4M3:
+      return launch_first_one<1, 1, fp8_t, false>(X, rsc, n, d, DP, C, rs, D2, A, norms, nullptr, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 bool screen_a_direct(kmpar_dtype dt, int split, int d) {
