@@ -96,10 +96,11 @@ typedef struct kmpar_trace {
 
 /* Tuning options of a context. */
 typedef enum kmpar_option {
-  /* Step-8 recluster of kmpar_init: 0 = automatic, 1 = one workgroup
-   * (candidate E values in LDS, rows streamed), 2 = several workgroups with
-   * LDS-resident row slices and grid barriers.  All give the same picks up
-   * to FP64 summation order. */
+  /* Step-8 recluster of kmpar_init: 0 = automatic (2 when the CUs' LDS can
+   * hold every candidate row, else 3), 1 = one workgroup (candidate E values
+   * in LDS, rows streamed), 2 = several workgroups with LDS-resident row
+   * slices, 3 = several workgroups reading the rows from global memory.
+   * All give the same picks up to FP64 summation order. */
   KMPAR_OPT_RECLUSTER_PATH = 0
 } kmpar_option;
 int kmpar_set_option(kmpar_ctx* ctx, kmpar_option opt, int64_t value);

@@ -131,7 +131,8 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.w = c.take<int>(capT);
   // one partial per (pick, block) and one row per pick: the recluster never
   // reuses a slot (the grid at launch has at most this many blocks)
-  const int G_max = recluster_blocks((int)capT, DP, kReclMaxBlocks);
+  ReclPlan plan{kReclMaxBlocks, 1, false, 0};
+  const int G_max = recluster_plan((int)capT, DP, kReclMaxBlocks, false, &plan) ? plan.G : kReclMaxBlocks;
   L.rpart = c.take<double>((size_t)k * G_max);
   L.udraw = c.take<double>(k);
   L.prow = c.take<float>((size_t)k * DP);
@@ -367,7 +368,7 @@ int kmpar_set_option(kmpar_ctx* ctx, kmpar_option opt, int64_t value) {
   if (!ctx) return KMPAR_E_INVAL;
   switch (opt) {
     case KMPAR_OPT_RECLUSTER_PATH:
-      if (value < 0 || value > 2) return set_err(ctx, KMPAR_E_INVAL, "recluster path %lld", (long long)value);
+      if (value < 0 || value > 3) return set_err(ctx, KMPAR_E_INVAL, "recluster path %lld", (long long)value);
       ctx->recl_path = (int)value;
       return KMPAR_OK;
   }
@@ -490,6 +491,19 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   if (rc) return rc;
   if (ws_bytes < need)
     return set_err(ctx, KMPAR_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  // The candidate capacity must fit an int, and step 8 must fit the CUs
+  // (rows in LDS or in global memory) unless the one-workgroup path is chosen.
+  const int64_t capT64 = 1 + (int64_t)rounds * cap_round_of(n, ell);
+  if (capT64 > INT32_MAX)
+    return set_err(ctx, KMPAR_E_INVAL, "candidate capacity %lld exceeds 2^31 - 1",
+                   (long long)capT64);
+  ReclPlan recl{};
+  const bool recl_ok =
+      recluster_plan((int)capT64, padded_dim(d), ctx->device >= 0 ? ctx->num_cu : kReclMaxBlocks,
+                     ctx->recl_path == 3, &recl);
+  if (!recl_ok && !(ctx->recl_path == 1 && recluster_block_lds((int)capT64, k) <= kReclBlockLdsMax))
+    return set_err(ctx, KMPAR_E_INVAL, "candidate capacity %lld too large for the recluster",
+                   (long long)capT64);
   if ((rc = device_ready(ctx))) return rc;
 
   DeviceGuard g(ctx->device);
@@ -497,7 +511,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   hipStream_t s = (hipStream_t)stream;
   const int N = (int)n, DP = padded_dim(d);
   const int cap_round = (int)cap_round_of(n, ell);
-  const int capT = 1 + rounds * cap_round;
+  const int capT = (int)capT64;
   InitLayout L = init_layout(ws, n, d, k, ell, rounds, dtype);
   kmpar_stats* st = stats ? stats : L.st;
   const uint64_t inst = 0;
@@ -557,15 +571,13 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   // Automatic: several workgroups (measured faster for a single instance at
   // the benchmark shapes: the one-workgroup pick loop is bound by its
   // 1024-thread FP64 scan and barriers); one workgroup only on request.
-  bool one_wg = false;
-  if (ctx->recl_path == 1) one_wg = recluster_block_lds(capT, k) <= kReclBlockLdsMax;
-  if (ctx->recl_path == 2) one_wg = false;
+  const bool one_wg =
+      !recl_ok || (ctx->recl_path == 1 && recluster_block_lds(capT, k) <= kReclBlockLdsMax);
   if (one_wg) {
     KMPAR_HIP(launch_recluster_block(L.CallT, capT, d, L.w, L.rs + rounds + 1, k, seed, inst,
                                      picks, centers, st, s));
   } else {
-    const int G = recluster_blocks(capT, DP, ctx->num_cu);
-    KMPAR_HIP(launch_recluster(L.Call, DP, capT, d, L.w, L.rs + rounds + 1, k, seed, inst, G,
+    KMPAR_HIP(launch_recluster(L.Call, DP, d, L.w, L.rs + rounds + 1, k, seed, inst, recl,
                                L.udraw, L.rpart, L.prow, picks, centers, st, s));
   }
   if (trace) {

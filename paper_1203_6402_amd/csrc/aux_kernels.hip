@@ -300,9 +300,9 @@ hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s) {
 // coherence is all the exchange needs, with no fences (on this chip an
 // agent-scope release or acquire writes back or invalidates the L2).  Every
 // wait has a spin limit, so every wave exits (status KMPAR_E_HIP).
-constexpr int kReclBlock = 256;
+constexpr int kReclBlock = 512;
 constexpr unsigned kSpinLimit = 1u << 22;
-constexpr size_t kReclLdsBudget = 120 * 1024;
+constexpr size_t kReclLdsBudget = 144 * 1024;
 constexpr unsigned long long kEmpty64 = ~0ull;
 constexpr unsigned kEmpty32 = ~0u;
 
@@ -342,7 +342,7 @@ struct ReclArgs {
   int k;
   uint64_t seed;
   uint64_t inst;
-  int slice_cap;       // LDS slice capacity (candidates per block)
+  int fit;             // candidates per block at most (LDS capacity)
   const double* u;     // [k] the draws U(seed, RECL, (s, 0, inst))
   double* part;        // [k][G] partial slots, all-ones on entry
   float* prow;         // [k][DP] row slots of the picks, all-ones on entry
@@ -357,6 +357,9 @@ __global__ void k_recl_draws(uint64_t seed, uint64_t inst, int k, double* u) {
   if (s < k) u[s] = philox_uniform(seed, kTagRecluster, (uint64_t)s, 0, inst);
 }
 
+// LROWS: the slice's rows sit in LDS (odd stride); otherwise they are read
+// from Call in global memory (candidate sets too large for the CUs' LDS).
+template <bool LROWS>
 __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
   extern __shared__ float4 lds4[];  // 16-byte aligned: cp is read as float4
   float* lds = reinterpret_cast<float*>(lds4);
@@ -365,23 +368,29 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
   __shared__ double sh_u, sh_base, sh_top;
   __shared__ int sh_pick, sh_owner, sh_failed, sh_stop;
   constexpr int NW = kReclBlock / kWave;
-  const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x, DP = a.DP, d = a.d;
+  const int b = blockIdx.x, tid = threadIdx.x, DP = a.DP, d = a.d;
   const int lane = tid % kWave, wv = tid / kWave;
-  const int DL = DP + 1;  // odd LDS row stride: lanes reading different rows miss each other's banks
+  const int DL = LROWS ? DP + 1 : DP;  // odd LDS row stride: rows land in different banks
   const int m = *a.rs_end;
+  // the blocks the candidate count needs (the grid is sized for the capacity)
+  const int G = min((int)gridDim.x, (m + a.fit - 1) / a.fit);
+  if (b >= G) return;
   const int lo = (int)((int64_t)b * m / G), hi = (int)((int64_t)(b + 1) * m / G);
   const int ns = hi - lo;
-  float* cp = lds;                                     // [DP] row of the latest pick
-  float* rows = cp + DP;                               // [slice_cap][DL]
-  float* E = rows + (size_t)a.slice_cap * DL;          // [slice_cap]
-  int* wl = reinterpret_cast<int*>(E + a.slice_cap);   // [slice_cap]
+  float* cp = lds;                                               // [DP] row of the latest pick
+  float* rows = LROWS ? cp + DP : nullptr;                       // [fit][DL]
+  float* E = cp + DP + (LROWS ? (size_t)a.fit * DL : 0);         // [fit]
+  int* wl = reinterpret_cast<int*>(E + a.fit);                   // [fit]
+  const float* grows = a.Call + (int64_t)lo * DP;                // the slice in global memory
   if (tid == 0) {
     sh_failed = 0;
     sh_stop = 0;
   }
-  for (int idx = tid; idx < ns * DP; idx += kReclBlock) {
-    const int j = idx / DP, e = idx - j * DP;
-    rows[j * DL + e] = a.Call[(int64_t)lo * DP + idx];
+  if constexpr (LROWS) {
+    for (int idx = tid; idx < ns * DP; idx += kReclBlock) {
+      const int j = idx / DP, e = idx - j * DP;
+      rows[j * DL + e] = grows[idx];
+    }
   }
   for (int j = tid; j < ns; j += kReclBlock) wl[j] = a.w[lo + j];
   // each thread owns a contiguous run of the slice (one candidate when the
@@ -402,15 +411,28 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
       // = acc), sixteen elements per step with the LDS reads issued first;
       // reads past the row stay inside the block's LDS and are masked.
       for (int j = rlo; j < rhi; ++j) {
-        const float* r = rows + (size_t)j * DL;
         float acc = 0.0f;
         for (int e0 = 0; e0 < DP; e0 += 16) {
           float xr[16];
           float4 c4[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) c4[q] = reinterpret_cast<const float4*>(cp + e0)[q];
+          if constexpr (LROWS) {
+            const float* r = rows + (size_t)j * DL;
 #pragma unroll
-          for (int q = 0; q < 16; ++q) xr[q] = r[e0 + q];
+            for (int q = 0; q < 16; ++q) xr[q] = r[e0 + q];
+          } else {
+            // whole float4s of the DP-padded row only: no read past it
+            const float4* r4 = reinterpret_cast<const float4*>(grows + (size_t)j * DP + e0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float4 v = (e0 + 4 * q < DP) ? r4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+              xr[4 * q] = v.x;
+              xr[4 * q + 1] = v.y;
+              xr[4 * q + 2] = v.z;
+              xr[4 * q + 3] = v.w;
+            }
+          }
 #pragma unroll
           for (int q = 0; q < 16; ++q) {
             const float cq = q % 4 == 0 ? c4[q / 4].x : q % 4 == 1 ? c4[q / 4].y
@@ -426,9 +448,8 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
     // block and the block total, all in one fixed order
     double v = 0.0;
     for (int j = rlo; j < rhi; ++j) v += (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
-    const double inc = wave_incl_scan(v);
-    double exw = __shfl_up(inc, 1, kWave);
-    if (lane == 0) exw = 0.0;
+    const double inc = wave_incl_scan_f64(v);
+    const double exw = wave_shr1_f64(inc);
     if (lane == kWave - 1) wtot[wv] = inc;
     __syncthreads();
     double wbase = 0.0, tot = 0.0;
@@ -453,10 +474,9 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
       const int q0 = min(G, lane * RG), q1 = min(G, q0 + RG);
       double ls = 0.0;
       for (int q = q0; q < q1; ++q) ls += gpart[q];
-      const double linc = wave_incl_scan(ls);
-      const double T = __shfl(linc, kWave - 1, kWave);
-      double run = __shfl_up(linc, 1, kWave);
-      if (lane == 0) run = 0.0;
+      const double linc = wave_incl_scan_f64(ls);
+      const double T = wave_read_f64(linc, kWave - 1);
+      double run = wave_shr1_f64(linc);
       const double thr = u * T;
       int own = -1, last_pos = -1;
       double lo_b = 0.0, hi_b = 0.0;
@@ -551,11 +571,11 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
       }
       const int jl = sh_pick;
       // hop 2 of round s: publish the row, then the outputs
+      const float* pr = LROWS ? rows + (size_t)jl * DL : grows + (size_t)jl * DP;
       if (tid < DP)
         __hip_atomic_store(reinterpret_cast<unsigned*>(&a.prow[(int64_t)s * DP + tid]),
-                           __float_as_uint(rows[(size_t)jl * DL + tid]), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      for (int e = tid; e < d; e += kReclBlock) a.centers[(int64_t)s * d + e] = rows[(size_t)jl * DL + e];
+                           __float_as_uint(pr[tid]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int e = tid; e < d; e += kReclBlock) a.centers[(int64_t)s * d + e] = pr[e];
       if (tid == 0) a.picks[s] = lo + jl;
     }
     made = s + 1;
@@ -591,28 +611,34 @@ hipError_t launch_recluster_block(const float* CallT, int capT, int d, const int
   KMPAR_RET_LAST();
 }
 
-int recluster_blocks(int capT, int DP, int num_cu) {
-  // Slices of at most one candidate per thread (the per-pick work inside a
-  // block is then one row fold and one scan step), more when the LDS budget
-  // or the CU count binds; every block must be resident at once.
-  const size_t per = (size_t)(DP + 1) * 4 + 8;
-  const int fit = (int)std::min<size_t>(kReclBlock, kReclLdsBudget / per);
+bool recluster_plan(int capT, int DP, int num_cu, bool global_rows, ReclPlan* p) {
+  // Slices of at most one candidate per thread with their rows in LDS (odd
+  // stride); when the CUs cannot hold every slice that way, all CUs take
+  // slices whose rows stay in global memory.  Every block must be resident
+  // at once, so the grid never exceeds the CU count.
+  const int gmax = std::min(num_cu, kReclMaxBlocks);
+  const size_t head = (size_t)DP * 4;
+  const size_t per_l = (size_t)(DP + 1) * 4 + 8;
+  int fit = (int)std::min<size_t>(kReclBlock, (kReclLdsBudget - head) / per_l);
   int G = (capT + fit - 1) / fit;
-  if (G > num_cu) G = num_cu;
-  if (G > kReclMaxBlocks) G = kReclMaxBlocks;
-  if (G < 1) G = 1;
-  return G;
+  if (!global_rows && G <= gmax) {
+    *p = ReclPlan{G, fit, true, head + (size_t)fit * per_l};
+    return true;
+  }
+  // global rows: one candidate per thread while the CUs suffice
+  G = std::min(gmax, (capT + kReclBlock - 1) / kReclBlock);
+  fit = (capT + G - 1) / G;
+  const size_t lds = head + (size_t)fit * 8;
+  if (lds > kReclLdsBudget) return false;
+  *p = ReclPlan{G, fit, false, lds};
+  return true;
 }
 
-size_t recluster_lds(int capT, int DP, int G) {
-  const int slice = (capT + G - 1) / G + 1;
-  return (size_t)slice * ((size_t)(DP + 1) * 4 + 8) + (size_t)DP * 4;
-}
-
-hipError_t launch_recluster(const float* Call, int DP, int capT, int d, const int* w,
-                            const int* rs_end, int k, uint64_t seed, uint64_t inst, int G,
+hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, const int* rs_end,
+                            int k, uint64_t seed, uint64_t inst, const ReclPlan& plan,
                             double* udraw, double* part, float* prow, int* picks,
                             float* centers, kmpar_stats* st, hipStream_t s) {
+  const int G = plan.G;
   hipLaunchKernelGGL(k_recl_draws, dim3((k + 255) / 256), dim3(256), 0, s, seed, inst, k, udraw);
   // every slot starts empty (all-ones); fill kernels, not memsets, so the
   // sequence can be captured in a graph
@@ -629,18 +655,21 @@ hipError_t launch_recluster(const float* Call, int DP, int capT, int d, const in
   a.k = k;
   a.seed = seed;
   a.inst = inst;
-  a.slice_cap = (capT + G - 1) / G + 1;
+  a.fit = plan.fit;
   a.u = udraw;
   a.part = part;
   a.prow = prow;
   a.picks = picks;
   a.centers = centers;
   a.st = st;
-  const size_t lds = recluster_lds(capT, DP, G);
-  e = hipFuncSetAttribute((const void*)k_recluster_grid, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds);
+  const void* fn = plan.lds_rows ? (const void*)k_recluster_grid<true>
+                                 : (const void*)k_recluster_grid<false>;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_recluster_grid, dim3(G), dim3(kReclBlock), lds, s, a);
+  if (plan.lds_rows)
+    hipLaunchKernelGGL(k_recluster_grid<true>, dim3(G), dim3(kReclBlock), plan.lds, s, a);
+  else
+    hipLaunchKernelGGL(k_recluster_grid<false>, dim3(G), dim3(kReclBlock), plan.lds, s, a);
   KMPAR_RET_LAST();
 }
 

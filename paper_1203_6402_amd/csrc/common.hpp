@@ -155,6 +155,36 @@ __device__ __forceinline__ V wave_incl_scan(V v) {
   return v;
 }
 
+// One DPP step on an FP64 value (both 32-bit halves): lanes whose source is
+// outside the row or whose row is masked off get 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Inclusive FP64 scan of a wave through DPP in a fixed order: prefix within
+// each 16-lane row (shifts 1, 2, 4, 8), then row 15 and row 31 broadcasts
+// carry the row totals forward.  Every lane of the wave must be active.
+__device__ __forceinline__ double wave_incl_scan_f64(double v) {
+  v += dpp_f64<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+// The value of lane l - 1 (0 in lane 0), by a whole-wave DPP shift.
+__device__ __forceinline__ double wave_shr1_f64(double v) { return dpp_f64<0x138, 0xF>(v); }
+// The value held by lane `src` (wave-uniform), via scalar reads.
+__device__ __forceinline__ double wave_read_f64(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 // Exclusive block scan of one value per thread; *total receives the block sum.
 // sh must hold BS/64 + 1 values.
 template <typename V, int BS>

@@ -145,11 +145,20 @@ hipError_t launch_recluster_block(const float* CallT, int capT, int d, const int
                                   const int* rs_end, int k, uint64_t seed, uint64_t inst,
                                   int* picks, float* centers, kmpar_stats* st, hipStream_t s);
 // Step-8 recluster over G workgroups (see aux_kernels.hip).
-int recluster_blocks(int capT, int DP, int num_cu);
-size_t recluster_lds(int capT, int DP, int G);
+// Grid of the multi-workgroup recluster for up to capT candidates of DP
+// floats on num_cu CUs: G blocks of at most `fit` candidates each, rows in
+// LDS or (lds_rows false, or forced by global_rows) in global memory, `lds`
+// dynamic LDS bytes per block.  False when even global rows do not fit.
+struct ReclPlan {
+  int G;
+  int fit;
+  bool lds_rows;
+  size_t lds;
+};
 constexpr int kReclMaxBlocks = 512;
-hipError_t launch_recluster(const float* Call, int DP, int capT, int d, const int* w,
-                            const int* rs_end, int k, uint64_t seed, uint64_t inst, int G,
+bool recluster_plan(int capT, int DP, int num_cu, bool global_rows, ReclPlan* p);
+hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, const int* rs_end,
+                            int k, uint64_t seed, uint64_t inst, const ReclPlan& plan,
                             double* udraw, double* part, float* prow, int* picks,
                             float* centers, kmpar_stats* st, hipStream_t s);
 hipError_t launch_pad_rows(const float* C, int m, int d, int DP, float* Cpad, hipStream_t s);

@@ -144,3 +144,19 @@ def test_create_rejects_bad_arguments(K):
     assert K._lib.kmpar_create(0, 5, ctypes.byref(h)) == K.E_INVAL
     assert K._lib.kmpar_create(-2, 0, ctypes.byref(h)) == K.E_INVAL
     assert K._lib.kmpar_create(0, 0, None) == K.E_INVAL
+
+
+def test_set_option_validation(K):
+    ctx = K.Context(None)
+    for path in (0, 1, 2, 3):
+        assert K._lib.kmpar_set_option(ctx._h, K.OPT_RECLUSTER_PATH, path) == 0
+    assert K._lib.kmpar_set_option(ctx._h, K.OPT_RECLUSTER_PATH, 4) == K.E_INVAL
+    assert K._lib.kmpar_set_option(ctx._h, K.OPT_RECLUSTER_PATH, -1) == K.E_INVAL
+    assert K._lib.kmpar_set_option(ctx._h, 7, 0) == K.E_INVAL
+
+
+def test_init_rejects_candidate_capacity_overflow(K):
+    # 1 + rounds * per-round capacity must fit an int32 (validated before any
+    # device work, so a host-only context reports it)
+    ctx = K.Context(None)
+    assert _call_init(K, ctx, n=2**30, d=8, k=10, ell=1e12, rounds=64, wsb=1 << 62) == K.E_INVAL

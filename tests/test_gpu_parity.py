@@ -170,10 +170,11 @@ def test_init_large_candidate_set_multiworkgroup_recluster(ctx):
     compare_init(X.astype(np.float64), r, tr, 40, 4000.0, 5, 8)
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 def test_recluster_paths_match_oracle(K, path):
-    # Both Step-8 implementations (one workgroup with pruned updates; several
-    # workgroups with grid barriers) replay against the oracle.
+    # Every Step-8 implementation (one workgroup with pruned updates; several
+    # workgroups with rows in LDS; several workgroups with rows in global
+    # memory) replays against the oracle.
     c = K.Context(0, K.MODE_PLAIN_FP32)
     c.set_option(K.OPT_RECLUSTER_PATH, path)
     X = synth.heavy_tailed(30000, 42, seed=21)
