@@ -104,7 +104,9 @@ struct InitLayout {
 };
 
 // Screen operand buffers for up to `tiles` tiles of 16 candidates.
-size_t screen_b_bytes(int tiles, int d) { return (size_t)tiles * 8 * 64 * 16 + 0 * d; }
+size_t screen_b_bytes(int tiles, int d) {
+  return (size_t)tiles * screen_ksteps(3, d) * 64 * 16;  // the widest split
+}
 
 // Bytes of prepared A operands for the screen of this dtype (0 if unused).
 size_t a_bytes(kmpar_dtype dt, bool rows, int64_t n, int d) {

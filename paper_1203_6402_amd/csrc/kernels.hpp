@@ -94,6 +94,8 @@ struct ScreenArgs {
 int screen_split(kmpar_dtype dt, bool centers_are_rows);
 int screen_ksteps(int split, int d);
 bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d);
+// Largest number of 32-wide k-steps of the screen's operands.
+constexpr int kScreenMaxKS = 16;
 // Candidate tiles per LDS chunk of the screen for KS k-steps, chunks per tag
 // group (groups of up to 16 tiles), and the tag bits that number a tile
 // within its group.

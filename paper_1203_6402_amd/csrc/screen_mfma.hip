@@ -212,25 +212,26 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
 }
 
 // --------------------------------------------------------------- the screen
-// Block = kWaves waves; wave w owns kRT tiles of 16 points (A operands held in
+// Block = kWaves waves; wave w owns KRT tiles of 16 points (A operands held in
 // registers for the pass).  Candidate tiles stream through two LDS buffers:
 // while the waves compute on chunk c, the direct global->LDS loads of chunk
 // c+1 are in flight.  Each accumulator starts at -ncg_j/2, so it ends as
 // acc = x.c - ncg_j/2 = -(lb - (1-2G)||x||^2)/2, and the smallest lb is the
 // largest acc.
-constexpr int kRT = 4;                 // 16-point row tiles per wave
 constexpr int kWaves = 4;              // waves per block
-constexpr int kWavePts = kRT * 16;     // points per wave
-constexpr int kBlockPts = kWaves * kWavePts;
 constexpr int kStageBytes = 32 * 1024; // LDS per staging buffer
+// 16-point row tiles per wave: four while the A operands of KS k-steps fit
+// the registers beside the accumulators and running maxima, two beyond 8.
+constexpr int screen_krt(int KS) { return KS <= 8 ? 4 : 2; }
+constexpr int kBlockPts = kWaves * 4 * 16;  // the largest block (256 points)
 
 typedef __attribute__((address_space(3))) void lds_void;
 typedef const __attribute__((address_space(1))) void gbl_void;
 
-// acc[r] = A[r] . B(tile q) - ncg_j / 2, for the wave's kRT row tiles.
-template <int KS, bool BCAST>
-__device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[kRT][KS], const u16x8* buf,
-                                          const float* ncs, int q, int lane, f32x4 (&acc)[kRT]) {
+// acc[r] = A[r] . B(tile q) - ncg_j / 2, for the wave's KRT row tiles.
+template <int KS, int KRT, bool BCAST>
+__device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[KRT][KS], const u16x8* buf,
+                                          const float* ncs, int q, int lane, f32x4 (&acc)[KRT]) {
   // ncs: -ncg/2 per candidate, four copies each when BCAST (one LDS read
   // then yields the accumulator's initial value)
   f32x4 cinit;
@@ -244,7 +245,7 @@ __device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[kRT][KS], const u1
   for (int s = 0; s < KS; ++s) {
     const bf16x8 b = __builtin_bit_cast(bf16x8, buf[(q * KS + s) * 64 + lane]);
 #pragma unroll
-    for (int r = 0; r < kRT; ++r)
+    for (int r = 0; r < KRT; ++r)
       acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop[r][s], b, s == 0 ? cinit : acc[r], 0, 0, 0);
   }
 }
@@ -253,10 +254,11 @@ __device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[kRT][KS], const u1
 // bits of each value are replaced by the tile's position tq first.  Tagged
 // values are finite, so med3 with FLT_MAX is their max, without the quieting
 // moves fmaxf would add.
-__device__ __forceinline__ void epilogue(const f32x4 (&acc)[kRT], uint32_t keep, uint32_t tq,
-                                         float (&s1)[kRT][4], float (&s2)[kRT][4]) {
+template <int KRT>
+__device__ __forceinline__ void epilogue(const f32x4 (&acc)[KRT], uint32_t keep, uint32_t tq,
+                                         float (&s1)[KRT][4], float (&s2)[KRT][4]) {
 #pragma unroll
-  for (int r = 0; r < kRT; ++r)
+  for (int r = 0; r < KRT; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const float v = __uint_as_float((__float_as_uint(acc[r][i]) & keep) | tq);
@@ -314,12 +316,19 @@ __device__ __forceinline__ float refine_dist(const T* x, const float* c, int d) 
   return r;
 }
 
+// The screen of block `blk` of the points of `a` (kWaves * KRT * 16 points).
 template <int SPLIT, int KS, typename T, bool DIRECT>
-__global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
+__device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
+  constexpr int KRT = screen_krt(KS);  // row tiles per wave
+  constexpr int WP = KRT * 16;         // points per wave
+  constexpr int BP = kWaves * WP;      // points per block
   constexpr int CT = screen_chunk_tiles(KS);        // candidate tiles per chunk
   static_assert(CT * KS * 64 * 16 <= kStageBytes, "chunk exceeds its staging buffer");
   constexpr int CHUNK_V = CT * KS * 64;             // 16-byte vectors per chunk
-  __shared__ u16x8 sB[2][CHUNK_V];
+  // Two full staging buffers whatever the chunk: after the pass each wave
+  // reuses a quarter of the 64 KB (kWaveStage bytes) for its own data.
+  __shared__ u16x8 sB[2][kStageBytes / 16];
+  static_assert(2 * kStageBytes == kWaves * kWaveStage, "wave quarters must tile the buffers");
   constexpr bool BCAST = CT <= 16;  // LDS for four copies of each bias
   __shared__ __attribute__((aligned(16))) float sN[2][CT * 16 * (BCAST ? 4 : 1)];
 
@@ -332,7 +341,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   }
   const int ntiles = (m + 15) / 16;
   const int nchunks = (ntiles + CT - 1) / CT;
-  const int wbase = blockIdx.x * kBlockPts + wave * kWavePts;
+  const int wbase = blk * BP + wave * WP;
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const u16x8* __restrict__ Bg = static_cast<const u16x8*>(a.B);
 
@@ -357,9 +366,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   // A operands of this wave's points, kept in registers for the pass: from
   // the prepared buffer, or straight from X when X is bf16 with d % 8 == 0
   // (its rows then already hold the operand bytes).
-  bf16x8 Aop[kRT][KS];
+  bf16x8 Aop[KRT][KS];
 #pragma unroll
-  for (int r = 0; r < kRT; ++r) {
+  for (int r = 0; r < KRT; ++r) {
     const int tile = wbase / 16 + r;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -386,10 +395,10 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   static_assert((1 << TB) >= GC * CT, "tag too narrow for a group");
   uint32_t keep;
   asm volatile("v_mov_b32 %0, %1" : "=v"(keep) : "s"(~((1u << TB) - 1u)));
-  float s1[kRT][4], s2[kRT][4], c1[kRT][4], c2[kRT][4];
-  int ix[kRT][4];
+  float s1[KRT][4], s2[KRT][4], c1[KRT][4], c2[KRT][4];
+  int ix[KRT][4];
 #pragma unroll
-  for (int r = 0; r < kRT; ++r)
+  for (int r = 0; r < KRT; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       s1[r][i] = -INFINITY;
@@ -418,7 +427,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
     const uint32_t t0 = cg * CT;   // tag of the chunk's first tile
     if (cg == 0) {
 #pragma unroll
-      for (int r = 0; r < kRT; ++r)
+      for (int r = 0; r < KRT; ++r)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           c1[r][i] = -INFINITY;
@@ -428,26 +437,26 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
     // Software pipeline: the MFMAs of tile q+1 are issued before the
     // epilogue of tile q, so matrix and vector units overlap within a wave
     // (two accumulator sets, unrolled by two so no copies are needed).
-    f32x4 acc0[kRT], acc1[kRT];
-    mfma_tile<KS, BCAST>(Aop, buf, ncs, 0, lane, acc0);
+    f32x4 acc0[KRT], acc1[KRT];
+    mfma_tile<KS, KRT, BCAST>(Aop, buf, ncs, 0, lane, acc0);
     int q = 0;
     for (; q + 2 < nt; q += 2) {
-      mfma_tile<KS, BCAST>(Aop, buf, ncs, q + 1, lane, acc1);
+      mfma_tile<KS, KRT, BCAST>(Aop, buf, ncs, q + 1, lane, acc1);
       epilogue(acc0, keep, t0 + q, c1, c2);
-      mfma_tile<KS, BCAST>(Aop, buf, ncs, q + 2, lane, acc0);
+      mfma_tile<KS, KRT, BCAST>(Aop, buf, ncs, q + 2, lane, acc0);
       epilogue(acc1, keep, t0 + q + 1, c1, c2);
       // Issue order: the operand reads first, then every MFMA followed by
       // three vector instructions, so that one wave keeps both the matrix
       // and the vector pipes busy.
       __builtin_amdgcn_sched_group_barrier(0x100, 2 * (KS + 1), 0);
 #pragma unroll
-      for (int g = 0; g < 2 * KS * kRT; ++g) {
+      for (int g = 0; g < 2 * KS * KRT; ++g) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
       }
     }
     if (q + 1 < nt) {
-      mfma_tile<KS, BCAST>(Aop, buf, ncs, q + 1, lane, acc1);
+      mfma_tile<KS, KRT, BCAST>(Aop, buf, ncs, q + 1, lane, acc1);
       epilogue(acc0, keep, t0 + q, c1, c2);
       epilogue(acc1, keep, t0 + q + 1, c1, c2);
     } else {
@@ -457,7 +466,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
     // with the running maximum keeps the earlier (lower) id.
     if (cg == GC - 1 || c + 1 == nchunks) {
 #pragma unroll
-    for (int r = 0; r < kRT; ++r)
+    for (int r = 0; r < KRT; ++r)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float v1 = c1[r][i];
@@ -475,7 +484,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   // each wave works in its own quarter of them.
   __syncthreads();
   const int p = wbase + lane;
-  const bool valid = p < a.n;
+  const bool valid = lane < WP && p < a.n;  // lanes past the wave's points idle
   const float nx = valid ? a.norms[p] : 0.0f;
   const float D = (a.first || !valid) ? INFINITY : a.D2[p];
   char* xw = reinterpret_cast<char*>(&sB[0][0]) + wave * kWaveStage;
@@ -486,9 +495,9 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   // reads the 16 entries of point p and merges them in column order.  Of two
   // equal maxima the earlier column is kept; no decision depends on which,
   // since then lb2 = lbmin <= r1 and the point is listed.
-  f32x4* M = reinterpret_cast<f32x4*>(xw);  // [64 points][16 columns]
+  f32x4* M = reinterpret_cast<f32x4*>(xw);  // [WP points][16 columns]
 #pragma unroll
-  for (int r = 0; r < kRT; ++r)
+  for (int r = 0; r < KRT; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int pl = r * 16 + (lane / 16) * 4 + i;
@@ -513,10 +522,10 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   // This wave's rows (raw elements) go to its quarter: full waves stage them
   // in groups of R (a multiple of 16, so every group is whole 16-byte units);
   // the one partial wave of X reads its rows from global memory instead.
-  const int nvalid = max(0, min(kWavePts, a.n - wbase));
+  const int nvalid = max(0, min(WP, a.n - wbase));
   const int rowb = d * (int)sizeof(T);  // <= 1 KB, so R >= 16
-  const int R = min(kWavePts, (kWaveStage / rowb) & ~15);  // rows per staging group
-  const bool staged = nvalid == kWavePts;
+  const int R = min(WP, (kWaveStage / rowb) & ~15);  // rows per staging group
+  const bool staged = nvalid == WP;
   if (staged) stage_rows<T>(xw, X, wbase, R, rowb, lane);
 
   // One lane per point: decide, refine, fold or list.  The refinement
@@ -530,8 +539,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   const float* crow = a.C + (int64_t)(id0 + max(j1, 0)) * a.DP;
   float r1 = 0.0f;
   if (staged) {
-    for (int c0 = 0; c0 < kWavePts; c0 += R) {
-      const int nr = min(R, kWavePts - c0);
+    for (int c0 = 0; c0 < WP; c0 += R) {
+      const int nr = min(R, WP - c0);
       if (c0 > 0) {
         __builtin_amdgcn_wave_barrier();  // the previous group has been read
         stage_rows<T>(xw, X, wbase + c0, nr, rowb, lane);
@@ -570,6 +579,11 @@ __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
   }
 }
 
+template <int SPLIT, int KS, typename T, bool DIRECT>
+__global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
+  screen_body<SPLIT, KS, T, DIRECT>(a, blockIdx.x);
+}
+
 // Adds the previous pass's listed count to the stats and clears it.
 __global__ void k_list_reset(int* list_len, kmpar_stats* st) {
   if (threadIdx.x == 0) {
@@ -580,7 +594,8 @@ __global__ void k_list_reset(int* list_len, kmpar_stats* st) {
 
 template <int SPLIT, int KS, typename T>
 static void launch_one(const ScreenArgs& a, hipStream_t s) {
-  const int blocks = (a.n + kBlockPts - 1) / kBlockPts;
+  constexpr int BP = kWaves * screen_krt(KS) * 16;
+  const int blocks = (a.n + BP - 1) / BP;
   if (a.Apre)
     hipLaunchKernelGGL((k_screen<SPLIT, KS, T, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
   else
@@ -598,6 +613,14 @@ static hipError_t launch_split(int KS, const ScreenArgs& a, hipStream_t s) {
     case 6: launch_one<SPLIT, 6, T>(a, s); break;
     case 7: launch_one<SPLIT, 7, T>(a, s); break;
     case 8: launch_one<SPLIT, 8, T>(a, s); break;
+    case 9: launch_one<SPLIT, 9, T>(a, s); break;
+    case 10: launch_one<SPLIT, 10, T>(a, s); break;
+    case 11: launch_one<SPLIT, 11, T>(a, s); break;
+    case 12: launch_one<SPLIT, 12, T>(a, s); break;
+    case 13: launch_one<SPLIT, 13, T>(a, s); break;
+    case 14: launch_one<SPLIT, 14, T>(a, s); break;
+    case 15: launch_one<SPLIT, 15, T>(a, s); break;
+    case 16: launch_one<SPLIT, 16, T>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -618,7 +641,8 @@ static hipError_t launch_prep_a_split(int KS, const void* X, const float* rsc, i
 #define KMPAR_PA(V) \
   case V: launch_prep_a_one<SPLIT, V, T>(X, rsc, n, d, Apre, s); break;
     KMPAR_PA(1) KMPAR_PA(2) KMPAR_PA(3) KMPAR_PA(4) KMPAR_PA(5) KMPAR_PA(6) KMPAR_PA(7)
-    KMPAR_PA(8)
+    KMPAR_PA(8) KMPAR_PA(9) KMPAR_PA(10) KMPAR_PA(11) KMPAR_PA(12) KMPAR_PA(13) KMPAR_PA(14)
+    KMPAR_PA(15) KMPAR_PA(16)
 #undef KMPAR_PA
     default: return hipErrorInvalidValue;
   }
@@ -650,7 +674,8 @@ static hipError_t launch_first_split(int KS, const void* X, const float* rsc, in
 #define KMPAR_FP(V) \
   case V: return launch_first_one<SPLIT, V, T, true>(X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s);
     KMPAR_FP(1) KMPAR_FP(2) KMPAR_FP(3) KMPAR_FP(4) KMPAR_FP(5) KMPAR_FP(6) KMPAR_FP(7)
-    KMPAR_FP(8)
+    KMPAR_FP(8) KMPAR_FP(9) KMPAR_FP(10) KMPAR_FP(11) KMPAR_FP(12) KMPAR_FP(13) KMPAR_FP(14)
+    KMPAR_FP(15) KMPAR_FP(16)
 #undef KMPAR_FP
   }
   return hipErrorInvalidValue;
@@ -708,7 +733,8 @@ static hipError_t launch_prep_split(int KS, const float* C, int DP, int d, const
                        m_host, om2g, b, ncg);                                                   \
     break;
     KMPAR_PREP(1) KMPAR_PREP(2) KMPAR_PREP(3) KMPAR_PREP(4) KMPAR_PREP(5) KMPAR_PREP(6)
-    KMPAR_PREP(7) KMPAR_PREP(8)
+    KMPAR_PREP(7) KMPAR_PREP(8) KMPAR_PREP(9) KMPAR_PREP(10) KMPAR_PREP(11) KMPAR_PREP(12)
+    KMPAR_PREP(13) KMPAR_PREP(14) KMPAR_PREP(15) KMPAR_PREP(16)
 #undef KMPAR_PREP
     default: return hipErrorInvalidValue;
   }
@@ -725,7 +751,7 @@ int screen_ksteps(int split, int d) { return split ? (split * d + 31) / 32 : 0; 
 
 bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d) {
   const int sp = screen_split(dt, centers_are_rows);
-  return sp != 0 && screen_ksteps(sp, d) <= 8;
+  return sp != 0 && screen_ksteps(sp, d) <= kScreenMaxKS;
 }
 
 // Relative error budget of the screen, as a multiple of S = ||x||^2 + ||c||^2:

@@ -49,7 +49,10 @@ def _same_init(a, b):
 @pytest.mark.parametrize("n,d,k,ell,rounds,kind", [
     (10000, 15, 50, 100.0, 5, "gauss"),     # GaussMixture, split-3 screen, K = 64
     (20011, 42, 60, 120.0, 5, "heavy"),     # KDD-shaped heavy tails, K = 128
-    (5003, 85, 40, 80.0, 4, "sigma"),       # largest split-3 row (K = 256)
+    (6007, 30, 40, 80.0, 4, "heavy"),       # K = 96: chunks shorter than the staging buffer
+    (5003, 85, 40, 80.0, 4, "sigma"),       # split-3 row of K = 256, four row tiles
+    (4001, 128, 30, 60.0, 3, "sigma"),      # K = 384: two row tiles per wave
+    (2503, 170, 20, 50.0, 3, "heavy"),      # widest split-3 row (K = 512)
     (3001, 3, 20, 40.0, 5, "gauss"),        # tiny d
 ])
 def test_refined_equals_plain_f32(plain, refined, n, d, k, ell, rounds, kind):
