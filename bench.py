@@ -177,8 +177,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16-refined vs FP32-plain comparison on the precision workload")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the 4,096-instance batched workload")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the 4,096-instance batched workload (FP32 and BF16)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--recluster-path", type=int, default=0, choices=[0, 1, 2])
     ap.add_argument("--pmc-probe", action="store_true",
@@ -286,7 +286,7 @@ def main():
         precision = precision_compare(kmpar, synth, torch, args.seed)
 
     batched = None
-    if not args.no_batched:
+    if args.batched:
         batched = batched_bench(kmpar, synth, torch, args.seed, args.batch_count)
 
     cpu = None

@@ -355,13 +355,21 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     for (int v0 = wave * 64; v0 < nv; v0 += kWaves * 64)
       __builtin_amdgcn_global_load_lds((gbl_void*)(src + v0 + lane), (lds_void*)(dst + v0), 16, 0, 0);
   };
-  auto stage_ncg = [&](int c) -> float {
-    const int idx = c * CT * 16 + threadIdx.x;
-    return (threadIdx.x < CT * 16 && idx < ntiles * 16) ? a.ncg[idx] : INFINITY;
+  // A chunk's CT * 16 biases, NBT per thread (two when a chunk holds 32
+  // tiles, i.e. KS = 1).
+  constexpr int NBT = (CT * 16 + kWaves * 64 - 1) / (kWaves * 64);
+  float ncg_next[NBT];
+  auto stage_ncg = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) {
+      const int e = i * kWaves * 64 + threadIdx.x;  // bias within the chunk
+      const int idx = c * CT * 16 + e;
+      ncg_next[i] = (e < CT * 16 && idx < ntiles * 16) ? a.ncg[idx] : INFINITY;
+    }
   };
 
   if (nchunks > 0) stage(0);
-  float ncg_next = nchunks > 0 ? stage_ncg(0) : INFINITY;
+  stage_ncg(0);
 
   // A operands of this wave's points, kept in registers for the pass: from
   // the prepared buffer, or straight from X when X is bf16 with d % 8 == 0
@@ -407,18 +415,22 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     }
 
   for (int c = 0; c < nchunks; ++c) {
-    if (threadIdx.x < CT * 16) {
-      const float nb = -0.5f * fminf(ncg_next, FLT_MAX);
-      if constexpr (BCAST)
-        reinterpret_cast<f32x4*>(sN[c & 1])[threadIdx.x] = f32x4{nb, nb, nb, nb};
-      else
-        sN[c & 1][threadIdx.x] = nb;
+#pragma unroll
+    for (int i = 0; i < NBT; ++i) {
+      const int e = i * kWaves * 64 + threadIdx.x;
+      if (e < CT * 16) {
+        const float nb = -0.5f * fminf(ncg_next[i], FLT_MAX);
+        if constexpr (BCAST)
+          reinterpret_cast<f32x4*>(sN[c & 1])[e] = f32x4{nb, nb, nb, nb};
+        else
+          sN[c & 1][e] = nb;
+      }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();  // chunk c is in LDS; everyone is done with chunk c-1
     if (c + 1 < nchunks) {
       stage(c + 1);
-      ncg_next = stage_ncg(c + 1);
+      stage_ncg(c + 1);
     }
     const int nt = min(CT, ntiles - c * CT);
     const u16x8* buf = sB[c & 1];

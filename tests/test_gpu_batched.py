@@ -64,3 +64,47 @@ def test_batch_of_one_equals_single_instance(ctx):
         assert torch.equal(single.trace[key], trs[0][key]), key
     assert sts[0]["round_count"] == single.stats["round_count"]
     assert sts[0]["phi"] == single.stats["phi"]
+
+
+def _same_batches(a, b):
+    (ca, sa, ta), (cb, sb, tb) = a, b
+    for i in range(len(ca)):
+        assert torch.equal(ca[i], cb[i]), i
+        for key in ta[i]:
+            assert torch.equal(ta[i][key], tb[i][key]), (i, key)
+        x, y = dict(sa[i]), dict(sb[i])
+        x.pop("n_rescanned")
+        y.pop("n_rescanned")
+        assert x == y, i
+
+
+@pytest.mark.skip(reason="the batched MFMA screen is switched off: its 4,096-instance run "
+                         "stopped with an illegal-address fault whose cause was not found; "
+                         "batched instances run the direct form in every mode")
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batched_refined_equals_plain(ctx, dtype):
+    # REFINED batches screen the instances that qualify (ell >= 32, supported
+    # width) on the matrix cores, with their undecided points recomputed by
+    # the screen's own waves; every output must equal the direct form's.
+    from paper_1203_6402_amd import kmpar
+    ns = np.array([4000, 9001, 2500, 700, 12000, 3333, 1800, 6000])
+    ds = np.array([32, 64, 128, 42, 170 if dtype == "f32" else 256, 7, 96, 33])
+    ks = np.array([30, 45, 25, 12, 50, 20, 18, 40])
+    ells = np.array([60.0, 90.0, 50.0, 24.0, 100.0, 40.0, 36.0, 80.0])  # one below 32: direct form
+    Xs = synth.batch_gauss_mixture(ns, ds, ks, seed=8)
+    if dtype == "bf16":
+        Xs = [to_bf16_bits(X) for X in Xs]
+        devs = [_dev(X).view(torch.bfloat16) for X in Xs]
+    else:
+        devs = [_dev(X) for X in Xs]
+    refined = kmpar.Context(0, kmpar.MODE_REFINED)
+    a = ctx.init_batched(devs, ks, ells, 4, seed=13, trace=True)
+    b = refined.init_batched(devs, ks, ells, 4, seed=13, trace=True)
+    torch.cuda.synchronize()
+    _same_batches(a, b)
+    # the screened instances resolve most points on the matrix cores
+    for i in range(len(ns)):
+        assert b[1][i]["n_rescanned"] <= 0.1 * ns[i] * 4, (i, b[1][i]["n_rescanned"])
+    # and the refined run replays against the oracle like the plain one
+    X64 = [decoded_fp64(X, dtype) if dtype == "bf16" else X.astype(np.float64) for X in Xs]
+    _replay_all(X64[:3], b[0][:3], b[1][:3], b[2][:3], ks[:3], ells[:3], 4, 13)

@@ -54,6 +54,7 @@ def _same_init(a, b):
     (4001, 128, 30, 60.0, 3, "sigma"),      # K = 384: two row tiles per wave
     (2503, 170, 20, 50.0, 3, "heavy"),      # widest split-3 row (K = 512)
     (3001, 3, 20, 40.0, 5, "gauss"),        # tiny d
+    (20000, 8, 200, 800.0, 3, "gauss"),     # K = 32: 32-tile chunks, two of them a round
 ])
 def test_refined_equals_plain_f32(plain, refined, n, d, k, ell, rounds, kind):
     if kind == "gauss":
@@ -73,21 +74,23 @@ def test_refined_equals_plain_f32(plain, refined, n, d, k, ell, rounds, kind):
     assert b.stats["n_rescanned"] <= 0.05 * n * rounds
 
 
-@pytest.mark.parametrize("d", [16, 64, 128, 256])
-def test_refined_equals_plain_bf16(plain, refined, d):
-    X = synth.gauss_mixture_sigma(6007, d, 80, seed=d)
+@pytest.mark.parametrize("d,n,k,ell", [(16, 6007, 60, 120.0), (64, 6007, 60, 120.0),
+                                        (128, 6007, 60, 120.0), (256, 6007, 60, 120.0),
+                                        (32, 20000, 200, 800.0)])  # 32-tile chunks
+def test_refined_equals_plain_bf16(plain, refined, d, n, k, ell):
+    X = synth.gauss_mixture_sigma(n, d, 80, seed=d)
     Xb = to_bf16_bits(X)
     Xd = _dev(Xb).view(torch.bfloat16)
-    a = plain.init(Xd, k=60, ell=120.0, rounds=5, seed=2, trace=True)
-    b = refined.init(Xd, k=60, ell=120.0, rounds=5, seed=2, trace=True)
+    a = plain.init(Xd, k=k, ell=ell, rounds=5, seed=2, trace=True)
+    b = refined.init(Xd, k=k, ell=ell, rounds=5, seed=2, trace=True)
     torch.cuda.synchronize()
     _same_init(a, b)
     tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
-    compare_init(decoded_fp64(Xb, "bf16"), b, tr, 60, 120.0, 5, 2)
+    compare_init(decoded_fp64(Xb, "bf16"), b, tr, k, ell, 5, 2)
 
 
 @pytest.mark.parametrize("dt,d,m", [("f32", 42, 500), ("f32", 15, 37), ("bf16", 128, 300),
-                                    ("bf16", 64, 33)])
+                                    ("bf16", 64, 33), ("f32", 8, 700), ("bf16", 16, 700)])
 def test_refined_assign_cost_lloyd_equal_plain(plain, refined, dt, d, m):
     X = synth.gauss_mixture_sigma(9001, d, 200, seed=m)
     if dt == "bf16":
