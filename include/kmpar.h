@@ -209,7 +209,8 @@ int kmpar_workspace_size_batched(const kmpar_ctx* ctx, const kmpar_instance* ins
  * `inst_host` and `inst_dev` hold the same table: the host copy sizes the
  * launches, the device copy is what the kernels read (the library copies
  * nothing between host and device).  All instances share `dtype`; the
- * distance pass runs in the context's mode (PLAIN_FP32 direct form).
+ * distance pass is the FP32 direct form whatever the context's mode (a
+ * REFINED context gives the same results, as its decisions equal PLAIN's).
  * Limits per instance as for kmpar_init; rounds must be equal across the
  * batch.  Per-instance stats are written when inst[i].stats is not NULL.
  * `traces_dev` (nullable) is a DEVICE array of `count` kmpar_trace records
