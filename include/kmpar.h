@@ -42,9 +42,11 @@ typedef enum kmpar_dtype { KMPAR_F32 = 0, KMPAR_BF16 = 1, KMPAR_FP8_E4M3 = 2 } k
 
 /* PLAIN_FP32: every point-center distance in FP32 direct form
  * sum_j (x_j - c_j)^2.  REFINED: distances screened on the matrix cores
- * from ||x||^2 - 2 x.c + ||c||^2 with a rigorous error band, and every
- * decision the band cannot settle recomputed in FP32 direct form, so both
- * modes take the same decisions up to FP32 rounding. */
+ * from ||x||^2 - 2 x.c + ||c||^2 with a rigorous error band (bf16 operands:
+ * BF16 rows and the codes of FP8 rows as they are, FP32 values split into
+ * two or three bf16 terms; FP8 row scales applied after the products), and
+ * every decision the band cannot settle recomputed in FP32 direct form, so
+ * both modes return the same results bit for bit. */
 typedef enum kmpar_mode { KMPAR_MODE_PLAIN_FP32 = 0, KMPAR_MODE_REFINED = 1 } kmpar_mode;
 
 typedef enum kmpar_status {

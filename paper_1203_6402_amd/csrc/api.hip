@@ -99,6 +99,7 @@ struct InitLayout {
   int* list_len;
   void* B;
   float* ncg;
+  float* scg;
   void* Apre;
   size_t bytes;
 };
@@ -146,6 +147,7 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.list_len = c.take<int>(4);
   L.B = c.take<char>(screen_b_bytes(tiles, d));
   L.ncg = c.take<float>((size_t)tiles * 16);
+  L.scg = c.take<float>((size_t)tiles * 16);
   L.Apre = c.take<char>(a_bytes(dt, true, n, d));
   L.bytes = c.off;
   return L;
@@ -163,6 +165,7 @@ struct AssignLayout {
   int* list_len;
   void* B;
   float* ncg;
+  float* scg;
   void* Apre;
   size_t bytes;
 };
@@ -192,6 +195,7 @@ AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op, kmpar
   L.list_len = c.take<int>(4);
   L.B = c.take<char>(screen_b_bytes(tiles, d));
   L.ncg = c.take<float>((size_t)tiles * 16);
+  L.scg = c.take<float>((size_t)tiles * 16);
   L.Apre = c.take<char>(a_bytes(dt, false, n, d));
   L.bytes = c.off;
   return L;
@@ -285,13 +289,18 @@ hipError_t timed_fold(kmpar_ctx* ctx, int slot, kmpar_dtype dt, int DP, const Fo
 
 // One REFINED distance pass: B operands, screen, direct-form rescan of the
 // points the screen listed.  `fa` describes the same pass for the direct form.
+// FP8 rows also take the candidates' scales (scg) and, against rows of X,
+// the candidates' point ids (cand), whose codes are the B operands.
 hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const FoldArgs& fa,
                         int max_tiles, const float* norms, const void* Apre, void* B, float* ncg,
-                        int* list, int* list_len, kmpar_stats* st, hipStream_t s) {
+                        const int* cand, float* scg, int* list, int* list_len, kmpar_stats* st,
+                        hipStream_t s) {
   const int KS = screen_ksteps(split, fa.d);
-  const float om2g = 1.0f - 2.0f * screen_g(split, fa.d);
-  hipError_t e = launch_prep_b(split, KS, fa.C, DP, fa.d, fa.rs, fa.m_host, max_tiles, om2g, B,
-                               ncg, s);
+  const float om2g = 1.0f - 2.0f * screen_g(dt, split, fa.d);
+  const bool fp8 = dt == KMPAR_FP8_E4M3;
+  hipError_t e = launch_prep_b(dt, split, KS, fa.C, DP, fa.d, fa.rs, fa.m_host, max_tiles, om2g, B,
+                               ncg, fa.X, fa.row_scale, fp8 ? cand : nullptr,
+                               fp8 ? scg : nullptr, s);
   if (e != hipSuccess) return e;
   ScreenArgs sa{};
   sa.X = fa.X;
@@ -306,6 +315,7 @@ hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const
   sa.Apre = Apre;
   sa.B = B;
   sa.ncg = ncg;
+  sa.scg = fp8 ? scg : nullptr;
   sa.norms = norms;
   sa.oneminus2g = om2g;
   sa.D2 = fa.D2;
@@ -558,7 +568,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
     fa.rs = L.rs + t;
     if (refined) {
       KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (cap_round + 15) / 16, L.norms, Apre, L.B,
-                             L.ncg, L.list, L.list_len, st, s));
+                             L.ncg, L.cand_point, L.scg, L.list, L.list_len, st, s));
     } else {
       KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
     }
@@ -636,7 +646,7 @@ static int assign_pass(kmpar_ctx* ctx, kmpar_dtype dtype, const AssignLayout& L,
       Apre = L.Apre;
     }
     KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (m + 15) / 16, L.norms, Apre, L.B, L.ncg,
-                           L.list, L.list_len, nullptr, s));
+                           nullptr, L.scg, L.list, L.list_len, nullptr, s));
   } else {
     KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
   }

@@ -98,9 +98,12 @@ struct Elem<bf16_t> {
     return decode_bf16(X[idx].bits);
   }
 };
+// An FP8 element is fl(q * s): the product is rounded once, never fused into
+// the arithmetic that uses it (every kernel then sees the same values).
 template <>
 struct Elem<fp8_t> {
   static __device__ __forceinline__ float get(const fp8_t* X, int64_t idx, float scale) {
+#pragma clang fp contract(off)
     return decode_e4m3(X[idx].bits) * scale;
   }
 };

@@ -27,6 +27,15 @@
 // assumes no overflow and negligible underflow: points with ||x||^2 outside
 // [2^-100, 2^100] are always listed, and candidates with ||c||^2 > 2^100
 // get a trivial bound (every point refines or lists them).
+//
+// FP8 rows (e4m3 codes q with a row scale s, element = fl(s * q)) enter the
+// matrix cores as their codes, which bf16 holds exactly: against rows of X
+// the products q_x . q_c are exact, against FP32 centers the centers take
+// the two-term split.  The accumulators start at zero and each value is
+// then scaled, acc * (s_x * s_c) - ncg_c / 2 (s_c = 1 for centers), which
+// the budget of G covers with the roundings of the scales.  Rows whose
+// scale lies outside [2^-63, 2^63] are listed; candidates whose scale does
+// get a trivial bound.
 #include <float.h>
 #include <cmath>
 #include <math.h>
@@ -50,6 +59,35 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Rows whose screen operands are codes with a separate per-row scale.
+template <typename T>
+struct ScaledRows {
+  static constexpr bool value = false;
+};
+template <>
+struct ScaledRows<fp8_t> {
+  static constexpr bool value = true;
+};
+// Range of row scales inside which the scaled epilogue cannot overflow.
+constexpr float kScaleMin = 0x1p-63f;
+constexpr float kScaleMax = 0x1p63f;
+
+// bf16 bits of an e4m3 code's value (exact: four significant bits).
+__device__ __forceinline__ uint16_t code_bf16(uint8_t q) {
+  return (uint16_t)(__float_as_uint(decode_e4m3(q)) >> 16);
+}
+
+// Element idx as the A operand takes it: the decoded element, or the
+// unscaled code of an FP8 row.
+template <typename T>
+__device__ __forceinline__ float op_elem(const T* X, int64_t idx, float decoded) {
+  return decoded;
+}
+template <>
+__device__ __forceinline__ float op_elem<fp8_t>(const fp8_t* X, int64_t idx, float) {
+  return decode_e4m3(X[idx].bits);
+}
 
 // Operand k of the screen's K axis.  SPLIT 1: A = x, B = c (both exact in
 // bf16).  SPLIT 2: A = [x | x], B = [hi(c) | lo(c)].  SPLIT 3: A = [hi(x) |
@@ -76,10 +114,15 @@ __device__ __forceinline__ uint16_t b_elem(float c, int part) {
 // One wave per tile of 16 candidates: writes KS k-steps of 64 lanes x 8 bf16
 // in the lane order the MFMA B operand uses (lane l: candidate l%16,
 // k = s*32 + (l/16)*8 + e), plus ncg_j = (1 - 2G) ||c_j||^2 (+inf past m).
-template <int SPLIT, int KS>
+// CODES: the operands are the e4m3 codes of X row cand[id0 + j] (SPLIT 1).
+// scg (nullable) receives each candidate's scale: the row scale with CODES,
+// 1 for FP32 centers, 0 past m or when the scale is outside the screen's
+// range (then the bias is trivial as well).
+template <int SPLIT, int KS, bool CODES>
 __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, const int* rs,
                                                int m_host, float oneminus2g, u16x8* B,
-                                               float* ncg) {
+                                               float* ncg, const fp8_t* Xc, const float* rsc,
+                                               const int* cand, float* scg) {
   int id0 = 0, m = m_host;
   if (rs) {
     id0 = rs[0];
@@ -91,6 +134,8 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
   const int j = q * 16 + (lane % 16);
   const bool valid = j < m;
   const float* c = C + (int64_t)(id0 + (valid ? j : 0)) * DP;
+  int64_t xrow = 0;
+  if constexpr (CODES) xrow = valid ? (int64_t)cand[id0 + j] * d : 0;
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     u16x8 v;
@@ -98,7 +143,10 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
     for (int e = 0; e < 8; ++e) {
       const int k = s * 32 + (lane / 16) * 8 + e;
       const int part = k / d, coord = k - part * d;
-      v[e] = (valid && part < SPLIT) ? b_elem<SPLIT>(c[coord], part) : (uint16_t)0;
+      if constexpr (CODES)
+        v[e] = (valid && part < SPLIT) ? code_bf16(Xc[xrow + coord].bits) : (uint16_t)0;
+      else
+        v[e] = (valid && part < SPLIT) ? b_elem<SPLIT>(c[coord], part) : (uint16_t)0;
     }
     B[((int64_t)q * KS + s) * 64 + lane] = v;
   }
@@ -106,9 +154,13 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
     float nc = 0.0f;
     if (valid)
       for (int e = 0; e < d; ++e) nc = fmaf(c[e], c[e], nc);
-    // Past m: +inf (never the maximum).  Beyond 2^100 (or not finite): a
-    // bias that makes the candidate's lower bound -inf.
-    ncg[j] = !valid ? INFINITY : (nc <= kNormMax ? oneminus2g * nc : -FLT_MAX);
+    float sc = 1.0f;
+    if constexpr (CODES) sc = valid ? rsc[cand[id0 + j]] : 0.0f;
+    const bool sc_ok = sc >= kScaleMin && sc <= kScaleMax;
+    // Past m: +inf (never the maximum).  Beyond 2^100 (or not finite), or a
+    // scale out of range: a bias that makes the candidate's lower bound -inf.
+    ncg[j] = !valid ? INFINITY : (nc <= kNormMax && sc_ok ? oneminus2g * nc : -FLT_MAX);
+    if (scg) scg[j] = (valid && sc_ok) ? sc : 0.0f;
   }
 }
 
@@ -136,7 +188,9 @@ __global__ __launch_bounds__(256) void k_prep_a(const T* X, const float* row_sca
     for (int e = 0; e < 8; ++e) {
       const int k = s * 32 + (lane / 16) * 8 + e;
       const int part = k / d, coord = k - part * d;
-      v[e] = (valid && part < SPLIT) ? a_elem<SPLIT>(xs[row * d + coord], part) : (uint16_t)0;
+      v[e] = (valid && part < SPLIT)
+                 ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * d + coord]), part)
+                 : (uint16_t)0;
     }
     Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
   }
@@ -204,7 +258,9 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
       for (int e = 0; e < 8; ++e) {
         const int k = s * 32 + (lane / 16) * 8 + e;
         const int part = k / d, coord = k - part * d;
-        v[e] = (valid && part < SPLIT) ? a_elem<SPLIT>(xs[row * d + coord], part) : (uint16_t)0;
+        v[e] = (valid && part < SPLIT)
+                   ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * d + coord]), part)
+                   : (uint16_t)0;
       }
       Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
     }
@@ -228,14 +284,17 @@ constexpr int kBlockPts = kWaves * 4 * 16;  // the largest block (256 points)
 typedef __attribute__((address_space(3))) void lds_void;
 typedef const __attribute__((address_space(1))) void gbl_void;
 
-// acc[r] = A[r] . B(tile q) - ncg_j / 2, for the wave's KRT row tiles.
-template <int KS, int KRT, bool BCAST>
+// acc[r] = A[r] . B(tile q) - ncg_j / 2, for the wave's KRT row tiles
+// (SC: acc[r] = A[r] . B(tile q); the epilogue scales and biases it).
+template <int KS, int KRT, bool BCAST, bool SC>
 __device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[KRT][KS], const u16x8* buf,
                                           const float* ncs, int q, int lane, f32x4 (&acc)[KRT]) {
   // ncs: -ncg/2 per candidate, four copies each when BCAST (one LDS read
   // then yields the accumulator's initial value)
   f32x4 cinit;
-  if constexpr (BCAST) {
+  if constexpr (SC) {
+    cinit = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  } else if constexpr (BCAST) {
     cinit = reinterpret_cast<const f32x4*>(ncs)[q * 16 + (lane % 16)];
   } else {
     const float cj = ncs[q * 16 + (lane % 16)];
@@ -253,15 +312,23 @@ __device__ __forceinline__ void mfma_tile(const bf16x8 (&Aop)[KRT][KS], const u1
 // Largest and second largest tagged acc of each (row tile, row): the low
 // bits of each value are replaced by the tile's position tq first.  Tagged
 // values are finite, so med3 with FLT_MAX is their max, without the quieting
-// moves fmaxf would add.
-template <int KRT>
+// moves fmaxf would add.  SC: each value is first scaled and biased,
+// acc * (s_row * s_j) - ncg_j / 2, with (-ncg_j / 2, s_j) of tile q's column
+// j from ncs and the row scales srow.
+template <int KRT, bool SC>
 __device__ __forceinline__ void epilogue(const f32x4 (&acc)[KRT], uint32_t keep, uint32_t tq,
-                                         float (&s1)[KRT][4], float (&s2)[KRT][4]) {
+                                         float (&s1)[KRT][4], float (&s2)[KRT][4],
+                                         const float (&srow)[KRT][4], const float* ncs, int q,
+                                         int lane) {
+  float2 col = make_float2(0.0f, 0.0f);
+  if constexpr (SC) col = reinterpret_cast<const float2*>(ncs)[q * 16 + (lane % 16)];
 #pragma unroll
   for (int r = 0; r < KRT; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float v = __uint_as_float((__float_as_uint(acc[r][i]) & keep) | tq);
+      float a = acc[r][i];
+      if constexpr (SC) a = fmaf(a, srow[r][i] * col.y, col.x);
+      const float v = __uint_as_float((__float_as_uint(a) & keep) | tq);
       s2[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], s2[r][i], v);
       s1[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], v, FLT_MAX);
     }
@@ -286,11 +353,12 @@ __device__ __forceinline__ void stage_rows(char* dst, const T* X, int64_t row0, 
 
 // FP32 direct form sum_e (x_e - c_e)^2, e ascending, exactly as the plain
 // kernels compute it (the terms past d add fmaf(0, 0, r) = r).  x: a raw
-// row, staged in LDS (XLDS: read 32 elements at a time without guards; reads
-// past the row stay inside LDS) or in X (guarded); c: an FP32 candidate row
-// (16-byte aligned), read eight float4 at a time.
+// row (decoded with the row scale sc), staged in LDS (XLDS: read 32 elements
+// at a time without guards; reads past the row stay inside LDS) or in X
+// (guarded); c: an FP32 candidate row (16-byte aligned), read eight float4
+// at a time.
 template <typename T, bool XLDS>
-__device__ __forceinline__ float refine_dist(const T* x, const float* c, int d) {
+__device__ __forceinline__ float refine_dist(const T* x, const float* c, int d, float sc) {
   float r = 0.0f;
   for (int e0 = 0; e0 < d; e0 += 32) {
     float4 cv[8];
@@ -301,7 +369,7 @@ __device__ __forceinline__ float refine_dist(const T* x, const float* c, int d) 
     float xv[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k)
-      xv[k] = (XLDS || e0 + k < d) ? Elem<T>::get(x, e0 + k, 1.0f) : 0.0f;
+      xv[k] = (XLDS || e0 + k < d) ? Elem<T>::get(x, e0 + k, sc) : 0.0f;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const float cc[4] = {cv[u].x, cv[u].y, cv[u].z, cv[u].w};
@@ -329,8 +397,10 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   // reuses a quarter of the 64 KB (kWaveStage bytes) for its own data.
   __shared__ u16x8 sB[2][kStageBytes / 16];
   static_assert(2 * kStageBytes == kWaves * kWaveStage, "wave quarters must tile the buffers");
-  constexpr bool BCAST = CT <= 16;  // LDS for four copies of each bias
-  __shared__ __attribute__((aligned(16))) float sN[2][CT * 16 * (BCAST ? 4 : 1)];
+  constexpr bool SC = ScaledRows<T>::value;  // codes with row scales
+  constexpr bool BCAST = !SC && CT <= 16;     // LDS for four copies of each bias
+  // per candidate: -ncg/2 (four copies when BCAST), or (-ncg/2, scale) when SC
+  __shared__ __attribute__((aligned(16))) float sN[2][CT * 16 * (BCAST ? 4 : (SC ? 2 : 1))];
 
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int d = a.d;
@@ -358,13 +428,15 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   // A chunk's CT * 16 biases, NBT per thread (two when a chunk holds 32
   // tiles, i.e. KS = 1).
   constexpr int NBT = (CT * 16 + kWaves * 64 - 1) / (kWaves * 64);
-  float ncg_next[NBT];
+  float ncg_next[NBT], scg_next[NBT];
   auto stage_ncg = [&](int c) {
 #pragma unroll
     for (int i = 0; i < NBT; ++i) {
       const int e = i * kWaves * 64 + threadIdx.x;  // bias within the chunk
       const int idx = c * CT * 16 + e;
-      ncg_next[i] = (e < CT * 16 && idx < ntiles * 16) ? a.ncg[idx] : INFINITY;
+      const bool in = e < CT * 16 && idx < ntiles * 16;
+      ncg_next[i] = in ? a.ncg[idx] : INFINITY;
+      if constexpr (SC) scg_next[i] = in ? a.scg[idx] : 0.0f;
     }
   };
 
@@ -372,8 +444,9 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   stage_ncg(0);
 
   // A operands of this wave's points, kept in registers for the pass: from
-  // the prepared buffer, or straight from X when X is bf16 with d % 8 == 0
-  // (its rows then already hold the operand bytes).
+  // the prepared buffer, or straight from X when d % 8 == 0 and X is bf16
+  // (its rows then already hold the operand bytes) or FP8 (eight codes per
+  // lane and k-step, converted exactly; part p of the K axis is the row).
   bf16x8 Aop[KRT][KS];
 #pragma unroll
   for (int r = 0; r < KRT; ++r) {
@@ -384,8 +457,18 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
       if constexpr (DIRECT) {
         const int p = wbase + r * 16 + (lane % 16);
         const int k0 = s * 32 + (lane / 16) * 8;
-        if (p < a.n && k0 < d)
-          v = *reinterpret_cast<const u16x8*>(static_cast<const uint16_t*>(a.X) + (int64_t)p * d + k0);
+        const int part = k0 / d, coord = k0 - part * d;
+        if (p < a.n && part < SPLIT) {
+          if constexpr (SC) {
+            const uint2 w = *reinterpret_cast<const uint2*>(
+                reinterpret_cast<const uint8_t*>(a.X) + (int64_t)p * d + coord);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              v[e] = code_bf16((uint8_t)((e < 4 ? w.x : w.y) >> (8 * (e % 4))));
+          } else {
+            v = *reinterpret_cast<const u16x8*>(static_cast<const uint16_t*>(a.X) + (int64_t)p * d + coord);
+          }
+        }
       } else {
         v = static_cast<const u16x8*>(a.Apre)[((int64_t)tile * KS + s) * 64 + lane];
       }
@@ -403,6 +486,20 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   static_assert((1 << TB) >= GC * CT, "tag too narrow for a group");
   uint32_t keep;
   asm volatile("v_mov_b32 %0, %1" : "=v"(keep) : "s"(~((1u << TB) - 1u)));
+  // SC: the scales of the rows of each value (0 outside the screen's range:
+  // such a point is listed whatever its values)
+  float srow[KRT][4];
+#pragma unroll
+  for (int r = 0; r < KRT; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      srow[r][i] = 0.0f;
+      if constexpr (SC) {
+        const int p = wbase + r * 16 + (lane / 16) * 4 + i;
+        const float sp = p < a.n ? a.row_scale[p] : 0.0f;
+        srow[r][i] = (sp >= kScaleMin && sp <= kScaleMax) ? sp : 0.0f;
+      }
+    }
   float s1[KRT][4], s2[KRT][4], c1[KRT][4], c2[KRT][4];
   int ix[KRT][4];
 #pragma unroll
@@ -420,7 +517,9 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
       const int e = i * kWaves * 64 + threadIdx.x;
       if (e < CT * 16) {
         const float nb = -0.5f * fminf(ncg_next[i], FLT_MAX);
-        if constexpr (BCAST)
+        if constexpr (SC)
+          reinterpret_cast<float2*>(sN[c & 1])[e] = make_float2(nb, scg_next[i]);
+        else if constexpr (BCAST)
           reinterpret_cast<f32x4*>(sN[c & 1])[e] = f32x4{nb, nb, nb, nb};
         else
           sN[c & 1][e] = nb;
@@ -450,13 +549,13 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     // epilogue of tile q, so matrix and vector units overlap within a wave
     // (two accumulator sets, unrolled by two so no copies are needed).
     f32x4 acc0[KRT], acc1[KRT];
-    mfma_tile<KS, KRT, BCAST>(Aop, buf, ncs, 0, lane, acc0);
+    mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, 0, lane, acc0);
     int q = 0;
     for (; q + 2 < nt; q += 2) {
-      mfma_tile<KS, KRT, BCAST>(Aop, buf, ncs, q + 1, lane, acc1);
-      epilogue(acc0, keep, t0 + q, c1, c2);
-      mfma_tile<KS, KRT, BCAST>(Aop, buf, ncs, q + 2, lane, acc0);
-      epilogue(acc1, keep, t0 + q + 1, c1, c2);
+      mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, q + 1, lane, acc1);
+      epilogue<KRT, SC>(acc0, keep, t0 + q, c1, c2, srow, ncs, q, lane);
+      mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, q + 2, lane, acc0);
+      epilogue<KRT, SC>(acc1, keep, t0 + q + 1, c1, c2, srow, ncs, q + 1, lane);
       // Issue order: the operand reads first, then every MFMA followed by
       // three vector instructions, so that one wave keeps both the matrix
       // and the vector pipes busy.
@@ -468,11 +567,11 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
       }
     }
     if (q + 1 < nt) {
-      mfma_tile<KS, KRT, BCAST>(Aop, buf, ncs, q + 1, lane, acc1);
-      epilogue(acc0, keep, t0 + q, c1, c2);
-      epilogue(acc1, keep, t0 + q + 1, c1, c2);
+      mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, q + 1, lane, acc1);
+      epilogue<KRT, SC>(acc0, keep, t0 + q, c1, c2, srow, ncs, q, lane);
+      epilogue<KRT, SC>(acc1, keep, t0 + q + 1, c1, c2, srow, ncs, q + 1, lane);
     } else {
-      epilogue(acc0, keep, t0 + q, c1, c2);
+      epilogue<KRT, SC>(acc0, keep, t0 + q, c1, c2, srow, ncs, q, lane);
     }
     // Group merge: candidate id from the tag and the lane's column; a tie
     // with the running maximum keeps the earlier (lower) id.
@@ -543,7 +642,9 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   // One lane per point: decide, refine, fold or list.  The refinement
   // reads the point's row from the staged copy and the candidate row as
   // float4.
-  const bool in_range = nx >= kNormMin && nx <= kNormMax;
+  float sp = 1.0f;  // the point's row scale (FP8)
+  if constexpr (SC) sp = valid ? a.row_scale[p] : 0.0f;
+  const bool in_range = nx >= kNormMin && nx <= kNormMax && (!SC || (sp >= kScaleMin && sp <= kScaleMax));
   const float nxg = a.oneminus2g * nx;
   const float lbmin = fmaf(b1, -2.0f, nxg);
   const float lb2 = fmaf(b2, -2.0f, nxg);
@@ -560,10 +661,10 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __builtin_amdgcn_wave_barrier();
       if (refine && lane >= c0 && lane < c0 + nr)
-        r1 = refine_dist<T, true>(reinterpret_cast<const T*>(xw + (lane - c0) * rowb), crow, d);
+        r1 = refine_dist<T, true>(reinterpret_cast<const T*>(xw + (lane - c0) * rowb), crow, d, sp);
     }
   } else if (refine) {
-    r1 = refine_dist<T, false>(X + (int64_t)p * d, crow, d);
+    r1 = refine_dist<T, false>(X + (int64_t)p * d, crow, d, sp);
   }
   if (!valid) return;
   bool listed = false;
@@ -614,25 +715,18 @@ static void launch_one(const ScreenArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_screen<SPLIT, KS, T, true>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
 }
 
-template <int SPLIT, typename T>
+// KS k-steps, dispatched up to MAXKS (the widest row the dtype and split
+// can have).
+template <int SPLIT, typename T, int MAXKS = kScreenMaxKS>
 static hipError_t launch_split(int KS, const ScreenArgs& a, hipStream_t s) {
+  if (KS < 1 || KS > MAXKS) return hipErrorInvalidValue;
   switch (KS) {
-    case 1: launch_one<SPLIT, 1, T>(a, s); break;
-    case 2: launch_one<SPLIT, 2, T>(a, s); break;
-    case 3: launch_one<SPLIT, 3, T>(a, s); break;
-    case 4: launch_one<SPLIT, 4, T>(a, s); break;
-    case 5: launch_one<SPLIT, 5, T>(a, s); break;
-    case 6: launch_one<SPLIT, 6, T>(a, s); break;
-    case 7: launch_one<SPLIT, 7, T>(a, s); break;
-    case 8: launch_one<SPLIT, 8, T>(a, s); break;
-    case 9: launch_one<SPLIT, 9, T>(a, s); break;
-    case 10: launch_one<SPLIT, 10, T>(a, s); break;
-    case 11: launch_one<SPLIT, 11, T>(a, s); break;
-    case 12: launch_one<SPLIT, 12, T>(a, s); break;
-    case 13: launch_one<SPLIT, 13, T>(a, s); break;
-    case 14: launch_one<SPLIT, 14, T>(a, s); break;
-    case 15: launch_one<SPLIT, 15, T>(a, s); break;
-    case 16: launch_one<SPLIT, 16, T>(a, s); break;
+#define KMPAR_LS(V) \
+  case V: if constexpr (V <= MAXKS) launch_one<SPLIT, V, T>(a, s); break;
+    KMPAR_LS(1) KMPAR_LS(2) KMPAR_LS(3) KMPAR_LS(4) KMPAR_LS(5) KMPAR_LS(6) KMPAR_LS(7)
+    KMPAR_LS(8) KMPAR_LS(9) KMPAR_LS(10) KMPAR_LS(11) KMPAR_LS(12) KMPAR_LS(13) KMPAR_LS(14)
+    KMPAR_LS(15) KMPAR_LS(16)
+#undef KMPAR_LS
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -646,12 +740,13 @@ static void launch_prep_a_one(const void* X, const float* rsc, int n, int d, voi
                      static_cast<const T*>(X), rsc, n, d, static_cast<u16x8*>(Apre));
 }
 
-template <int SPLIT, typename T>
+template <int SPLIT, typename T, int MAXKS = kScreenMaxKS>
 static hipError_t launch_prep_a_split(int KS, const void* X, const float* rsc, int n, int d,
                                       void* Apre, hipStream_t s) {
+  if (KS < 1 || KS > MAXKS) return hipErrorInvalidValue;
   switch (KS) {
 #define KMPAR_PA(V) \
-  case V: launch_prep_a_one<SPLIT, V, T>(X, rsc, n, d, Apre, s); break;
+  case V: if constexpr (V <= MAXKS) launch_prep_a_one<SPLIT, V, T>(X, rsc, n, d, Apre, s); break;
     KMPAR_PA(1) KMPAR_PA(2) KMPAR_PA(3) KMPAR_PA(4) KMPAR_PA(5) KMPAR_PA(6) KMPAR_PA(7)
     KMPAR_PA(8) KMPAR_PA(9) KMPAR_PA(10) KMPAR_PA(11) KMPAR_PA(12) KMPAR_PA(13) KMPAR_PA(14)
     KMPAR_PA(15) KMPAR_PA(16)
@@ -678,13 +773,17 @@ static hipError_t launch_first_one(const void* X, const float* rsc, int n, int d
   return hipGetLastError();
 }
 
-template <int SPLIT, typename T>
+template <int SPLIT, typename T, int MAXKS = kScreenMaxKS>
 static hipError_t launch_first_split(int KS, const void* X, const float* rsc, int n, int d, int DP,
                                      const float* C, const int* rs, float* D2, int* A,
                                      float* norms, void* Apre, hipStream_t s) {
+  if (KS < 1 || KS > MAXKS) return hipErrorInvalidValue;
   switch (KS) {
-#define KMPAR_FP(V) \
-  case V: return launch_first_one<SPLIT, V, T, true>(X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s);
+#define KMPAR_FP(V)                                                                              \
+  case V:                                                                                        \
+    if constexpr (V <= MAXKS)                                                                    \
+      return launch_first_one<SPLIT, V, T, true>(X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s); \
+    break;
     KMPAR_FP(1) KMPAR_FP(2) KMPAR_FP(3) KMPAR_FP(4) KMPAR_FP(5) KMPAR_FP(6) KMPAR_FP(7)
     KMPAR_FP(8) KMPAR_FP(9) KMPAR_FP(10) KMPAR_FP(11) KMPAR_FP(12) KMPAR_FP(13) KMPAR_FP(14)
     KMPAR_FP(15) KMPAR_FP(16)
@@ -704,6 +803,8 @@ hipError_t launch_first_pass(kmpar_dtype dt, int split, int KS, bool prep, const
       return launch_first_split<1, bf16_t>(KS, X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s);
     if (dt == KMPAR_BF16 && split == 2)
       return launch_first_split<2, bf16_t>(KS, X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s);
+    if (dt == KMPAR_FP8_E4M3 && split == 1)
+      return launch_first_split<1, fp8_t, 8>(KS, X, rsc, n, d, DP, C, rs, D2, A, norms, Apre, s);
     return hipErrorInvalidValue;
   }
   switch (dt) {
@@ -718,6 +819,7 @@ hipError_t launch_first_pass(kmpar_dtype dt, int split, int KS, bool prep, const
 }
 
 bool screen_a_direct(kmpar_dtype dt, int split, int d) {
+  if (dt == KMPAR_FP8_E4M3) return d % 8 == 0;  // codes converted in registers
   return dt == KMPAR_BF16 && split == 1 && d % 8 == 0;
 }
 
@@ -731,18 +833,24 @@ hipError_t launch_prep_a(kmpar_dtype dt, int split, int KS, const void* X, const
   if (dt == KMPAR_F32 && split == 3) return launch_prep_a_split<3, float>(KS, X, rsc, n, d, Apre, s);
   if (dt == KMPAR_BF16 && split == 1) return launch_prep_a_split<1, bf16_t>(KS, X, rsc, n, d, Apre, s);
   if (dt == KMPAR_BF16 && split == 2) return launch_prep_a_split<2, bf16_t>(KS, X, rsc, n, d, Apre, s);
+  if (dt == KMPAR_FP8_E4M3 && split == 2)
+    return launch_prep_a_split<2, fp8_t>(KS, X, rsc, n, d, Apre, s);
   return hipErrorInvalidValue;
 }
 
-template <int SPLIT>
+template <int SPLIT, bool CODES = false, int MAXKS = kScreenMaxKS>
 static hipError_t launch_prep_split(int KS, const float* C, int DP, int d, const int* rs, int m_host,
-                                    int max_tiles, float om2g, void* B, float* ncg, hipStream_t s) {
+                                    int max_tiles, float om2g, void* B, float* ncg, const void* X,
+                                    const float* rsc, const int* cand, float* scg, hipStream_t s) {
+  if (KS < 1 || KS > MAXKS) return hipErrorInvalidValue;
   u16x8* b = static_cast<u16x8*>(B);
+  const fp8_t* xc = static_cast<const fp8_t*>(X);
   switch (KS) {
-#define KMPAR_PREP(V)                                                                           \
-  case V:                                                                                       \
-    hipLaunchKernelGGL((k_prep_b<SPLIT, V>), dim3(max_tiles), dim3(64), 0, s, C, DP, d, rs,    \
-                       m_host, om2g, b, ncg);                                                   \
+#define KMPAR_PREP(V)                                                                          \
+  case V:                                                                                      \
+    if constexpr (V <= MAXKS)                                                                  \
+      hipLaunchKernelGGL((k_prep_b<SPLIT, V, CODES>), dim3(max_tiles), dim3(64), 0, s, C, DP, d, \
+                         rs, m_host, om2g, b, ncg, xc, rsc, cand, scg);                        \
     break;
     KMPAR_PREP(1) KMPAR_PREP(2) KMPAR_PREP(3) KMPAR_PREP(4) KMPAR_PREP(5) KMPAR_PREP(6)
     KMPAR_PREP(7) KMPAR_PREP(8) KMPAR_PREP(9) KMPAR_PREP(10) KMPAR_PREP(11) KMPAR_PREP(12)
@@ -755,8 +863,8 @@ static hipError_t launch_prep_split(int KS, const float* C, int DP, int d, const
 
 int screen_split(kmpar_dtype dt, bool centers_are_rows) {
   if (dt == KMPAR_F32) return 3;
-  if (dt == KMPAR_BF16) return centers_are_rows ? 1 : 2;
-  return 0;  // FP8: no screen (direct form)
+  // bf16 rows and FP8 codes are exact in bf16; FP32 centers take two terms
+  return centers_are_rows ? 1 : 2;
 }
 
 int screen_ksteps(int split, int d) { return split ? (split * d + 31) / 32 : 0; }
@@ -770,8 +878,10 @@ bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d) {
 // bf16 split truncation (twice the dot), FP32 accumulation of K products,
 // FP32 norms, the roundings of the lower-bound arithmetic, the FP32
 // direct-form error of the distances it is compared with, and the tile tag
-// in the low mantissa bits; times 2 for margin.
-float screen_g(int split, int d) {
+// in the low mantissa bits; times 2 for margin.  FP8 rows add the roundings
+// of their decoded elements (fl(s q), twice the dot: 2u S) and of the scaled
+// epilogue (s_x s_c, the fma, the bias: 3u, doubled).
+float screen_g(kmpar_dtype dt, int split, int d) {
   const double u = 0x1.0p-24;
   const int K = 32 * screen_ksteps(split, d);
   double split_err = 0.0;
@@ -784,18 +894,27 @@ float screen_g(int split, int d) {
   // |acc| <= |x.c| + ||c||^2 / 2 <= 1.01 S; the tag moves it by less than
   // 2^(TB-23) |acc|, and lb by twice that.
   const double tag_err = 2.02 * std::ldexp(1.0, screen_tag_bits(screen_ksteps(split, d)) - 23);
+  const double scale_err = dt == KMPAR_FP8_E4M3 ? 8.2 * u : 0.0;
   const double safety = 2.0;  // 2G = safety * budget
-  return (float)(safety * (split_err + acc_err + misc + tag_err) / 2.0);
+  return (float)(safety * (split_err + acc_err + misc + tag_err + scale_err) / 2.0);
 }
 
-hipError_t launch_prep_b(int split, int KS, const float* C, int DP, int d, const int* rs,
-                         int m_host, int max_tiles, float om2g, void* B, float* ncg,
+hipError_t launch_prep_b(kmpar_dtype dt, int split, int KS, const float* C, int DP, int d,
+                         const int* rs, int m_host, int max_tiles, float om2g, void* B, float* ncg,
+                         const void* X, const float* rsc, const int* cand, float* scg,
                          hipStream_t s) {
   if (max_tiles <= 0) return hipSuccess;
+  const bool fp8 = dt == KMPAR_FP8_E4M3;
+  if (fp8 && split == 1) {
+    if (!cand || !scg) return hipErrorInvalidValue;
+    return launch_prep_split<1, true, 8>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, X, rsc,
+                                         cand, scg, s);
+  }
+  float* sc = fp8 ? scg : nullptr;  // FP32 centers against FP8 rows: scale 1
   switch (split) {
-    case 1: return launch_prep_split<1>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, s);
-    case 2: return launch_prep_split<2>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, s);
-    case 3: return launch_prep_split<3>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, s);
+    case 1: return launch_prep_split<1>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, sc, s);
+    case 2: return launch_prep_split<2>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, sc, s);
+    case 3: return launch_prep_split<3>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, sc, s);
   }
   return hipErrorInvalidValue;
 }
@@ -806,6 +925,9 @@ hipError_t launch_screen(kmpar_dtype dt, int split, int KS, const ScreenArgs& a,
   if (dt == KMPAR_F32 && split == 3) return launch_split<3, float>(KS, a, s);
   if (dt == KMPAR_BF16 && split == 1) return launch_split<1, bf16_t>(KS, a, s);
   if (dt == KMPAR_BF16 && split == 2) return launch_split<2, bf16_t>(KS, a, s);
+  if (dt == KMPAR_FP8_E4M3 && !a.scg) return hipErrorInvalidValue;
+  if (dt == KMPAR_FP8_E4M3 && split == 1) return launch_split<1, fp8_t, 8>(KS, a, s);
+  if (dt == KMPAR_FP8_E4M3 && split == 2) return launch_split<2, fp8_t>(KS, a, s);
   return hipErrorInvalidValue;
 }
 

@@ -10,7 +10,7 @@ import torch
 
 from oracle import oracle as O
 from paper_1203_6402_amd import synth
-from tests.gpu_util import compare_init, decoded_fp64, gpu_init, to_bf16_bits
+from tests.gpu_util import compare_init, decoded_fp64, gpu_init, to_bf16_bits, to_e4m3
 
 pytestmark = pytest.mark.gpu
 
@@ -89,30 +89,64 @@ def test_refined_equals_plain_bf16(plain, refined, d, n, k, ell):
     compare_init(decoded_fp64(Xb, "bf16"), b, tr, k, ell, 5, 2)
 
 
+@pytest.mark.parametrize("d,n,k,ell,kind", [
+    (16, 6007, 40, 80.0, "sigma"),     # one k-step, codes read straight from X
+    (42, 5003, 40, 80.0, "heavy"),     # d % 8 != 0: operands prepared by the first pass
+    (128, 4001, 30, 60.0, "sigma"),    # four k-steps
+    (256, 3001, 30, 60.0, "sigma"),    # eight k-steps (the widest row)
+    (8, 20000, 200, 800.0, "gauss"),   # 32-tile chunks, two of them a round
+])
+def test_refined_equals_plain_fp8(plain, refined, d, n, k, ell, kind):
+    # e4m3 codes with per-row scales max|x|/448: the screen multiplies the
+    # codes exactly and scales each value afterwards.
+    if kind == "gauss":
+        X = synth.gauss_mixture(n, d, k, 10.0, seed=n)
+    elif kind == "heavy":
+        X = synth.heavy_tailed(n, d, seed=n)
+    else:
+        X = synth.gauss_mixture_sigma(n, d, 60, seed=n)
+    q, sc = to_e4m3(X)
+    Xd, sd = _dev(q), _dev(sc)
+    a = plain.init(Xd, k=k, ell=ell, rounds=4, seed=3, row_scale=sd, trace=True)
+    b = refined.init(Xd, k=k, ell=ell, rounds=4, seed=3, row_scale=sd, trace=True)
+    torch.cuda.synchronize()
+    _same_init(a, b)
+    tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
+    compare_init(decoded_fp64(q, "fp8", sc), b, tr, k, ell, 4, 3)
+    assert b.stats["n_rescanned"] <= 0.05 * n * 4
+
+
 @pytest.mark.parametrize("dt,d,m", [("f32", 42, 500), ("f32", 15, 37), ("bf16", 128, 300),
-                                    ("bf16", 64, 33), ("f32", 8, 700), ("bf16", 16, 700)])
+                                    ("bf16", 64, 33), ("f32", 8, 700), ("bf16", 16, 700),
+                                    ("fp8", 64, 300), ("fp8", 42, 200), ("fp8", 256, 100),
+                                    ("fp8", 16, 700)])
 def test_refined_assign_cost_lloyd_equal_plain(plain, refined, dt, d, m):
     X = synth.gauss_mixture_sigma(9001, d, 200, seed=m)
+    rs = None
     if dt == "bf16":
         Xh = to_bf16_bits(X)
         Xd = _dev(Xh).view(torch.bfloat16)
         X64 = decoded_fp64(Xh, "bf16")
+    elif dt == "fp8":
+        q, sc = to_e4m3(X)
+        Xd, rs = _dev(q), _dev(sc)
+        X64 = decoded_fp64(q, "fp8", sc)
     else:
         Xd = _dev(X)
         X64 = X.astype(np.float64)
     rng = np.random.default_rng(m)
     C = (X64[rng.choice(9001, m, replace=False)] + rng.normal(size=(m, d)) * 0.1).astype(np.float32)
-    a1, d1 = plain.assign(Xd, _dev(C))
-    a2, d2 = refined.assign(Xd, _dev(C))
-    p1, p2 = plain.cost(Xd, _dev(C)), refined.cost(Xd, _dev(C))
+    a1, d1 = plain.assign(Xd, _dev(C), row_scale=rs)
+    a2, d2 = refined.assign(Xd, _dev(C), row_scale=rs)
+    p1, p2 = plain.cost(Xd, _dev(C), row_scale=rs), refined.cost(Xd, _dev(C), row_scale=rs)
     torch.cuda.synchronize()
     assert torch.equal(a1, a2) and torch.equal(d1, d2) and torch.equal(p1, p2)
     oa, od2, _ = O.nearest(X64, C.astype(np.float64))
     np.testing.assert_allclose(d2.cpu().numpy(), od2, rtol=1e-5)
     C1, C2 = _dev(C), _dev(C)
     for _ in range(3):
-        x1, q1 = plain.lloyd_step(Xd, C1, want_assign=True)
-        x2, q2 = refined.lloyd_step(Xd, C2, want_assign=True)
+        x1, q1 = plain.lloyd_step(Xd, C1, row_scale=rs, want_assign=True)
+        x2, q2 = refined.lloyd_step(Xd, C2, row_scale=rs, want_assign=True)
         torch.cuda.synchronize()
         assert torch.equal(x1, x2) and torch.equal(q1, q2) and torch.equal(C1, C2)
 
