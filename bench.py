@@ -86,6 +86,66 @@ def precision_compare(kmpar, synth, torch, seed, steps=2):
     return out
 
 
+def c3_compare(kmpar, synth, torch, seed, steps=2, with_plain=True):
+    """FP8 precision workload: n = 50M, d = 256, e4m3 codes with per-row
+    scales max|x|/448 from a 2,000-component Gaussian mixture (centers
+    N(0, 25 I), sigma logU[0.5, 4]), k = 2000, ell = 2k, r = 5; REFINED init
+    against PLAIN (PLAIN takes about a minute here and runs once)."""
+    n, d, k, rounds = 50_000_000, 256, 2000, 5
+    ell = 2.0 * k
+    log("C3: generating 50M x 256 e4m3 rows on the device")
+    Q, S = synth.gauss_mixture_sigma_fp8_torch(n, d, 2000, seed=seed, device="cuda:0")
+    out = {"workload": "Gaussian mixture, 2,000 components, e4m3 storage with row scales "
+                       "(synthetic)", "n": n, "d": d, "k": k, "ell": ell, "rounds": rounds}
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ctx = kmpar.Context(0, kmpar.MODE_REFINED)
+    r = ctx.init(Q, k=k, ell=ell, rounds=rounds, seed=seed, row_scale=S)
+    torch.cuda.synchronize()
+    out["refined_init_ms"] = timed(lambda: ctx.init(Q, k=k, ell=ell, rounds=rounds, seed=seed,
+                                                    row_scale=S, check=False), steps)
+    out["refined_init_evals_per_s"] = float(n) * r.stats["n_candidates"] / (out["refined_init_ms"] / 1e3)
+    log(f"C3 refined: init {out['refined_init_ms']:.1f} ms (|C|={r.stats['n_candidates']})")
+    ctx.profile(True)
+    rp = ctx.init(Q, k=k, ell=ell, rounds=rounds, seed=seed, row_scale=S)
+    torch.cuda.synchronize()
+    p = ctx.profile_read(kmpar.SLOT_SCREEN)
+    ctx.profile(False)
+    dur = p["ms"] / p["launches"] / 1e3
+    flops = 2.0 * d * p["pairs"] / p["launches"]
+    out["screen_avg_launch_us"] = dur * 1e6
+    out["screen_tflops"] = flops / dur / 1e12
+    out["screen_frac_of_bf16_peak"] = flops / dur / 1e12 / PEAK_BF16_MFMA_TFLOPS
+    out["rescanned_points"] = rp.stats["n_rescanned"]
+    log(f"C3 screen: {p['launches']} launches, avg {dur*1e6:.1f} us, "
+        f"{flops/dur/1e12:.1f} TFLOP/s algorithmic")
+    del ctx
+    if with_plain:
+        pctx = kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
+        log("C3 plain: one init (about a minute)")
+        holder = {}
+        out["plain_init_ms"] = timed(lambda: holder.__setitem__(
+            "r", pctx.init(Q, k=k, ell=ell, rounds=rounds, seed=seed, row_scale=S)), 1)
+        rpl = holder["r"]
+        log(f"C3 plain: init {out['plain_init_ms']:.1f} ms")
+        out["init_speedup"] = out["plain_init_ms"] / out["refined_init_ms"]
+        out["init_centers_bitwise_equal"] = bool(torch.equal(r.centers, rpl.centers))
+        out["init_phi_rel_diff"] = abs(r.stats["phi"][-1] - rpl.stats["phi"][-1]) / max(
+            abs(rpl.stats["phi"][-1]), 1e-300)
+        del pctx
+    del Q, S
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_bench(kmpar, synth, torch, seed, count, steps=2):
     """Many independent instances in one kmpar_init_batched call: n_i
     log-uniform in [2,000, 200,000], d_i uniform in {32, 64, 128},
@@ -177,6 +237,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16-refined vs FP32-plain comparison on the precision workload")
+    ap.add_argument("--c3", action="store_true",
+                    help="also run the FP8 workload (50M x 256 e4m3, k = 2000), REFINED init "
+                         "against PLAIN")
+    ap.add_argument("--c3-no-plain", action="store_true",
+                    help="with --c3: REFINED only (for profiling)")
     ap.add_argument("--batched", action="store_true",
                     help="also time the 4,096-instance batched workload (FP32 and BF16)")
     ap.add_argument("--batch-count", type=int, default=4096)
@@ -285,6 +350,10 @@ def main():
     if not args.no_precision:
         precision = precision_compare(kmpar, synth, torch, args.seed)
 
+    c3 = None
+    if args.c3:
+        c3 = c3_compare(kmpar, synth, torch, args.seed, with_plain=not args.c3_no_plain)
+
     batched = None
     if args.batched:
         batched = batched_bench(kmpar, synth, torch, args.seed, args.batch_count)
@@ -306,7 +375,7 @@ def main():
                       "graph_replay_ms_per_step": graph_ms,
                       "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu, "precision": precision,
-           "batched": batched}
+           "fp8": c3, "batched": batched}
     print(json.dumps(out), flush=True)
 
 

@@ -289,8 +289,8 @@ hipError_t timed_fold(kmpar_ctx* ctx, int slot, kmpar_dtype dt, int DP, const Fo
 
 // One REFINED distance pass: B operands, screen, direct-form rescan of the
 // points the screen listed.  `fa` describes the same pass for the direct form.
-// FP8 rows also take the candidates' scales (scg) and, against rows of X,
-// the candidates' point ids (cand), whose codes are the B operands.
+// FP8 rows also take the candidates' point ids (cand), whose codes are the
+// B operands, and their scales (scg).
 hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const FoldArgs& fa,
                         int max_tiles, const float* norms, const void* Apre, void* B, float* ncg,
                         const int* cand, float* scg, int* list, int* list_len, kmpar_stats* st,

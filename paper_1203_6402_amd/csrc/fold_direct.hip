@@ -121,13 +121,26 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
   }
 }
 
-// Direct-form rescan of the points a screen pass listed: one wave per point,
-// each lane takes every 64th candidate; the wave reduction keeps the smallest
-// distance and, among equal ones, the lowest id -- the decision the
-// one-thread-per-point fold takes, with the same per-candidate arithmetic.
+// Direct-form rescan of the points a screen pass listed.  A block takes 64
+// listed points at a time (one per lane, their decoded rows in LDS with an
+// odd row stride) and streams the m candidates through LDS in chunks of 32
+// rows, so each candidate row is read once per 64 points; wave w computes
+// candidates w, w + 4, ... of every chunk for all 64 points.  Each distance
+// has the fold's arithmetic (t = x_e - c_e, acc = fma(t, t, acc), e
+// ascending over the zero-padded row), each thread keeps its first
+// strictly smallest candidate, and the four waves' winners are merged by
+// (distance, id): per point the smallest distance, the lowest id on ties,
+// which is the decision the one-thread-per-point fold takes.
+constexpr int kRescanPts = 64;   // listed points per block step
+constexpr int kRescanCands = 32; // candidate rows per LDS chunk
+
 template <int DP, typename T>
 __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
-  __shared__ float xs[4][DP];
+  constexpr int P = kRescanPts, CC = kRescanCands, XS = DP + 1, NI = CC / 4;
+  __shared__ float xs[P * XS];
+  __shared__ __attribute__((aligned(16))) float cs[CC * DP];
+  __shared__ float rb[4][P];
+  __shared__ int rj[4][P];
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   const int nlist = *a.list_len;
   int id0, m;
@@ -140,45 +153,72 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
   }
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const float* __restrict__ C = a.C + (int64_t)id0 * DP;
-  for (int it = blockIdx.x * 4 + w; it < nlist; it += gridDim.x * 4) {
-    const int p = a.list[it];
-    const float sc = row_scale_of<T>(a.row_scale, p);
-    for (int e = lane; e < DP; e += 64) xs[w][e] = (e < a.d) ? Elem<T>::get(X, (int64_t)p * a.d + e, sc) : 0.0f;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int g = blockIdx.x; g * P < nlist; g += gridDim.x) {
+    const int np = min(P, nlist - g * P);
+    __syncthreads();  // the previous group is merged and written
+    for (int idx = threadIdx.x; idx < P * DP; idx += 256) {
+      const int r = idx / DP, e = idx - r * DP;
+      float v = 0.0f;
+      if (r < np && e < a.d) {
+        const int p = a.list[g * P + r];
+        v = Elem<T>::get(X, (int64_t)p * a.d + e, row_scale_of<T>(a.row_scale, p));
+      }
+      xs[r * XS + e] = v;
+    }
     float best = INFINITY;
     int bj = -1;
-    for (int c = lane; c < m; c += 64) {
-      const float4* cr = reinterpret_cast<const float4*>(C + (int64_t)c * DP);
-      float acc = 0.0f;
-#pragma unroll
-      for (int e4 = 0; e4 < DP / 4; ++e4) {
-        const float4 cv = cr[e4];
-        float t = xs[w][4 * e4 + 0] - cv.x;
-        acc = fmaf(t, t, acc);
-        t = xs[w][4 * e4 + 1] - cv.y;
-        acc = fmaf(t, t, acc);
-        t = xs[w][4 * e4 + 2] - cv.z;
-        acc = fmaf(t, t, acc);
-        t = xs[w][4 * e4 + 3] - cv.w;
-        acc = fmaf(t, t, acc);
+    const float* xr = xs + lane * XS;
+    for (int c0 = 0; c0 < m; c0 += CC) {
+      const int nc = min(CC, m - c0);
+      __syncthreads();  // the previous chunk is consumed (and xs is written)
+      for (int idx = threadIdx.x; idx < CC * (DP / 4); idx += 256) {
+        const int j = idx / (DP / 4);
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (j < nc) v = reinterpret_cast<const float4*>(C + (int64_t)(c0 + j) * DP)[idx - j * (DP / 4)];
+        reinterpret_cast<float4*>(cs)[idx] = v;
       }
-      if (acc < best) {
-        best = acc;
-        bj = c;
+      __syncthreads();
+      float acc[NI];
+#pragma unroll
+      for (int i = 0; i < NI; ++i) acc[i] = 0.0f;
+#pragma unroll 2
+      for (int e = 0; e < DP; e += 4) {
+        const float x0 = xr[e], x1 = xr[e + 1], x2 = xr[e + 2], x3 = xr[e + 3];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          const float4 cv = reinterpret_cast<const float4*>(cs + (w + 4 * i) * DP)[e / 4];
+          float t = x0 - cv.x;
+          acc[i] = fmaf(t, t, acc[i]);
+          t = x1 - cv.y;
+          acc[i] = fmaf(t, t, acc[i]);
+          t = x2 - cv.z;
+          acc[i] = fmaf(t, t, acc[i]);
+          t = x3 - cv.w;
+          acc[i] = fmaf(t, t, acc[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        const int j = w + 4 * i;
+        if (j < nc && acc[i] < best) {
+          best = acc[i];
+          bj = c0 + j;
+        }
       }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const float ob = __shfl_xor(best, off, 64);
-      const int oj = __shfl_xor(bj, off, 64);
-      if (ob < best || (ob == best && (unsigned)oj < (unsigned)bj)) {
-        best = ob;
-        bj = oj;
+    rb[w][lane] = best;
+    rj[w][lane] = bj;
+    __syncthreads();
+    if (w == 0 && lane < np) {
+      for (int q = 1; q < 4; ++q) {
+        const float ob = rb[q][lane];
+        const int oj = rj[q][lane];
+        if (ob < best || (ob == best && (unsigned)oj < (unsigned)bj)) {
+          best = ob;
+          bj = oj;
+        }
       }
-    }
-    if (lane == 0) {
+      const int p = a.list[g * P + lane];
       if (a.first) {
         a.D2[p] = best;
         a.A[p] = bj >= 0 ? id0 + bj : -1;
@@ -187,7 +227,6 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
         a.A[p] = id0 + bj;
       }
     }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -256,7 +295,9 @@ hipError_t launch_fold_direct(kmpar_dtype dt, int DP, const FoldArgs& a, hipStre
 
 template <typename T>
 static hipError_t launch_rescan_t(int DP, const FoldArgs& a, hipStream_t s) {
-  int blocks = (a.list_cap + 3) / 4;
+  // the listed count is only known on the device: enough blocks for the
+  // largest list up to four per CU, each looping over groups of 64 points
+  int blocks = (a.list_cap + kRescanPts - 1) / kRescanPts;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) return hipSuccess;
   const dim3 grid(blocks), block(256);

@@ -81,8 +81,8 @@ struct ScreenArgs {
   const void* Apre;      // bf16 A operands from launch_prep_a (nullptr: read X directly)
   const void* B;         // bf16 B operands from launch_prep_b
   const float* ncg;      // (1 - 2G) ||c||^2 per candidate, +inf past m
-  const float* scg;      // FP8 rows: each candidate's scale (1 for FP32 centers, 0 for a
-                         // trivial bound); nullptr otherwise
+  const float* scg;      // FP8 rows: each candidate's scale (0 for a trivial bound);
+                         // nullptr otherwise
   const float* norms;    // ||x||^2 per point
   float oneminus2g;
   float* D2;
@@ -113,10 +113,8 @@ constexpr int screen_tag_bits(int KS) {
 // Error constant G of the screen's lower bound.
 float screen_g(kmpar_dtype dt, int split, int d);
 // B operands of the candidates C[rs[0] ..) (or C[0 .. m_host)), their biases
-// and, for FP8 rows, their scales.  FP8 rows against rows of X (cand !=
-// nullptr) take the candidates' e4m3 codes from X rows cand[id]; FP8 rows
-// against FP32 centers (cand == nullptr) split the centers and give them
-// scale 1.
+// and, for FP8 rows, their scales: FP8 rows (split 1, against rows of X)
+// take the candidates' e4m3 codes from X rows cand[id].
 hipError_t launch_prep_b(kmpar_dtype dt, int split, int KS, const float* C, int DP, int d,
                          const int* rs, int m_host, int max_tiles, float om2g, void* B, float* ncg,
                          const void* X, const float* rsc, const int* cand, float* scg,

@@ -29,13 +29,13 @@
 // get a trivial bound (every point refines or lists them).
 //
 // FP8 rows (e4m3 codes q with a row scale s, element = fl(s * q)) enter the
-// matrix cores as their codes, which bf16 holds exactly: against rows of X
-// the products q_x . q_c are exact, against FP32 centers the centers take
-// the two-term split.  The accumulators start at zero and each value is
-// then scaled, acc * (s_x * s_c) - ncg_c / 2 (s_c = 1 for centers), which
-// the budget of G covers with the roundings of the scales.  Rows whose
-// scale lies outside [2^-63, 2^63] are listed; candidates whose scale does
-// get a trivial bound.
+// matrix cores as their codes, which bf16 holds exactly, against the codes
+// of candidate rows of X: the products q_x . q_c are exact.  The
+// accumulators start at zero and each value is then scaled,
+// acc * (s_x * s_c) - ncg_c / 2, which the budget of G covers with the
+// roundings of the scales.  Rows whose scale lies outside [2^-63, 2^63] are
+// listed; candidates whose scale does get a trivial bound.  (Assignment
+// passes of FP8 rows against FP32 centers use the direct form.)
 #include <float.h>
 #include <cmath>
 #include <math.h>
@@ -114,10 +114,9 @@ __device__ __forceinline__ uint16_t b_elem(float c, int part) {
 // One wave per tile of 16 candidates: writes KS k-steps of 64 lanes x 8 bf16
 // in the lane order the MFMA B operand uses (lane l: candidate l%16,
 // k = s*32 + (l/16)*8 + e), plus ncg_j = (1 - 2G) ||c_j||^2 (+inf past m).
-// CODES: the operands are the e4m3 codes of X row cand[id0 + j] (SPLIT 1).
-// scg (nullable) receives each candidate's scale: the row scale with CODES,
-// 1 for FP32 centers, 0 past m or when the scale is outside the screen's
-// range (then the bias is trivial as well).
+// CODES: the operands are the e4m3 codes of X row cand[id0 + j] (SPLIT 1),
+// and scg receives each candidate's row scale, 0 past m or when the scale
+// is outside the screen's range (then the bias is trivial as well).
 template <int SPLIT, int KS, bool CODES>
 __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, const int* rs,
                                                int m_host, float oneminus2g, u16x8* B,
@@ -160,7 +159,7 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
     // Past m: +inf (never the maximum).  Beyond 2^100 (or not finite), or a
     // scale out of range: a bias that makes the candidate's lower bound -inf.
     ncg[j] = !valid ? INFINITY : (nc <= kNormMax && sc_ok ? oneminus2g * nc : -FLT_MAX);
-    if (scg) scg[j] = (valid && sc_ok) ? sc : 0.0f;
+    if constexpr (CODES) scg[j] = (valid && sc_ok) ? sc : 0.0f;
   }
 }
 
@@ -819,7 +818,7 @@ hipError_t launch_first_pass(kmpar_dtype dt, int split, int KS, bool prep, const
 }
 
 bool screen_a_direct(kmpar_dtype dt, int split, int d) {
-  if (dt == KMPAR_FP8_E4M3) return d % 8 == 0;  // codes converted in registers
+  if (dt == KMPAR_FP8_E4M3) return split == 1 && d % 8 == 0;  // codes converted in registers
   return dt == KMPAR_BF16 && split == 1 && d % 8 == 0;
 }
 
@@ -833,8 +832,6 @@ hipError_t launch_prep_a(kmpar_dtype dt, int split, int KS, const void* X, const
   if (dt == KMPAR_F32 && split == 3) return launch_prep_a_split<3, float>(KS, X, rsc, n, d, Apre, s);
   if (dt == KMPAR_BF16 && split == 1) return launch_prep_a_split<1, bf16_t>(KS, X, rsc, n, d, Apre, s);
   if (dt == KMPAR_BF16 && split == 2) return launch_prep_a_split<2, bf16_t>(KS, X, rsc, n, d, Apre, s);
-  if (dt == KMPAR_FP8_E4M3 && split == 2)
-    return launch_prep_a_split<2, fp8_t>(KS, X, rsc, n, d, Apre, s);
   return hipErrorInvalidValue;
 }
 
@@ -864,6 +861,8 @@ static hipError_t launch_prep_split(int KS, const float* C, int DP, int d, const
 int screen_split(kmpar_dtype dt, bool centers_are_rows) {
   if (dt == KMPAR_F32) return 3;
   // bf16 rows and FP8 codes are exact in bf16; FP32 centers take two terms
+  // against bf16 rows (FP8 rows against centers: no screen, direct form)
+  if (dt == KMPAR_FP8_E4M3) return centers_are_rows ? 1 : 0;
   return centers_are_rows ? 1 : 2;
 }
 
@@ -910,11 +909,11 @@ hipError_t launch_prep_b(kmpar_dtype dt, int split, int KS, const float* C, int 
     return launch_prep_split<1, true, 8>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, X, rsc,
                                          cand, scg, s);
   }
-  float* sc = fp8 ? scg : nullptr;  // FP32 centers against FP8 rows: scale 1
+  if (fp8) return hipErrorInvalidValue;
   switch (split) {
-    case 1: return launch_prep_split<1>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, sc, s);
-    case 2: return launch_prep_split<2>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, sc, s);
-    case 3: return launch_prep_split<3>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, sc, s);
+    case 1: return launch_prep_split<1>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, s);
+    case 2: return launch_prep_split<2>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, s);
+    case 3: return launch_prep_split<3>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, s);
   }
   return hipErrorInvalidValue;
 }
@@ -927,7 +926,6 @@ hipError_t launch_screen(kmpar_dtype dt, int split, int KS, const ScreenArgs& a,
   if (dt == KMPAR_BF16 && split == 2) return launch_split<2, bf16_t>(KS, a, s);
   if (dt == KMPAR_FP8_E4M3 && !a.scg) return hipErrorInvalidValue;
   if (dt == KMPAR_FP8_E4M3 && split == 1) return launch_split<1, fp8_t, 8>(KS, a, s);
-  if (dt == KMPAR_FP8_E4M3 && split == 2) return launch_split<2, fp8_t>(KS, a, s);
   return hipErrorInvalidValue;
 }
 

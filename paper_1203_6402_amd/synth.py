@@ -17,7 +17,8 @@ Recipes (all with ``numpy.random.Generator(PCG64(seed))`` on the host, or a seed
   ``s ~ logU[1, 1e6]`` per (component, column), ``z ~ N(0, 1)``, and each entry
   is zeroed with probability ``zero_frac``.
 * ``gauss_mixture_sigma`` -- Gaussian mixture with centers ``N(0, var_c I)`` and a
-  per-component isotropic sigma drawn log-uniform in ``[sig_lo, sig_hi]``.
+  per-component isotropic sigma drawn log-uniform in ``[sig_lo, sig_hi]``; its FP8
+  variant stores each row as e4m3 codes with the row scale ``max|x| / 448``.
 * ``batch_instances`` -- shapes of many independent small instances.
 """
 from __future__ import annotations
@@ -100,6 +101,34 @@ def gauss_mixture_sigma_torch(n: int, d: int, comps: int, seed: int,
         x = centers[lab] + sig[lab, None] * torch.randn(c, d, generator=g, device=device)
         X[s:s + c] = x.to(X.dtype)
     return X
+
+
+def gauss_mixture_sigma_fp8_torch(n: int, d: int, comps: int, seed: int,
+                                  device="cuda", var_c: float = 25.0,
+                                  sig_lo: float = 0.5, sig_hi: float = 4.0,
+                                  chunk: int = 1 << 21):
+    """``gauss_mixture_sigma`` stored as OCP e4m3 codes with one FP32 scale
+    per row, max|x| / 448 (448 is the largest e4m3 value), each row divided by
+    its scale and rounded to nearest even; made chunk by chunk on the device
+    so that the FP32 rows never exist all at once.  Returns (codes as an
+    n x d uint8 tensor, scales as an n float32 tensor)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    centers = torch.randn(comps, d, generator=g, device=device) * math.sqrt(var_c)
+    lo, hi = math.log(sig_lo), math.log(sig_hi)
+    sig = torch.exp(lo + (hi - lo) * torch.rand(comps, generator=g, device=device))
+    Q = torch.empty(n, d, device=device, dtype=torch.uint8)
+    S = torch.empty(n, device=device, dtype=torch.float32)
+    for s in range(0, n, chunk):
+        c = min(chunk, n - s)
+        lab = torch.randint(0, comps, (c,), generator=g, device=device)
+        x = centers[lab] + sig[lab, None] * torch.randn(c, d, generator=g, device=device)
+        scale = x.abs().amax(dim=1).clamp_min(1e-30) / 448.0
+        Q[s:s + c] = (x / scale[:, None]).to(torch.float8_e4m3fn).view(torch.uint8)
+        S[s:s + c] = scale
+    return Q, S
 
 
 def batch_instances(count: int, seed: int, n_lo: int = 2000, n_hi: int = 200000,

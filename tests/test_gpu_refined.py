@@ -116,10 +116,20 @@ def test_refined_equals_plain_fp8(plain, refined, d, n, k, ell, kind):
     assert b.stats["n_rescanned"] <= 0.05 * n * 4
 
 
+# FP8 rows against FP32 centers had a screen of their own (codes against a
+# two-term split of the centers); a run of ten Lloyd steps at n = 50M, d = 256
+# stopped with an illegal-address fault whose cause was not found, so it was
+# taken out and these cases only check the direct form against itself.
+_FP8_ASSIGN_OFF = pytest.mark.skip(reason="the FP8-rows assignment screen was taken out after an "
+                                          "unexplained fault; FP8 assignment uses the direct form")
+
+
 @pytest.mark.parametrize("dt,d,m", [("f32", 42, 500), ("f32", 15, 37), ("bf16", 128, 300),
                                     ("bf16", 64, 33), ("f32", 8, 700), ("bf16", 16, 700),
-                                    ("fp8", 64, 300), ("fp8", 42, 200), ("fp8", 256, 100),
-                                    ("fp8", 16, 700)])
+                                    pytest.param("fp8", 64, 300, marks=_FP8_ASSIGN_OFF),
+                                    pytest.param("fp8", 42, 200, marks=_FP8_ASSIGN_OFF),
+                                    pytest.param("fp8", 256, 100, marks=_FP8_ASSIGN_OFF),
+                                    pytest.param("fp8", 16, 700, marks=_FP8_ASSIGN_OFF)])
 def test_refined_assign_cost_lloyd_equal_plain(plain, refined, dt, d, m):
     X = synth.gauss_mixture_sigma(9001, d, 200, seed=m)
     rs = None
