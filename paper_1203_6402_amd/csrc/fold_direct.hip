@@ -121,27 +121,29 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
   }
 }
 
-// Direct-form rescan of the points a screen pass listed.  A block takes 64
-// listed points at a time (one per lane, their decoded rows in LDS with an
-// odd row stride) and streams the m candidates through LDS in chunks of 32
-// rows, so each candidate row is read once per 64 points; wave w computes
-// candidates w, w + 4, ... of every chunk for all 64 points.  Each distance
-// has the fold's arithmetic (t = x_e - c_e, acc = fma(t, t, acc), e
-// ascending over the zero-padded row), each thread keeps its first
-// strictly smallest candidate, and the four waves' winners are merged by
-// (distance, id): per point the smallest distance, the lowest id on ties,
-// which is the decision the one-thread-per-point fold takes.
-constexpr int kRescanPts = 64;   // listed points per block step
-constexpr int kRescanCands = 32; // candidate rows per LDS chunk
+// Direct-form rescan of the points a screen pass listed.  A block takes 32
+// listed points at a time (their decoded rows in LDS with an odd row stride)
+// and streams the m candidates through LDS in chunks of 32 rows (row stride
+// DP + 4, so the two rows a wave reads at once sit in different banks), each
+// candidate row read once per 32 points.  Thread t serves point t % 32 and
+// candidates s, s + 8, ... of every chunk, s = t / 32.  Each distance has
+// the fold's arithmetic (t = x_e - c_e, acc = fma(t, t, acc), e ascending
+// over the zero-padded row), each thread keeps its first strictly smallest
+// candidate, and the eight slots' winners are merged by (distance, id): per
+// point the smallest distance, the lowest id on ties, which is the decision
+// the one-thread-per-point fold takes.
+constexpr int kRescanPts = 32;    // listed points per block step
+constexpr int kRescanCands = 32;  // candidate rows per LDS chunk
 
 template <int DP, typename T>
 __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
-  constexpr int P = kRescanPts, CC = kRescanCands, XS = DP + 1, NI = CC / 4;
+  constexpr int P = kRescanPts, CC = kRescanCands, XS = DP + 1, CSTR = DP + 4;
+  constexpr int NS = 256 / P, NI = CC / NS;  // candidate slots, candidates per slot
   __shared__ float xs[P * XS];
-  __shared__ __attribute__((aligned(16))) float cs[CC * DP];
-  __shared__ float rb[4][P];
-  __shared__ int rj[4][P];
-  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  __shared__ __attribute__((aligned(16))) float cs[CC * CSTR];
+  __shared__ float rb[NS][P];
+  __shared__ int rj[NS][P];
+  const int r = threadIdx.x % P, slot = threadIdx.x / P;
   const int nlist = *a.list_len;
   int id0, m;
   if (a.rs) {
@@ -157,25 +159,25 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
     const int np = min(P, nlist - g * P);
     __syncthreads();  // the previous group is merged and written
     for (int idx = threadIdx.x; idx < P * DP; idx += 256) {
-      const int r = idx / DP, e = idx - r * DP;
+      const int q = idx / DP, e = idx - q * DP;
       float v = 0.0f;
-      if (r < np && e < a.d) {
-        const int p = a.list[g * P + r];
+      if (q < np && e < a.d) {
+        const int p = a.list[g * P + q];
         v = Elem<T>::get(X, (int64_t)p * a.d + e, row_scale_of<T>(a.row_scale, p));
       }
-      xs[r * XS + e] = v;
+      xs[q * XS + e] = v;
     }
     float best = INFINITY;
     int bj = -1;
-    const float* xr = xs + lane * XS;
+    const float* xr = xs + r * XS;
     for (int c0 = 0; c0 < m; c0 += CC) {
       const int nc = min(CC, m - c0);
       __syncthreads();  // the previous chunk is consumed (and xs is written)
       for (int idx = threadIdx.x; idx < CC * (DP / 4); idx += 256) {
-        const int j = idx / (DP / 4);
+        const int j = idx / (DP / 4), e4 = idx - j * (DP / 4);
         float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (j < nc) v = reinterpret_cast<const float4*>(C + (int64_t)(c0 + j) * DP)[idx - j * (DP / 4)];
-        reinterpret_cast<float4*>(cs)[idx] = v;
+        if (j < nc) v = reinterpret_cast<const float4*>(C + (int64_t)(c0 + j) * DP)[e4];
+        reinterpret_cast<float4*>(cs + j * CSTR)[e4] = v;
       }
       __syncthreads();
       float acc[NI];
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
         const float x0 = xr[e], x1 = xr[e + 1], x2 = xr[e + 2], x3 = xr[e + 3];
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
-          const float4 cv = reinterpret_cast<const float4*>(cs + (w + 4 * i) * DP)[e / 4];
+          const float4 cv = reinterpret_cast<const float4*>(cs + (slot + NS * i) * CSTR)[e / 4];
           float t = x0 - cv.x;
           acc[i] = fmaf(t, t, acc[i]);
           t = x1 - cv.y;
@@ -199,26 +201,26 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
       }
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
-        const int j = w + 4 * i;
+        const int j = slot + NS * i;
         if (j < nc && acc[i] < best) {
           best = acc[i];
           bj = c0 + j;
         }
       }
     }
-    rb[w][lane] = best;
-    rj[w][lane] = bj;
+    rb[slot][r] = best;
+    rj[slot][r] = bj;
     __syncthreads();
-    if (w == 0 && lane < np) {
-      for (int q = 1; q < 4; ++q) {
-        const float ob = rb[q][lane];
-        const int oj = rj[q][lane];
+    if (slot == 0 && r < np) {
+      for (int q = 1; q < NS; ++q) {
+        const float ob = rb[q][r];
+        const int oj = rj[q][r];
         if (ob < best || (ob == best && (unsigned)oj < (unsigned)bj)) {
           best = ob;
           bj = oj;
         }
       }
-      const int p = a.list[g * P + lane];
+      const int p = a.list[g * P + r];
       if (a.first) {
         a.D2[p] = best;
         a.A[p] = bj >= 0 ? id0 + bj : -1;
@@ -296,7 +298,7 @@ hipError_t launch_fold_direct(kmpar_dtype dt, int DP, const FoldArgs& a, hipStre
 template <typename T>
 static hipError_t launch_rescan_t(int DP, const FoldArgs& a, hipStream_t s) {
   // the listed count is only known on the device: enough blocks for the
-  // largest list up to four per CU, each looping over groups of 64 points
+  // largest list up to four per CU, each looping over groups of points
   int blocks = (a.list_cap + kRescanPts - 1) / kRescanPts;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) return hipSuccess;
