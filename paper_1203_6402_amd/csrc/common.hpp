@@ -88,23 +88,32 @@ __device__ __forceinline__ float decode_e4m3(uint8_t q) {
 
 template <typename T>
 struct Elem;
+// get: element idx of X; from_bits: the same value from the element's raw
+// bits (the low 8 * sizeof(T) bits of b), for kernels that load vectors.
 template <>
 struct Elem<float> {
   static __device__ __forceinline__ float get(const float* X, int64_t idx, float) { return X[idx]; }
+  static __device__ __forceinline__ float from_bits(uint32_t b, float) { return __uint_as_float(b); }
 };
 template <>
 struct Elem<bf16_t> {
   static __device__ __forceinline__ float get(const bf16_t* X, int64_t idx, float) {
     return decode_bf16(X[idx].bits);
   }
+  static __device__ __forceinline__ float from_bits(uint32_t b, float) {
+    return decode_bf16((uint16_t)b);
+  }
 };
 // An FP8 element is fl(q * s): the product is rounded once, never fused into
 // the arithmetic that uses it (every kernel then sees the same values).
 template <>
 struct Elem<fp8_t> {
-  static __device__ __forceinline__ float get(const fp8_t* X, int64_t idx, float scale) {
+  static __device__ __forceinline__ float from_bits(uint32_t b, float scale) {
 #pragma clang fp contract(off)
-    return decode_e4m3(X[idx].bits) * scale;
+    return decode_e4m3((uint8_t)b) * scale;
+  }
+  static __device__ __forceinline__ float get(const fp8_t* X, int64_t idx, float scale) {
+    return from_bits(X[idx].bits, scale);
   }
 };
 

@@ -207,29 +207,55 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
                                                     float* D2, int* A, float* norms,
                                                     u16x8* Apre) {
   extern __shared__ float xs[];  // [64][d] rows, then the first center [DP]
+  __shared__ float ss[64];       // FP8 row scales
   float* c0 = xs + 64 * d;
   const int p0 = blockIdx.x * 64;
   const int np = max(0, min(64, n - p0));
   const int id0 = rs[0];
   for (int e = threadIdx.x; e < DP; e += 256) c0[e] = C[(int64_t)id0 * DP + e];
-  // coalesced, twelve loads in flight per thread before the LDS stores
-  constexpr int U = 12;
+  constexpr bool SC = ScaledRows<T>::value;
+  if constexpr (SC) {
+    if (threadIdx.x < np) ss[threadIdx.x] = row_scale[p0 + threadIdx.x];
+    __syncthreads();
+  }
+  // The block's rows are one contiguous span starting 16-byte aligned
+  // (64 d sizeof(T) bytes per block): coalesced 16-byte loads, four in
+  // flight per thread, each decoded into EPV elements; a tail shorter than
+  // 16 bytes is read element by element.
+  constexpr int S = (int)sizeof(T), EPV = 16 / S;
   const int cnt = np * d;
-  for (int i0 = 0; i0 < cnt; i0 += U * 256) {
-    float v[U];
+  const int nvec = cnt * S / 16;
+  const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(X) +
+                                                    (int64_t)p0 * d * S);
+  constexpr int U = 4;
+  for (int v0 = 0; v0 < nvec; v0 += U * 256) {
+    uint4 w[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int idx = i0 + u * 256 + threadIdx.x;
-      v[u] = idx < cnt ? Elem<T>::get(X, (int64_t)p0 * d + idx,
-                                      row_scale_of<T>(row_scale, p0 + idx / d))
-                       : 0.0f;
+      const int idx = v0 + u * 256 + threadIdx.x;
+      if (idx < nvec) w[u] = src[idx];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int idx = i0 + u * 256 + threadIdx.x;
-      if (idx < cnt) xs[idx] = v[u];
+      const int idx = v0 + u * 256 + threadIdx.x;
+      if (idx < nvec) {
+        const uint32_t wd[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+        const int e = idx * EPV;
+        int row = e / d, col = e - row * d;
+#pragma unroll
+        for (int k = 0; k < EPV; ++k) {
+          const uint32_t b = wd[(k * S) / 4] >> (8 * ((k * S) % 4));
+          xs[e + k] = Elem<T>::from_bits(b, SC ? ss[row] : 1.0f);
+          if (++col == d) {
+            col = 0;
+            ++row;
+          }
+        }
+      }
     }
   }
+  for (int e = nvec * EPV + threadIdx.x; e < cnt; e += 256)
+    xs[e] = Elem<T>::get(X, (int64_t)p0 * d + e, row_scale_of<T>(row_scale, p0 + e / d));
   __syncthreads();
   if (threadIdx.x < np) {
     const float* xr = xs + threadIdx.x * d;
