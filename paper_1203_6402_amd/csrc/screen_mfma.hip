@@ -304,6 +304,12 @@ constexpr int kStageBytes = 32 * 1024; // LDS per staging buffer
 // 16-point row tiles per wave: four while the A operands of KS k-steps fit
 // the registers beside the accumulators and running maxima, two beyond 8.
 constexpr int screen_krt(int KS) { return KS <= 8 ? 4 : 2; }
+// Rows with scales spend more registers per value (row scales, the scaled
+// epilogue): two row tiles from five k-steps on, so two waves share a SIMD.
+template <int KS, typename T>
+constexpr int screen_krt_t() {
+  return ScaledRows<T>::value ? (KS <= 4 ? 4 : 2) : screen_krt(KS);
+}
 constexpr int kBlockPts = kWaves * 4 * 16;  // the largest block (256 points)
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -412,7 +418,7 @@ __device__ __forceinline__ float refine_dist(const T* x, const float* c, int d, 
 // The screen of block `blk` of the points of `a` (kWaves * KRT * 16 points).
 template <int SPLIT, int KS, typename T, bool DIRECT>
 __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
-  constexpr int KRT = screen_krt(KS);  // row tiles per wave
+  constexpr int KRT = screen_krt_t<KS, T>();  // row tiles per wave
   constexpr int WP = KRT * 16;         // points per wave
   constexpr int BP = kWaves * WP;      // points per block
   constexpr int CT = screen_chunk_tiles(KS);        // candidate tiles per chunk
@@ -732,7 +738,7 @@ __global__ void k_list_reset(int* list_len, kmpar_stats* st) {
 
 template <int SPLIT, int KS, typename T>
 static void launch_one(const ScreenArgs& a, hipStream_t s) {
-  constexpr int BP = kWaves * screen_krt(KS) * 16;
+  constexpr int BP = kWaves * screen_krt_t<KS, T>() * 16;
   const int blocks = (a.n + BP - 1) / BP;
   if (a.Apre)
     hipLaunchKernelGGL((k_screen<SPLIT, KS, T, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
