@@ -7,6 +7,7 @@ kernels.  Importing this module fails loudly when the library is missing.
 from __future__ import annotations
 
 import ctypes
+from types import SimpleNamespace
 import os
 from dataclasses import dataclass
 
@@ -249,23 +250,20 @@ class Context:
         """kmpar_init_batched: instance i uses Philox inst = i.  Returns
         (list of k_i x d_i center tensors, list of stats dicts, list of traces
         or None)."""
-        centers, offs, stats, keep, traces = _batched_impl(self, Xs, ks, ells, rounds, seed,
-                                                           row_scales, stream, trace)
-        self._batch_keep = keep                   # device tables live until the next call
-        views = [centers[offs[i]:offs[i] + int(ks[i]) * Xs[i].shape[1]].view(int(ks[i]),
-                                                                              Xs[i].shape[1])
-                 for i in range(len(Xs))]
+        b = _batched_impl(self, Xs, ks, ells, rounds, seed, row_scales, stream, trace)
+        self._batch_keep = b                      # device tables live until the next call
+        traces = b.traces
         if not check:
-            return views, stats, traces
-        ssz = ctypes.sizeof(Stats)
-        raw = stats.cpu()
-        st = [parse_stats(raw[i * ssz:(i + 1) * ssz], rounds) for i in range(len(Xs))]
+            views = [b.centers[b.offs[i]:b.offs[i] + int(ks[i]) * Xs[i].shape[1]]
+                     .view(int(ks[i]), Xs[i].shape[1]) for i in range(len(Xs))]
+            return views, b.stats, traces
+        centers, st = _batched_results(b, ks, Xs, rounds)
         if traces is not None:
             for t, s_ in zip(traces, st):
                 t["cand_point"] = t["cand_point"][:s_["n_candidates"]]
                 t["cand_weight"] = t["cand_weight"][:s_["n_candidates"]]
                 t["center_cand"] = t["center_cand"][:s_["n_centers"]]
-        return [v[:s_["n_centers"]] for v, s_ in zip(views, st)], st, traces
+        return centers, st, traces
 
     def lloyd_step(self, X, C, row_scale=None, want_assign=False, stream=None):
         """Updates C (k x d FP32, contiguous) in place; returns (assign|None, phi)."""
@@ -308,7 +306,8 @@ class CapturedInit:
         return parse_stats(self.stats_raw, self.rounds)
 
 
-def _batched_impl(ctx, Xs, ks, ells, rounds, seed, row_scales, stream, trace=False):
+def _batched_impl(ctx, Xs, ks, ells, rounds, seed, row_scales, stream, trace=False, launch=True,
+                  shared_ws=True):
     count = len(Xs)
     dev = Xs[0].device
     dt = ctx._x(Xs[0], row_scales[0] if row_scales else None)
@@ -347,13 +346,59 @@ def _batched_impl(ctx, Xs, ks, ells, rounds, seed, row_scales, stream, trace=Fal
     out = _sz(0)
     ctx._check(_lib.kmpar_workspace_size_batched(ctx._h, desc.ctypes.data, count, dt,
                                                  ctypes.byref(out)), "kmpar_workspace_size_batched")
-    ws = ctx._workspace(int(out.value), dev)
-    ctx._check(_lib.kmpar_init_batched(ctx._h, desc.ctypes.data, desc_dev.data_ptr(), count, dt,
-                                       seed, ws.data_ptr(), ws.numel(),
-                                       tr_dev.data_ptr() if tr_dev is not None else None,
+    ws = ctx._workspace(int(out.value), dev) if shared_ws else \
+        torch.empty(max(int(out.value), 256), dtype=torch.uint8, device=dev)
+    batch = SimpleNamespace(desc=desc, desc_dev=desc_dev, count=count, dt=dt, ws=ws, tr_dev=tr_dev,
+                            centers=centers, offs=offs, stats=stats, traces=traces)
+    if launch:
+        _batched_launch(ctx, batch, seed, stream)
+    return batch
+
+
+def _batched_launch(ctx, b, seed, stream):
+    ctx._check(_lib.kmpar_init_batched(ctx._h, b.desc.ctypes.data, b.desc_dev.data_ptr(), b.count,
+                                       b.dt, seed, b.ws.data_ptr(), b.ws.numel(),
+                                       b.tr_dev.data_ptr() if b.tr_dev is not None else None,
                                        _stream(stream)),
                "kmpar_init_batched")
-    return centers, offs, stats, (desc_dev, tr_dev), traces
+
+
+def _batched_results(b, ks, Xs, rounds):
+    """Center views and parsed stats of a finished batch."""
+    views = [b.centers[b.offs[i]:b.offs[i] + int(ks[i]) * Xs[i].shape[1]].view(int(ks[i]),
+                                                                                Xs[i].shape[1])
+             for i in range(len(Xs))]
+    ssz = ctypes.sizeof(Stats)
+    raw = b.stats.cpu()
+    st = [parse_stats(raw[i * ssz:(i + 1) * ssz], rounds) for i in range(len(Xs))]
+    return [v[:s_["n_centers"]] for v, s_ in zip(views, st)], st
+
+
+class CapturedBatch:
+    """kmpar_init_batched captured once into a HIP graph (torch.cuda.CUDAGraph)
+    and replayed.  The instance table, the outputs and a workspace of its own
+    are made before the capture, so the graph holds only the library's
+    launches; every replay rewrites the centers and the stats records."""
+
+    def __init__(self, ctx, Xs, ks, ells, rounds, seed, row_scales=None):
+        self.batch = _batched_impl(ctx, Xs, ks, ells, rounds, seed, row_scales, None,
+                                   launch=True, shared_ws=False)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        self.stream = torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            with torch.cuda.graph(self.graph, stream=self.stream):
+                _batched_launch(ctx, self.batch, seed, self.stream)
+        self._keep = (ctx, list(Xs), row_scales)
+        self._shape = (list(ks), rounds)
+
+    def replay(self):
+        self.graph.replay()
+
+    def results(self):
+        """(list of k_i x d_i center tensors, list of stats dicts)."""
+        ks, rounds = self._shape
+        return _batched_results(self.batch, ks, self._keep[1], rounds)
 
 
 def parse_stats(st: torch.Tensor, rounds: int) -> dict:

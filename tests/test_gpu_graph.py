@@ -38,3 +38,26 @@ def test_graph_replays_match_eager(K, mode):
         # eager work on another context and input between replays
         other.init(Y, k=30, ell=60.0, rounds=3, seed=rep)
         torch.cuda.synchronize()
+
+
+def test_batched_graph_replays_match_eager(K):
+    # A batch of independent instances in one fixed launch sequence, captured once:
+    # every replay must give the eager batch's centers and stats.
+    ns, ds, ks = synth.batch_instances(40, seed=6, n_lo=500, n_hi=8000)
+    Xs = [torch.from_numpy(X).to("cuda:0") for X in synth.batch_gauss_mixture(ns, ds, ks, seed=6)]
+    ells = 2.0 * ks
+    ctx = K.Context(0, K.MODE_PLAIN_FP32)
+    ec, es, _ = ctx.init_batched(Xs, ks, ells, 4, seed=5)
+    cap = K.CapturedBatch(ctx, Xs, ks, ells, 4, 5)
+    Y = torch.from_numpy(synth.gauss_mixture(20000, 15, 30, 10.0, seed=2)).to("cuda:0")
+    for rep in range(3):
+        cap.batch.centers.zero_()
+        cap.replay()
+        torch.cuda.synchronize()
+        cs, st = cap.results()
+        for i in range(len(Xs)):
+            assert torch.equal(cs[i], ec[i]), (rep, i)
+            assert st[i] == es[i], (rep, i)
+        # eager work on the same context (its own workspace) between replays
+        ctx.init(Y, k=30, ell=60.0, rounds=3, seed=rep)
+        torch.cuda.synchronize()
