@@ -171,11 +171,13 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
 template <int SPLIT, int KS, typename T>
 __global__ __launch_bounds__(256) void k_prep_a(const T* X, const float* row_scale, int n, int d,
                                                 u16x8* Apre) {
-  extern __shared__ float xs[];  // [64][d]
+  extern __shared__ float xs[];  // [64][XS], XS = d + 1 when d is a multiple of 32
+  const int pad = d % 32 == 0 ? 1 : 0, XS = d + pad;
   const int p0 = blockIdx.x * 64;
   const int np = max(0, min(64, n - p0));
   for (int idx = threadIdx.x; idx < np * d; idx += 256)
-    xs[idx] = Elem<T>::get(X, (int64_t)p0 * d + idx, row_scale_of<T>(row_scale, p0 + idx / d));
+    xs[idx + (idx / d) * pad] =
+        Elem<T>::get(X, (int64_t)p0 * d + idx, row_scale_of<T>(row_scale, p0 + idx / d));
   __syncthreads();
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   const int row = w * 16 + (lane % 16);
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(256) void k_prep_a(const T* X, const float* row_sca
       const int k = s * 32 + (lane / 16) * 8 + e;
       const int part = k / d, coord = k - part * d;
       v[e] = (valid && part < SPLIT)
-                 ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * d + coord]), part)
+                 ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * XS + coord]), part)
                  : (uint16_t)0;
     }
     Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
@@ -206,9 +208,13 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
                                                     int d, int DP, const float* C, const int* rs,
                                                     float* D2, int* A, float* norms,
                                                     u16x8* Apre) {
-  extern __shared__ float xs[];  // [64][d] rows, then the first center [DP]
+  // [64][XS] rows, then the first center [DP]; XS = d + 1 when d is a
+  // multiple of 32, so the 64 threads that walk one row each do not all read
+  // the same bank
+  extern __shared__ float xs[];
   __shared__ float ss[64];       // FP8 row scales
-  float* c0 = xs + 64 * d;
+  const int pad = d % 32 == 0 ? 1 : 0, XS = d + pad;
+  float* c0 = xs + 64 * XS;
   const int p0 = blockIdx.x * 64;
   const int np = max(0, min(64, n - p0));
   const int id0 = rs[0];
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
 #pragma unroll
         for (int k = 0; k < EPV; ++k) {
           const uint32_t b = wd[(k * S) / 4] >> (8 * ((k * S) % 4));
-          xs[e + k] = Elem<T>::from_bits(b, SC ? ss[row] : 1.0f);
+          xs[e + k + row * pad] = Elem<T>::from_bits(b, SC ? ss[row] : 1.0f);
           if (++col == d) {
             col = 0;
             ++row;
@@ -255,10 +261,10 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
     }
   }
   for (int e = nvec * EPV + threadIdx.x; e < cnt; e += 256)
-    xs[e] = Elem<T>::get(X, (int64_t)p0 * d + e, row_scale_of<T>(row_scale, p0 + e / d));
+    xs[e + (e / d) * pad] = Elem<T>::get(X, (int64_t)p0 * d + e, row_scale_of<T>(row_scale, p0 + e / d));
   __syncthreads();
   if (threadIdx.x < np) {
-    const float* xr = xs + threadIdx.x * d;
+    const float* xr = xs + threadIdx.x * XS;
     float acc = 0.0f, nx = 0.0f;
 #pragma unroll 8
     for (int e = 0; e < d; ++e) {
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
         const int k = s * 32 + (lane / 16) * 8 + e;
         const int part = k / d, coord = k - part * d;
         v[e] = (valid && part < SPLIT)
-                   ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * d + coord]), part)
+                   ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * XS + coord]), part)
                    : (uint16_t)0;
       }
       Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
@@ -764,11 +770,16 @@ static hipError_t launch_split(int KS, const ScreenArgs& a, hipStream_t s) {
 }
 
 template <int SPLIT, int KS, typename T>
-static void launch_prep_a_one(const void* X, const float* rsc, int n, int d, void* Apre,
-                              hipStream_t s) {
+static hipError_t launch_prep_a_one(const void* X, const float* rsc, int n, int d, void* Apre,
+                                    hipStream_t s) {
   const int blocks = (n + kBlockPts - 1) / kBlockPts * (kBlockPts / 64);
-  hipLaunchKernelGGL((k_prep_a<SPLIT, KS, T>), dim3(blocks), dim3(256), (size_t)64 * d * 4, s,
+  const size_t lds = (size_t)64 * (d + (d % 32 == 0 ? 1 : 0)) * 4;
+  hipError_t e = hipFuncSetAttribute((const void*)k_prep_a<SPLIT, KS, T>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_prep_a<SPLIT, KS, T>), dim3(blocks), dim3(256), lds, s,
                      static_cast<const T*>(X), rsc, n, d, static_cast<u16x8*>(Apre));
+  return hipGetLastError();
 }
 
 template <int SPLIT, typename T, int MAXKS = kScreenMaxKS>
@@ -777,7 +788,7 @@ static hipError_t launch_prep_a_split(int KS, const void* X, const float* rsc, i
   if (KS < 1 || KS > MAXKS) return hipErrorInvalidValue;
   switch (KS) {
 #define KMPAR_PA(V) \
-  case V: if constexpr (V <= MAXKS) launch_prep_a_one<SPLIT, V, T>(X, rsc, n, d, Apre, s); break;
+  case V: if constexpr (V <= MAXKS) return launch_prep_a_one<SPLIT, V, T>(X, rsc, n, d, Apre, s); break;
     KMPAR_PA(1) KMPAR_PA(2) KMPAR_PA(3) KMPAR_PA(4) KMPAR_PA(5) KMPAR_PA(6) KMPAR_PA(7)
     KMPAR_PA(8) KMPAR_PA(9) KMPAR_PA(10) KMPAR_PA(11) KMPAR_PA(12) KMPAR_PA(13) KMPAR_PA(14)
     KMPAR_PA(15) KMPAR_PA(16)
@@ -794,7 +805,7 @@ static hipError_t launch_first_one(const void* X, const float* rsc, int n, int d
   // grid: 64-row blocks; with PREP the A tiles of all ceil(n / 256) * 16
   // tiles the screen reads are written (rows past n as zeros)
   const int blocks = PREP ? (n + kBlockPts - 1) / kBlockPts * (kBlockPts / 64) : (n + 63) / 64;
-  const size_t lds = ((size_t)64 * d + DP) * 4;
+  const size_t lds = ((size_t)64 * (d + (d % 32 == 0 ? 1 : 0)) + DP) * 4;
   hipError_t e = hipFuncSetAttribute((const void*)k_first_prep<SPLIT, KS, T, PREP>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
