@@ -105,9 +105,24 @@ typedef enum kmpar_option {
    * in LDS, rows streamed), 2 = several workgroups with LDS-resident row
    * slices, 3 = several workgroups reading the rows from global memory.
    * All give the same picks up to FP64 summation order. */
-  KMPAR_OPT_RECLUSTER_PATH = 0
+  KMPAR_OPT_RECLUSTER_PATH = 0,
+  /* Tile shapes of kmpar_init_batched's distance pass: 1 (default) = the
+   * first batch that meets a (dtype, padded row length) times every
+   * candidates-per-step variant of that group's fold on its first round
+   * (re-applying a fold changes nothing, so results do not depend on it) and
+   * the context keeps the fastest for later batches; 0 = fixed defaults.
+   * Tuning synchronises the stream once per new shape and is skipped while
+   * the stream is being captured into a graph. */
+  KMPAR_OPT_BATCH_AUTOTUNE = 1
 } kmpar_option;
 int kmpar_set_option(kmpar_ctx* ctx, kmpar_option opt, int64_t value);
+
+/* The batched tile shapes tuned so far, one entry per (dtype, padded row
+ * length): up to `cap` entries are written to dtype[], dp[] (padded row
+ * length) and cb[] (candidates per step); *count receives the number of
+ * entries.  Host memory; no device work. */
+int kmpar_batch_tiles(const kmpar_ctx* ctx, int32_t* dtype, int32_t* dp, int32_t* cb, int32_t cap,
+                      int32_t* count);
 
 /* Kernel timing for measurement: while enabled, every launch of a distance
  * kernel (the fold of Algorithm 2 steps 4-5 and of the assignment passes) is

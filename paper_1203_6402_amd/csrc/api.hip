@@ -31,6 +31,7 @@ struct kmpar_ctx {
   std::string err;
   bool prof = false;
   int recl_path = 0;  // KMPAR_OPT_RECLUSTER_PATH
+  kmpar::BatchTuner tuner;  // KMPAR_OPT_BATCH_AUTOTUNE and its choices
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
 };
@@ -383,8 +384,28 @@ int kmpar_set_option(kmpar_ctx* ctx, kmpar_option opt, int64_t value) {
       if (value < 0 || value > 3) return set_err(ctx, KMPAR_E_INVAL, "recluster path %lld", (long long)value);
       ctx->recl_path = (int)value;
       return KMPAR_OK;
+    case KMPAR_OPT_BATCH_AUTOTUNE:
+      if (value < 0 || value > 1) return set_err(ctx, KMPAR_E_INVAL, "batch autotune %lld", (long long)value);
+      ctx->tuner.enabled = value != 0;
+      return KMPAR_OK;
   }
   return set_err(ctx, KMPAR_E_INVAL, "unknown option %d", (int)opt);
+}
+
+int kmpar_batch_tiles(const kmpar_ctx* ctx, int32_t* dtype, int32_t* dp, int32_t* cb, int32_t cap,
+                      int32_t* count) {
+  if (!ctx || !count || cap < 0 || (cap > 0 && (!dtype || !dp || !cb))) return KMPAR_E_INVAL;
+  int32_t c = 0;
+  for (const auto& kv : ctx->tuner.cb) {
+    if (c < cap) {
+      dtype[c] = kv.first / 4096;
+      dp[c] = kv.first % 4096;
+      cb[c] = kv.second;
+    }
+    ++c;
+  }
+  *count = c;
+  return KMPAR_OK;
 }
 
 int kmpar_profile_enable(kmpar_ctx* ctx, int on) {
@@ -758,7 +779,7 @@ int kmpar_init_batched(kmpar_ctx* ctx, const kmpar_instance* inst_host,
   if (traces_dev && ((uintptr_t)traces_dev & 7u))
     return set_err(ctx, KMPAR_E_INVAL, "traces_dev misaligned");
   KMPAR_HIP(launch_batched(dtype, inst_host, inst_dev, count, inst_host[0].rounds, seed, ws,
-                           traces_dev, (hipStream_t)stream));
+                           traces_dev, &ctx->tuner, (hipStream_t)stream));
   return KMPAR_OK;
 }
 

@@ -8,6 +8,8 @@
 // instance and skips candidates that the new pick provably cannot improve.
 #include <math.h>
 
+#include <map>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "recluster_block.hpp"
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(256) void kb_gather(const kmpar_instance* inst, int
 // ---------------------------------------------------------------- the fold
 // Same per-point arithmetic as k_fold_direct: candidates in id order, strict
 // improvement, FP32 direct form.
-template <int DP, typename T>
+template <int DP, typename T, int CB>
 __global__ __launch_bounds__(kBFold) void kb_fold(const kmpar_instance* inst, int rounds,
                                                   PlanPtrs p, int g, int t, int first) {
   constexpr int DCH = DP <= 128 ? DP : DP / 2;
@@ -239,25 +241,35 @@ __global__ __launch_bounds__(kBFold) void kb_fold(const kmpar_instance* inst, in
   const int64_t row = (int64_t)i * d;
   float best = INFINITY;
   int bj = -1;
+  // CB candidates per step, each an independent chain of FMAs (the tile
+  // shape the batch's tuner chooses); candidates in id order, the first
+  // strictly smallest kept, so every CB gives the same result.
   if constexpr (NCH == 1) {
     float x[DP];
 #pragma unroll
     for (int j = 0; j < DP; ++j) x[j] = (j < d) ? Elem<T>::get(X, row + j, sc) : 0.0f;
-    for (int c = 0; c < m; ++c) {
-      const float* __restrict__ cr = C + (int64_t)c * DP;
-      float acc = 0.0f;
+    for (int c0 = 0; c0 < m; c0 += CB) {
+      float acc[CB];
 #pragma unroll
-      for (int j = 0; j < DP; ++j) {
-        const float tt = x[j] - cr[j];
-        acc = fmaf(tt, tt, acc);
+      for (int qq = 0; qq < CB; ++qq) {
+        acc[qq] = 0.0f;
+        if (c0 + qq < m) {
+          const float* __restrict__ cr = C + (int64_t)(c0 + qq) * DP;
+#pragma unroll
+          for (int j = 0; j < DP; ++j) {
+            const float tt = x[j] - cr[j];
+            acc[qq] = fmaf(tt, tt, acc[qq]);
+          }
+        }
       }
-      if (acc < best) {
-        best = acc;
-        bj = c;
-      }
+#pragma unroll
+      for (int qq = 0; qq < CB; ++qq)
+        if (c0 + qq < m && acc[qq] < best) {
+          best = acc[qq];
+          bj = c0 + qq;
+        }
     }
   } else {
-    constexpr int CB = 8;
     for (int c0 = 0; c0 < m; c0 += CB) {
       float acc[CB];
 #pragma unroll
@@ -505,19 +517,55 @@ size_t batched_workspace(const kmpar_instance* inst, int count, int rounds, int*
   return (size_t)(pp.regions - (char*)nullptr) + (size_t)total;
 }
 
-template <int DP, typename T>
+// Candidate blocks the tuner tries: rows of up to 128 padded elements are
+// held whole in registers (1, 2 or 4 candidates per step), wider rows in
+// two halves (4 or 8).
+constexpr int kCbNarrow[3] = {1, 2, 4};
+constexpr int kCbWide[2] = {4, 8};
+static int batch_cb_default(int DP) { return DP <= 128 ? 1 : 8; }
+static int batch_cb_variants(int DP, int* out) {
+  if (DP <= 128) {
+    for (int i = 0; i < 3; ++i) out[i] = kCbNarrow[i];
+    return 3;
+  }
+  for (int i = 0; i < 2; ++i) out[i] = kCbWide[i];
+  return 2;
+}
+
+template <int DP, typename T, int CB>
 static void launch_bfold(const kmpar_instance* inst, int rounds, const PlanPtrs& p, int g, int t,
                          int first, int tiles, hipStream_t s) {
-  hipLaunchKernelGGL((kb_fold<DP, T>), dim3(tiles), dim3(kBFold), 0, s, inst, rounds, p, g, t, first);
+  hipLaunchKernelGGL((kb_fold<DP, T, CB>), dim3(tiles), dim3(kBFold), 0, s, inst, rounds, p, g, t,
+                     first);
+}
+
+template <int DP, typename T>
+static hipError_t launch_bfold_cb(int cb, const kmpar_instance* inst, int rounds, const PlanPtrs& p,
+                                  int g, int t, int first, int tiles, hipStream_t s) {
+  if constexpr (DP <= 128) {
+    switch (cb) {
+      case 1: launch_bfold<DP, T, 1>(inst, rounds, p, g, t, first, tiles, s); return hipSuccess;
+      case 2: launch_bfold<DP, T, 2>(inst, rounds, p, g, t, first, tiles, s); return hipSuccess;
+      case 4: launch_bfold<DP, T, 4>(inst, rounds, p, g, t, first, tiles, s); return hipSuccess;
+    }
+  } else {
+    switch (cb) {
+      case 4: launch_bfold<DP, T, 4>(inst, rounds, p, g, t, first, tiles, s); return hipSuccess;
+      case 8: launch_bfold<DP, T, 8>(inst, rounds, p, g, t, first, tiles, s); return hipSuccess;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
-static hipError_t launch_bfold_dp(int DP, const kmpar_instance* inst, int rounds, const PlanPtrs& p,
-                                  int g, int t, int first, int tiles, hipStream_t s) {
+static hipError_t launch_bfold_dp(int DP, int cb, const kmpar_instance* inst, int rounds,
+                                  const PlanPtrs& p, int g, int t, int first, int tiles,
+                                  hipStream_t s) {
   if (tiles <= 0) return hipSuccess;
+  hipError_t e = hipErrorInvalidValue;
   switch (DP) {
 #define KMPAR_CASE(V) \
-  case V: launch_bfold<V, T>(inst, rounds, p, g, t, first, tiles, s); break;
+  case V: e = launch_bfold_cb<V, T>(cb, inst, rounds, p, g, t, first, tiles, s); break;
     KMPAR_CASE(4) KMPAR_CASE(8) KMPAR_CASE(12) KMPAR_CASE(16) KMPAR_CASE(20) KMPAR_CASE(24)
     KMPAR_CASE(28) KMPAR_CASE(32) KMPAR_CASE(36) KMPAR_CASE(40) KMPAR_CASE(44) KMPAR_CASE(48)
     KMPAR_CASE(52) KMPAR_CASE(56) KMPAR_CASE(60) KMPAR_CASE(64) KMPAR_CASE(80) KMPAR_CASE(96)
@@ -526,13 +574,50 @@ static hipError_t launch_bfold_dp(int DP, const kmpar_instance* inst, int rounds
 #undef KMPAR_CASE
     default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
+// Times every candidate-block variant of group g's fold of round t (the
+// launches re-apply the same fold, which changes nothing after the first)
+// and returns the fastest; the stream is synchronised once.
 template <typename T>
-static hipError_t run_batched_t(const kmpar_instance* ih, const kmpar_instance* idev, int count,
-                                int rounds, uint64_t seed, void* ws, const kmpar_trace* tr,
-                                hipStream_t s) {
+static hipError_t tune_bfold(int DP, const kmpar_instance* inst, int rounds, const PlanPtrs& p,
+                             int g, int t, int tiles, hipStream_t s, int* best_cb) {
+  int vars[3];
+  const int nv = batch_cb_variants(DP, vars);
+  hipEvent_t ev[4];
+  for (int i = 0; i <= nv; ++i) {
+    hipError_t e = hipEventCreate(&ev[i]);
+    if (e != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+      return e;
+    }
+  }
+  hipError_t e = hipEventRecord(ev[0], s);
+  for (int i = 0; i < nv && e == hipSuccess; ++i) {
+    e = launch_bfold_dp<T>(DP, vars[i], inst, rounds, p, g, t, 0, tiles, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[i + 1], s);
+  }
+  if (e == hipSuccess) e = hipEventSynchronize(ev[nv]);
+  float best_ms = 0.0f;
+  *best_cb = vars[0];
+  for (int i = 0; i < nv && e == hipSuccess; ++i) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+    if (e == hipSuccess && (i == 0 || ms < best_ms)) {
+      best_ms = ms;
+      *best_cb = vars[i];
+    }
+  }
+  for (int i = 0; i <= nv; ++i) (void)hipEventDestroy(ev[i]);
+  return e;
+}
+
+template <typename T>
+static hipError_t run_batched_t(kmpar_dtype dt, const kmpar_instance* ih, const kmpar_instance* idev,
+                                int count, int rounds, uint64_t seed, void* ws,
+                                const kmpar_trace* tr, BatchTuner* tuner, hipStream_t s) {
   int dps[kBatchMaxGroups];
   int G = 0;
   (void)batched_workspace(ih, count, rounds, &G, dps);
@@ -554,12 +639,28 @@ static hipError_t run_batched_t(const kmpar_instance* ih, const kmpar_instance* 
     if (capT > max_cap) max_cap = capT;
     if (ih[i].k > max_k) max_k = ih[i].k;
   }
+  // tile shapes: the tuner's choice per (dtype, padded row length), tuned on
+  // round 1 the first time a shape is seen (never under stream capture)
+  int gcb[kBatchMaxGroups];
+  bool gtune[kBatchMaxGroups];
+  bool can_tune = tuner && tuner->enabled;
+  if (can_tune) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      can_tune = false;
+  }
+  for (int g = 0; g < G; ++g) {
+    const int key = BatchTuner::key((int)dt, dps[g]);
+    const bool known = tuner && tuner->cb.count(key) != 0;
+    gcb[g] = known ? tuner->cb.at(key) : batch_cb_default(dps[g]);
+    gtune[g] = can_tune && !known && rounds >= 1;
+  }
   const dim3 per_inst(count), inst_threads((count + 255) / 256);
   hipLaunchKernelGGL(kb_plan, dim3(1), dim3(1024), 0, s, idev, count, rounds, gt, p);
   hipLaunchKernelGGL(kb_first, inst_threads, dim3(256), 0, s, idev, count, rounds, p, seed);
   hipLaunchKernelGGL(kb_gather<T>, per_inst, dim3(256), 0, s, idev, rounds, p, 0);
   for (int g = 0; g < G; ++g) {
-    hipError_t e = launch_bfold_dp<T>(dps[g], idev, rounds, p, g, 0, 1, gtiles[g], s);
+    hipError_t e = launch_bfold_dp<T>(dps[g], gcb[g], idev, rounds, p, g, 0, 1, gtiles[g], s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(kb_phi_partial, dim3((unsigned)phi_blocks), dim3(256), 0, s, idev, count,
@@ -573,7 +674,13 @@ static hipError_t run_batched_t(const kmpar_instance* ih, const kmpar_instance* 
                        rounds, p, seed, t);
     hipLaunchKernelGGL(kb_gather<T>, per_inst, dim3(256), 0, s, idev, rounds, p, t);
     for (int g = 0; g < G; ++g) {
-      hipError_t e = launch_bfold_dp<T>(dps[g], idev, rounds, p, g, t, 0, gtiles[g], s);
+      hipError_t e;
+      if (t == 1 && gtune[g] && gtiles[g] > 0) {
+        e = tune_bfold<T>(dps[g], idev, rounds, p, g, t, gtiles[g], s, &gcb[g]);
+        if (e == hipSuccess) tuner->cb[BatchTuner::key((int)dt, dps[g])] = gcb[g];
+      } else {
+        e = launch_bfold_dp<T>(dps[g], gcb[g], idev, rounds, p, g, t, 0, gtiles[g], s);
+      }
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kb_phi_partial, dim3((unsigned)phi_blocks), dim3(256), 0, s, idev, count,
@@ -595,11 +702,11 @@ static hipError_t run_batched_t(const kmpar_instance* ih, const kmpar_instance* 
 
 hipError_t launch_batched(kmpar_dtype dt, const kmpar_instance* ih, const kmpar_instance* idev,
                           int count, int rounds, uint64_t seed, void* ws, const kmpar_trace* tr,
-                          hipStream_t s) {
+                          BatchTuner* tuner, hipStream_t s) {
   switch (dt) {
-    case KMPAR_F32: return run_batched_t<float>(ih, idev, count, rounds, seed, ws, tr, s);
-    case KMPAR_BF16: return run_batched_t<bf16_t>(ih, idev, count, rounds, seed, ws, tr, s);
-    case KMPAR_FP8_E4M3: return run_batched_t<fp8_t>(ih, idev, count, rounds, seed, ws, tr, s);
+    case KMPAR_F32: return run_batched_t<float>(dt, ih, idev, count, rounds, seed, ws, tr, tuner, s);
+    case KMPAR_BF16: return run_batched_t<bf16_t>(dt, ih, idev, count, rounds, seed, ws, tr, tuner, s);
+    case KMPAR_FP8_E4M3: return run_batched_t<fp8_t>(dt, ih, idev, count, rounds, seed, ws, tr, tuner, s);
   }
   return hipErrorInvalidValue;
 }

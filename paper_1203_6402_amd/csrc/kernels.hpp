@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+
 #include "../../include/kmpar.h"
 
 namespace kmpar {
@@ -188,8 +190,15 @@ hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_s
 // Batched k-means|| (batched.hip).
 constexpr int kBatchMaxGroups = 24;
 size_t batched_workspace(const kmpar_instance* inst, int count, int rounds, int* G_out, int* dps);
+// Tile shapes of the batched distance pass (candidates per step) chosen by
+// timing on the first batch of each (dtype, padded row length).
+struct BatchTuner {
+  bool enabled = true;
+  std::map<int, int> cb;  // key(dtype, DP) -> candidates per step
+  static int key(int dt, int DP) { return dt * 4096 + DP; }
+};
 hipError_t launch_batched(kmpar_dtype dt, const kmpar_instance* ih, const kmpar_instance* idev,
                           int count, int rounds, uint64_t seed, void* ws, const kmpar_trace* tr,
-                          hipStream_t s);
+                          BatchTuner* tuner, hipStream_t s);
 
 }  // namespace kmpar

@@ -66,6 +66,7 @@ _lib.lloyd_step.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, 
 _lib.kmpar_workspace_size_batched.argtypes = [_vp, _vp, _i32, ctypes.c_int, ctypes.POINTER(_sz)]
 _lib.kmpar_init_batched.argtypes = [_vp, _vp, _vp, _i32, ctypes.c_int, _u64, _vp, _sz, _vp, _vp]
 _lib.kmpar_set_option.argtypes = [_vp, ctypes.c_int, _i64]
+_lib.kmpar_batch_tiles.argtypes = [_vp, _vp, _vp, _vp, _i32, ctypes.POINTER(_i32)]
 _lib.kmpar_profile_enable.argtypes = [_vp, ctypes.c_int]
 _lib.kmpar_profile_read.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i64),
                                     ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]
@@ -75,8 +76,9 @@ EXPORTED = ["kmpar_create", "kmpar_destroy", "kmpar_strerror", "kmpar_last_error
             "kmpar_sizeof_stats", "kmpar_max_candidates", "kmpar_workspace_size", "kmpar_init",
             "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_profile_enable",
             "kmpar_profile_read", "kmpar_workspace_size_batched", "kmpar_init_batched",
-            "kmpar_set_option"]
+            "kmpar_set_option", "kmpar_batch_tiles"]
 OPT_RECLUSTER_PATH = 0
+OPT_BATCH_AUTOTUNE = 1
 
 # kmpar_instance (include/kmpar.h), 64 bytes.
 INSTANCE_DTYPE = np.dtype([("X", "<u8"), ("row_scale", "<u8"), ("centers", "<u8"), ("stats", "<u8"),
@@ -174,6 +176,18 @@ class Context:
 
     def set_option(self, opt: int, value: int):
         self._check(_lib.kmpar_set_option(self._h, opt, int(value)), "kmpar_set_option")
+
+    def batch_tiles(self) -> list:
+        """[(dtype code, padded row length, candidates per step)] the batched
+        tuner has chosen so far."""
+        cnt = _i32(0)
+        self._check(_lib.kmpar_batch_tiles(self._h, None, None, None, 0, ctypes.byref(cnt)),
+                    "kmpar_batch_tiles")
+        n = cnt.value
+        a, b, c = (np.zeros(max(n, 1), np.int32) for _ in range(3))
+        self._check(_lib.kmpar_batch_tiles(self._h, a.ctypes.data, b.ctypes.data, c.ctypes.data, n,
+                                           ctypes.byref(cnt)), "kmpar_batch_tiles")
+        return [(int(a[i]), int(b[i]), int(c[i])) for i in range(n)]
 
     def profile(self, on: bool = True):
         self._check(_lib.kmpar_profile_enable(self._h, 1 if on else 0), "kmpar_profile_enable")

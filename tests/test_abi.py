@@ -153,6 +153,17 @@ def test_set_option_validation(K):
     assert K._lib.kmpar_set_option(ctx._h, K.OPT_RECLUSTER_PATH, 4) == K.E_INVAL
     assert K._lib.kmpar_set_option(ctx._h, K.OPT_RECLUSTER_PATH, -1) == K.E_INVAL
     assert K._lib.kmpar_set_option(ctx._h, 7, 0) == K.E_INVAL
+    for v in (0, 1):
+        assert K._lib.kmpar_set_option(ctx._h, K.OPT_BATCH_AUTOTUNE, v) == 0
+    assert K._lib.kmpar_set_option(ctx._h, K.OPT_BATCH_AUTOTUNE, 2) == K.E_INVAL
+
+
+def test_batch_tiles_empty_before_any_batch(K):
+    ctx = K.Context(None)
+    assert ctx.batch_tiles() == []
+    cnt = ctypes.c_int32(0)
+    assert K._lib.kmpar_batch_tiles(ctx._h, None, None, None, -1, ctypes.byref(cnt)) == K.E_INVAL
+    assert K._lib.kmpar_batch_tiles(ctx._h, None, None, None, 4, ctypes.byref(cnt)) == K.E_INVAL
 
 
 def test_init_rejects_candidate_capacity_overflow(K):

@@ -108,3 +108,38 @@ def test_batched_refined_equals_plain(ctx, dtype):
     # and the refined run replays against the oracle like the plain one
     X64 = [decoded_fp64(X, dtype) if dtype == "bf16" else X.astype(np.float64) for X in Xs]
     _replay_all(X64[:3], b[0][:3], b[1][:3], b[2][:3], ks[:3], ells[:3], 4, 13)
+
+
+def test_batched_autotune_keeps_results():
+    # The tuner times every candidates-per-step variant of each group's fold
+    # on round 1 (re-applying a fold changes nothing): a tuned context, a
+    # context that has tuned already and an untuned one give the same batch.
+    from paper_1203_6402_amd import kmpar
+    ns, ds, ks = synth.batch_instances(24, seed=9, n_lo=500, n_hi=12000, dims=(32, 60, 128, 160))
+    Xs = synth.batch_gauss_mixture(ns, ds, ks, seed=9)
+    devs = [_dev(X) for X in Xs]
+    ells = 2.0 * ks
+    fixed = kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
+    fixed.set_option(kmpar.OPT_BATCH_AUTOTUNE, 0)
+    tuned = kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
+    a = fixed.init_batched(devs, ks, ells, 4, seed=21, trace=True)
+    b = tuned.init_batched(devs, ks, ells, 4, seed=21, trace=True)   # tunes on round 1
+    c = tuned.init_batched(devs, ks, ells, 4, seed=21, trace=True)   # uses the tuned shapes
+    torch.cuda.synchronize()
+    _same_batches(a, b)
+    _same_batches(a, c)
+    assert fixed.batch_tiles() == []
+    tiles = tuned.batch_tiles()
+    dps = sorted({kmpar_dp(int(d)) for d in ds})
+    assert sorted(t[1] for t in tiles) == dps
+    for dt, dp, cb in tiles:
+        assert cb in ((1, 2, 4) if dp <= 128 else (4, 8))
+
+
+def kmpar_dp(d):
+    # padded row length of the candidate rows (multiples of 4 / 16 / 32)
+    if d <= 64:
+        return (d + 3) // 4 * 4
+    if d <= 128:
+        return (d + 15) // 16 * 16
+    return (d + 31) // 32 * 32
