@@ -150,7 +150,8 @@ def batched_bench(kmpar, synth, torch, seed, count, steps=2):
     """Many independent instances in one kmpar_init_batched call: n_i
     log-uniform in [2,000, 200,000], d_i uniform in {32, 64, 128},
     k_i = ceil(sqrt(n_i)/2), GaussMixture data (R = 10), ell = 2k_i, r = 5;
-    FP32 and BF16 storage."""
+    FP32 and BF16 storage.  Timed with the tile shapes the tuner picks (its
+    tuning call is the untimed first one) and with the fixed defaults."""
     import numpy as np
     ns, ds, ks = synth.batch_instances(count, seed=seed)
     ells = 2.0 * ks
@@ -159,27 +160,33 @@ def batched_bench(kmpar, synth, torch, seed, count, steps=2):
     out = {"workload": f"{count} independent GaussMixture instances (synthetic)",
            "instances": count, "sum_n": int(ns.sum()), "mean_d": float(ds.mean()),
            "k_range": [int(ks.min()), int(ks.max())], "rounds": 5}
-    ctx = kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
+    tuned = kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
+    fixed = kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
+    fixed.set_option(kmpar.OPT_BATCH_AUTOTUNE, 0)
     for name, conv in (("fp32", None), ("bf16", torch.bfloat16)):
         Xv = Xs if conv is None else [X.to(conv) for X in Xs]
-        _, sts, _ = ctx.init_batched(Xv, ks, ells, 5, seed=seed)
-        bad = sum(1 for s_ in sts if s_["status"] != 0)
-        evals = float(sum(int(n) * s_["n_candidates"] for n, s_ in zip(ns, sts)))
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            ctx.init_batched(Xv, ks, ells, 5, seed=seed, check=False)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        out[f"{name}_ms"] = ms
-        out[f"{name}_evals_per_s"] = evals / (ms / 1e3)
-        out[f"{name}_instances_not_ok"] = bad
-        log(f"batched {name}: {ms:.1f} ms per batch, {evals / (ms / 1e3):.3e} evals/s, "
-            f"{bad} instances with a non-OK status")
+        for label, ctx in (("", tuned), ("_fixed", fixed)):
+            _, sts, _ = ctx.init_batched(Xv, ks, ells, 5, seed=seed)
+            bad = sum(1 for s_ in sts if s_["status"] != 0)
+            evals = float(sum(int(n) * s_["n_candidates"] for n, s_ in zip(ns, sts)))
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                ctx.init_batched(Xv, ks, ells, 5, seed=seed, check=False)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            out[f"{name}{label}_ms"] = ms
+            out[f"{name}{label}_evals_per_s"] = evals / (ms / 1e3)
+            out[f"{name}{label}_instances_not_ok"] = bad
+            log(f"batched {name}{label}: {ms:.1f} ms per batch, {evals / (ms / 1e3):.3e} evals/s, "
+                f"{bad} instances with a non-OK status")
         if conv is not None:
             del Xv
+    out["tuned_tiles"] = [{"dtype": dt, "padded_d": dp, "candidates_per_step": cb}
+                          for dt, dp, cb in tuned.batch_tiles()]
+    log(f"batched tiles: {out['tuned_tiles']}")
     del Xs
     torch.cuda.empty_cache()
     return out
