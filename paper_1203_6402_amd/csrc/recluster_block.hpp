@@ -21,6 +21,29 @@ namespace kmpar {
 // unpruned update would.
 // Candidate rows are read from the dim-major copy CallT[e * ldT + j], so the
 // lanes of a wave, which take consecutive candidates, read consecutive words.
+
+// FP32 direct form sum_e (c_e - p_e)^2, e ascending, of dim-major column j
+// against the row p: sixteen loads are issued before their sixteen fmas, so
+// a thread waits for memory once per sixteen elements, not once per element.
+__device__ __forceinline__ float col_dist(const float* __restrict__ CallT, int ldT, int j,
+                                          const float* p, int d) {
+  float acc = 0.0f;
+  for (int e0 = 0; e0 < d; e0 += 16) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      v[u] = e0 + u < d ? CallT[(int64_t)(e0 + u) * ldT + j] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (e0 + u < d) {
+        const float t = v[u] - p[e0 + u];
+        acc = fmaf(t, t, acc);
+      }
+    }
+  }
+  return acc;
+}
+
 template <int BS>
 __device__ void recluster_block(const float* __restrict__ CallT, int ldT, int d,
                                 const int* __restrict__ w, int m, int k, uint64_t seed,
@@ -108,22 +131,12 @@ __device__ void recluster_block(const float* __restrict__ CallT, int ldT, int d,
     }
     __syncthreads();
     for (int q = tid; q < s; q += BS) {
-      const int pq = pk[q];
-      float acc = 0.0f;
-      for (int e = 0; e < d; ++e) {
-        const float t = CallT[(int64_t)e * ldT + pq] - cp[e];
-        acc = fmaf(t, t, acc);
-      }
-      pd[q] = acc;
+      pd[q] = col_dist(CallT, ldT, pk[q], cp, d);
     }
     __syncthreads();
     for (int j = tid; j < m; j += BS) {
       if (s > 0 && pd[near[j]] > 4.0f * E[j] * (1.0f + eps)) continue;
-      float acc = 0.0f;
-      for (int e = 0; e < d; ++e) {
-        const float t = CallT[(int64_t)e * ldT + j] - cp[e];
-        acc = fmaf(t, t, acc);
-      }
+      const float acc = col_dist(CallT, ldT, j, cp, d);
       if (s == 0 || acc < E[j]) {
         E[j] = acc;
         near[j] = s;
