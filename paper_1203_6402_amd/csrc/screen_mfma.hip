@@ -860,9 +860,15 @@ hipError_t launch_first_pass(kmpar_dtype dt, int split, int KS, bool prep, const
   return hipErrorInvalidValue;
 }
 
+// Whether the screen takes its A operands straight from X (no prepared copy):
+// BF16 rows (either split: both parts of the K axis are the row itself) or
+// FP8 codes read eight at a time when d % 8 == 0, so eight K indices never
+// straddle two parts.  FP32 rows use the prepared split terms: building them
+// in the screen from 4-byte gathers costs each wave more at its start than
+// the prepared copy saves.
 bool screen_a_direct(kmpar_dtype dt, int split, int d) {
   if (dt == KMPAR_FP8_E4M3) return split == 1 && d % 8 == 0;  // codes converted in registers
-  return dt == KMPAR_BF16 && split == 1 && d % 8 == 0;
+  return dt == KMPAR_BF16 && d % 8 == 0;
 }
 
 size_t screen_a_bytes(int n, int KS) {
