@@ -86,6 +86,38 @@ def precision_compare(kmpar, synth, torch, seed, steps=2):
     return out
 
 
+def c0_lloyd(kmpar, synth, torch, seed, iters=20, reps=5):
+    """C0: GaussMixture k* = 50 centers ~ N(0, 10 I) in d = 15, n = 10,000,
+    k = 50, ell = 2k, r = 5, then 20 Lloyd iterations; per mode, the time of
+    one init and of one Lloyd iteration (HIP events, averaged)."""
+    n, d, k = 10_000, 15, 50
+    X = torch.from_numpy(synth.gauss_mixture(n, d, k, 10.0, seed=seed)).to("cuda:0")
+    out = {"workload": "GaussMixture (synthetic), n = 10,000, d = 15, k = 50, ell = 2k, r = 5, "
+                       f"{iters} Lloyd iterations", "iterations": iters}
+    for name, mode in (("refined", kmpar.MODE_REFINED), ("plain", kmpar.MODE_PLAIN_FP32)):
+        ctx = kmpar.Context(0, mode)
+        r = ctx.init(X, k=k, ell=2.0 * k, rounds=5, seed=seed)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.init(X, k=k, ell=2.0 * k, rounds=5, seed=seed, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{name}_init_ms"] = e0.elapsed_time(e1) / reps
+        C = r.centers.clone()
+        e0.record()
+        for _ in range(iters):
+            _, phi = ctx.lloyd_step(X, C)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{name}_lloyd_ms_per_iter"] = e0.elapsed_time(e1) / iters
+        out[f"{name}_final_phi"] = float(phi.item())
+        log(f"C0 {name}: init {out[f'{name}_init_ms']:.3f} ms, Lloyd "
+            f"{out[f'{name}_lloyd_ms_per_iter']:.3f} ms/iter, phi {out[f'{name}_final_phi']:.6g}")
+    return out
+
+
 def c3_compare(kmpar, synth, torch, seed, steps=2, with_plain=True):
     """FP8 precision workload: n = 50M, d = 256, e4m3 codes with per-row
     scales max|x|/448 from a 2,000-component Gaussian mixture (centers
@@ -353,6 +385,8 @@ def main():
     log(f"dominant {dom}: avg {dur_per_launch*1e6:.1f} us, {achieved:.2f} TFLOP/s algorithmic "
         f"({100*achieved/peak:.1f}% of {peak})")
 
+    c0 = c0_lloyd(kmpar, synth, torch, args.seed)
+
     precision = None
     if not args.no_precision:
         precision = precision_compare(kmpar, synth, torch, args.seed)
@@ -381,7 +415,7 @@ def main():
                       "rescanned_points": rp.stats["n_rescanned"],
                       "graph_replay_ms_per_step": graph_ms,
                       "parallelism": "single GPU"},
-           "roofline": roofline, "cpu_baseline": cpu, "precision": precision,
+           "roofline": roofline, "cpu_baseline": cpu, "c0_lloyd": c0, "precision": precision,
            "fp8": c3, "batched": batched}
     print(json.dumps(out), flush=True)
 
