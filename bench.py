@@ -274,6 +274,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of the input the oracle baseline runs on (0: all of them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lloyd", action="store_true",
+                    help="skip the Lloyd legs (C1 full size and C0)")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the BF16-refined vs FP32-plain comparison on the precision workload")
     ap.add_argument("--c3", action="store_true",
@@ -385,7 +387,24 @@ def main():
     log(f"dominant {dom}: avg {dur_per_launch*1e6:.1f} us, {achieved:.2f} TFLOP/s algorithmic "
         f"({100*achieved/peak:.1f}% of {peak})")
 
-    c0 = c0_lloyd(kmpar, synth, torch, args.seed)
+    # Row a9 at full size: Lloyd iterations on this input from the centers found above.
+    c1_lloyd = c0 = None
+    if not args.no_lloyd:
+        C = r.centers.clone()
+        phi0 = float(ctx.cost(Xd, C).item())
+        ctx.lloyd_step(Xd, C)
+        torch.cuda.synchronize()
+        l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        l0.record()
+        for _ in range(5):
+            _, phi = ctx.lloyd_step(Xd, C)
+        l1.record()
+        torch.cuda.synchronize()
+        c1_lloyd = {"ms_per_iter": l0.elapsed_time(l1) / 5, "iterations": 6,
+                    "phi_after": float(phi.item()), "phi_init": phi0}
+        log(f"C1 Lloyd: {c1_lloyd['ms_per_iter']:.3f} ms/iter, phi {phi0:.6g} -> "
+            f"{c1_lloyd['phi_after']:.6g}")
+        c0 = c0_lloyd(kmpar, synth, torch, args.seed)
 
     precision = None
     if not args.no_precision:
@@ -415,7 +434,7 @@ def main():
                       "rescanned_points": rp.stats["n_rescanned"],
                       "graph_replay_ms_per_step": graph_ms,
                       "parallelism": "single GPU"},
-           "roofline": roofline, "cpu_baseline": cpu, "c0_lloyd": c0, "precision": precision,
+           "roofline": roofline, "cpu_baseline": cpu, "c1_lloyd": c1_lloyd, "c0_lloyd": c0, "precision": precision,
            "fp8": c3, "batched": batched}
     print(json.dumps(out), flush=True)
 

@@ -678,8 +678,12 @@ hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, cons
 //  1. per-block cluster counts   bcnt[c * nbs + b]
 //  2. exclusive scan of the flattened table -> each (cluster, block) slot
 //  3. stable scatter of point indices into cluster-sorted order
-//  4. cluster chunks of kSegChunk sorted points, summed in FP64 in order
+//  4. cluster chunks of kSegChunk sorted points, each split into fixed
+//     consecutive slices summed in FP64 in point order, the slices then
+//     added in slice order
 //  5. per cluster: sum of its chunk sums in order, divided by the count.
+// Every sum runs in an order fixed by (n, d, k, assignment) alone, so the
+// update is reproducible run to run.
 __global__ __launch_bounds__(256) void k_sort_count(const int* A, int n, int k, int* bcnt,
                                                     int nbs) {
   extern __shared__ int h[];
@@ -730,33 +734,40 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// One wave per block scatters its chunk in point order; equal keys inside a
-// 64-point tile are ranked by lane, and the per-cluster cursor advances once
-// per key group.
-__global__ __launch_bounds__(64) void k_sort_scatter(const int* A, int n, int k, const int* bbase,
-                                                     int nbs, int* sorted) {
+__device__ __forceinline__ uint64_t lanemask_gt() {
+  const int lane = threadIdx.x % kWave;
+  return lane == kWave - 1 ? 0ull : (~0ull << (lane + 1));
+}
+
+// One wave per block scatters its chunk in point order, a 64-point tile at a
+// time. The lanes holding the same key are found with one ballot per key bit
+// (nbits = bits of k - 1); a lane's slot is its key's cursor plus the number
+// of lower lanes with that key, and the highest such lane advances the cursor
+// by the group's size once every lane has read it.
+__global__ __launch_bounds__(64) void k_sort_scatter(const int* A, int n, int k, int nbits,
+                                                     const int* bbase, int nbs, int* sorted) {
   extern __shared__ int cur[];
   for (int c = threadIdx.x; c < k; c += 64) cur[c] = bbase[(int64_t)c * nbs + blockIdx.x];
   __syncthreads();
-  const int lane = threadIdx.x;
   const int base = blockIdx.x * kSortChunk;
-  for (int tile = 0; tile < kSortChunk; tile += 64) {
-    const int i = base + tile + lane;
+  for (int tile = 0; tile < kSortChunk && base + tile < n; tile += 64) {
+    const int i = base + tile + threadIdx.x;
     const int key0 = (i < n) ? A[i] : -1;
     const bool valid = key0 >= 0 && key0 < k;
-    const int key = valid ? key0 : -1;
-    uint64_t pending = __ballot(valid);
-    while (pending) {
-      const int leader = __ffsll((unsigned long long)pending) - 1;
-      const int lkey = __shfl(key, leader, kWave);
-      const uint64_t grp = __ballot(valid && key == lkey);
-      const int pos0 = cur[lkey];
-      if (valid && key == lkey) sorted[pos0 + __popcll(grp & lanemask_lt())] = i;
-      __syncthreads();
-      if (lane == leader) cur[lkey] = pos0 + __popcll(grp);
-      __syncthreads();
-      pending &= ~grp;
+    const int key = valid ? key0 : 0;
+    uint64_t grp = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (key >> b) & 1;
+      const uint64_t on = __ballot(valid && bit);
+      grp &= bit ? on : ~on;
     }
+    const int pos0 = valid ? cur[key] : 0;
+    __syncthreads();
+    if (valid) {
+      sorted[pos0 + __popcll(grp & lanemask_lt())] = i;
+      if ((grp & lanemask_gt()) == 0) cur[key] = pos0 + __popcll(grp);
+    }
+    __syncthreads();
   }
 }
 
@@ -788,10 +799,22 @@ __global__ __launch_bounds__(1024) void k_chunk_list(const int* bbase, int nbs, 
   }
 }
 
+// Lanes per slice row: the power of two covering d, at most 64.
+__host__ __device__ __forceinline__ int seg_width(int d) {
+  int w = 1;
+  while (w < d && w < 64) w <<= 1;
+  return w;
+}
+
+// Block q sums chunk q of its cluster: 256 threads form 256 / DW slices of DW
+// lanes (lane = element), slice s owns the s-th of that many consecutive
+// pieces of the chunk and adds its rows in point order, eight rows' loads
+// issued ahead of their adds; the slices' sums are then added in slice order.
 template <typename T>
-__global__ __launch_bounds__(64) void k_seg_sum(const T* X, const float* row_scale, int d,
-                                                const int* sorted, const int* coff,
-                                                const int* cstart, int k, double* part) {
+__global__ __launch_bounds__(256) void k_seg_sum(const T* X, const float* row_scale, int d,
+                                                 const int* sorted, const int* coff,
+                                                 const int* cstart, int k, double* part) {
+  __shared__ double red[256];
   const int q = blockIdx.x;
   if (q >= cstart[k]) return;
   int lo = 0, hi = k;  // largest c with cstart[c] <= q
@@ -802,13 +825,39 @@ __global__ __launch_bounds__(64) void k_seg_sum(const T* X, const float* row_sca
   const int c = lo;
   const int p0 = coff[c] + (q - cstart[c]) * kSegChunk;
   const int p1 = min(coff[c + 1], p0 + kSegChunk);
-  for (int e = threadIdx.x; e < d; e += 64) {
+  const int DW = seg_width(d), NS = 256 / DW;
+  const int t = threadIdx.x, sl = t / DW, el = t % DW;
+  const int len = p1 - p0, per = (len + NS - 1) / NS;
+  const int a = p0 + min(len, sl * per), b = p0 + min(len, (sl + 1) * per);
+  for (int e0 = 0; e0 < d; e0 += DW) {
+    const int e = e0 + el;
     double acc = 0.0;
-    for (int p = p0; p < p1; ++p) {
-      const int i = sorted[p];
-      acc += (double)Elem<T>::get(X, (int64_t)i * d + e, row_scale_of<T>(row_scale, i));
+    if (e < d) {
+      int p = a;
+      for (; p + 8 <= b; p += 8) {
+        int idx[8];
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) idx[u] = sorted[p + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          v[u] = Elem<T>::get(X, (int64_t)idx[u] * d + e, row_scale_of<T>(row_scale, idx[u]));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (double)v[u];
+      }
+      for (; p < b; ++p) {
+        const int i = sorted[p];
+        acc += (double)Elem<T>::get(X, (int64_t)i * d + e, row_scale_of<T>(row_scale, i));
+      }
     }
-    part[(int64_t)q * d + e] = acc;
+    red[t] = acc;
+    __syncthreads();
+    if (t < DW && e0 + t < d) {
+      double sum = 0.0;
+      for (int j = 0; j < NS; ++j) sum += red[j * DW + t];
+      part[(int64_t)q * d + e0 + t] = sum;
+    }
+    __syncthreads();
   }
 }
 
@@ -834,20 +883,22 @@ hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_s
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, w.bcnt, L, w.scan_tmp);
   hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, w.scan_tmp, ntiles, (int*)nullptr);
   hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(256), 0, s, w.bcnt, L, w.scan_tmp);
-  hipLaunchKernelGGL(k_sort_scatter, dim3(nbs), dim3(64), lds, s, A, n, k, w.bcnt, nbs, w.sorted);
+  const int nbits = k > 1 ? 32 - __builtin_clz((unsigned)(k - 1)) : 0;
+  hipLaunchKernelGGL(k_sort_scatter, dim3(nbs), dim3(64), lds, s, A, n, k, nbits, w.bcnt, nbs,
+                     w.sorted);
   hipLaunchKernelGGL(k_chunk_list, dim3(1), dim3(1024), 0, s, w.bcnt, nbs, k, n, w.coff, w.cstart);
   const int max_chunks = (n + kSegChunk - 1) / kSegChunk + k;
   switch (dt) {
     case KMPAR_F32:
-      hipLaunchKernelGGL(k_seg_sum<float>, dim3(max_chunks), dim3(64), 0, s, (const float*)X,
+      hipLaunchKernelGGL(k_seg_sum<float>, dim3(max_chunks), dim3(256), 0, s, (const float*)X,
                          row_scale, d, w.sorted, w.coff, w.cstart, k, w.part);
       break;
     case KMPAR_BF16:
-      hipLaunchKernelGGL(k_seg_sum<bf16_t>, dim3(max_chunks), dim3(64), 0, s, (const bf16_t*)X,
+      hipLaunchKernelGGL(k_seg_sum<bf16_t>, dim3(max_chunks), dim3(256), 0, s, (const bf16_t*)X,
                          row_scale, d, w.sorted, w.coff, w.cstart, k, w.part);
       break;
     case KMPAR_FP8_E4M3:
-      hipLaunchKernelGGL(k_seg_sum<fp8_t>, dim3(max_chunks), dim3(64), 0, s, (const fp8_t*)X,
+      hipLaunchKernelGGL(k_seg_sum<fp8_t>, dim3(max_chunks), dim3(256), 0, s, (const fp8_t*)X,
                          row_scale, d, w.sorted, w.coff, w.cstart, k, w.part);
       break;
   }
