@@ -658,13 +658,14 @@ static int assign_pass(kmpar_ctx* ctx, kmpar_dtype dtype, const AssignLayout& L,
   const int d = fa.d, DP = padded_dim(d);
   if (ctx->mode == KMPAR_MODE_REFINED && screen_supported(dtype, false, d) && m >= kScreenMinM) {
     const int split = screen_split(dtype, false);
-    KMPAR_HIP(launch_rownorm(dtype, fa.X, fa.row_scale, fa.n, d, L.norms, s));
     KMPAR_HIP(launch_fill_i32(L.list_len, 0, 1, s));
     const void* Apre = nullptr;
-    if (!screen_a_direct(dtype, split, d)) {
+    if (!screen_a_direct(dtype, split, d)) {  // one read of X: norms and A operands
       KMPAR_HIP(launch_prep_a(dtype, split, screen_ksteps(split, d), fa.X, fa.row_scale, fa.n, d,
-                              L.Apre, s));
+                              L.norms, L.Apre, s));
       Apre = L.Apre;
+    } else {
+      KMPAR_HIP(launch_rownorm(dtype, fa.X, fa.row_scale, fa.n, d, L.norms, s));
     }
     KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (m + 15) / 16, L.norms, Apre, L.B, L.ncg,
                            nullptr, L.scg, L.list, L.list_len, nullptr, s));

@@ -866,9 +866,19 @@ __global__ __launch_bounds__(64) void k_centroid(const double* part, const int* 
   const int c = blockIdx.x;
   const int cnt = coff[c + 1] - coff[c];
   if (cnt == 0) return;  // an empty cluster keeps its center
+  const int q0 = cstart[c], q1 = cstart[c + 1];
   for (int e = threadIdx.x; e < d; e += 64) {
+    // chunk sums added in chunk order; eight loads issued ahead of their adds
     double s = 0.0;
-    for (int q = cstart[c]; q < cstart[c + 1]; ++q) s += part[(int64_t)q * d + e];
+    int q = q0;
+    for (; q + 8 <= q1; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * d + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; q < q1; ++q) s += part[(int64_t)q * d + e];
     C[(int64_t)c * d + e] = (float)(s / (double)cnt);
   }
 }

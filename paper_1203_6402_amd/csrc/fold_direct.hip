@@ -232,39 +232,6 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
   }
 }
 
-// ||x||^2 in FP32, coordinates in order (same arithmetic as the fold's norm).
-template <typename T>
-__global__ __launch_bounds__(256) void k_rownorm(const T* X, const float* row_scale, int n, int d,
-                                                 float* norms) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const float sc = row_scale_of<T>(row_scale, i);
-  float nx = 0.0f;
-  for (int j = 0; j < d; ++j) {
-    const float v = Elem<T>::get(X, (int64_t)i * d + j, sc);
-    nx = fmaf(v, v, nx);
-  }
-  norms[i] = nx;
-}
-
-hipError_t launch_rownorm(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
-                          float* norms, hipStream_t s) {
-  const dim3 grid((n + 255) / 256), block(256);
-  switch (dt) {
-    case KMPAR_F32:
-      hipLaunchKernelGGL(k_rownorm<float>, grid, block, 0, s, (const float*)X, row_scale, n, d, norms);
-      break;
-    case KMPAR_BF16:
-      hipLaunchKernelGGL(k_rownorm<bf16_t>, grid, block, 0, s, (const bf16_t*)X, row_scale, n, d,
-                         norms);
-      break;
-    case KMPAR_FP8_E4M3:
-      hipLaunchKernelGGL(k_rownorm<fp8_t>, grid, block, 0, s, (const fp8_t*)X, row_scale, n, d, norms);
-      break;
-  }
-  return hipGetLastError();
-}
-
 template <typename T>
 static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
   const int work = a.list ? a.list_cap : a.n;

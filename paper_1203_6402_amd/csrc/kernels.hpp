@@ -124,8 +124,9 @@ hipError_t launch_prep_b(kmpar_dtype dt, int split, int KS, const float* C, int 
 hipError_t launch_screen(kmpar_dtype dt, int split, int KS, const ScreenArgs& a, hipStream_t s);
 bool screen_a_direct(kmpar_dtype dt, int split, int d);
 size_t screen_a_bytes(int n, int KS);
+// The screen's A operands and, when norms != nullptr, ||x||^2, from one read of X.
 hipError_t launch_prep_a(kmpar_dtype dt, int split, int KS, const void* X, const float* rsc, int n,
-                         int d, void* Apre, hipStream_t s);
+                         int d, float* norms, void* Apre, hipStream_t s);
 hipError_t launch_list_reset(int* list_len, kmpar_stats* st, hipStream_t s);
 // The first pass against candidate rs[0] (D2, A, optional norms), fused with
 // the A operands of the screen when prep.
@@ -133,6 +134,7 @@ hipError_t launch_first_pass(kmpar_dtype dt, int split, int KS, bool prep, const
                              const float* rsc, int n, int d, int DP, const float* C,
                              const int* rs, float* D2, int* A, float* norms, void* Apre,
                              hipStream_t s);
+// ||x||^2 in FP32, coordinates in ascending order (the first pass's arithmetic).
 hipError_t launch_rownorm(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
                           float* norms, hipStream_t s);
 

@@ -163,71 +163,21 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
   }
 }
 
-// --------------------------------------------------------------- A operands
-// The point side of the screen, built once per call: for every tile of 16
-// points and k-step s, 64 lanes x 8 bf16 in the lane order of the MFMA A
-// operand (lane l: point l%16, k = s*32 + (l/16)*8 + e).  Rows are staged
-// through LDS as FP32 with coalesced loads.  Tiles past n are zero.
-template <int SPLIT, int KS, typename T>
-__global__ __launch_bounds__(256) void k_prep_a(const T* X, const float* row_scale, int n, int d,
-                                                u16x8* Apre) {
-  extern __shared__ float xs[];  // [64][XS], XS = d + 1 when d is a multiple of 32
-  const int pad = d % 32 == 0 ? 1 : 0, XS = d + pad;
-  const int p0 = blockIdx.x * 64;
-  const int np = max(0, min(64, n - p0));
-  for (int idx = threadIdx.x; idx < np * d; idx += 256)
-    xs[idx + (idx / d) * pad] =
-        Elem<T>::get(X, (int64_t)p0 * d + idx, row_scale_of<T>(row_scale, p0 + idx / d));
-  __syncthreads();
-  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  const int row = w * 16 + (lane % 16);
-  const bool valid = row < np;
-#pragma unroll
-  for (int s = 0; s < KS; ++s) {
-    u16x8 v;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = s * 32 + (lane / 16) * 8 + e;
-      const int part = k / d, coord = k - part * d;
-      v[e] = (valid && part < SPLIT)
-                 ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * XS + coord]), part)
-                 : (uint16_t)0;
-    }
-    Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
-  }
-}
-
-// ------------------------------------------------------------ first pass
-// Algorithm 2 step 2 (the first pass, m = 1) fused with the preparation of
-// the A operands: one coalesced read of each block of 64 rows of X gives
-// D^2 to the first center (FP32 direct form, coordinates ascending, as the
-// fold computes it), A = its id, ||x||^2 (when norms != nullptr) and, when
-// PREP, the A operands exactly as k_prep_a writes them.
-template <int SPLIT, int KS, typename T, bool PREP>
-__global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row_scale, int n,
-                                                    int d, int DP, const float* C, const int* rs,
-                                                    float* D2, int* A, float* norms,
-                                                    u16x8* Apre) {
-  // [64][XS] rows, then the first center [DP]; XS = d + 1 when d is a
-  // multiple of 32, so the 64 threads that walk one row each do not all read
-  // the same bank
-  extern __shared__ float xs[];
-  __shared__ float ss[64];       // FP8 row scales
-  const int pad = d % 32 == 0 ? 1 : 0, XS = d + pad;
-  float* c0 = xs + 64 * XS;
-  const int p0 = blockIdx.x * 64;
-  const int np = max(0, min(64, n - p0));
-  const int id0 = rs[0];
-  for (int e = threadIdx.x; e < DP; e += 256) c0[e] = C[(int64_t)id0 * DP + e];
+// ------------------------------------------------------------ row staging
+// Rows p0 .. p0+np-1 of X decoded to FP32 into xs[row * XS + col], XS = d + pad.
+// The block's rows are one contiguous span starting 16-byte aligned (64 d
+// sizeof(T) bytes per block): coalesced 16-byte loads, four in flight per
+// thread, each decoded into 16 / sizeof(T) elements; a tail shorter than 16
+// bytes is read element by element. FP8 rows' scales go to ss first. Every
+// thread of the block calls it; the caller synchronises before reading xs.
+template <typename T>
+__device__ __forceinline__ void stage_rows(const T* X, const float* row_scale, int p0, int np, int d,
+                                           int pad, float* ss, float* xs) {
   constexpr bool SC = ScaledRows<T>::value;
   if constexpr (SC) {
     if (threadIdx.x < np) ss[threadIdx.x] = row_scale[p0 + threadIdx.x];
     __syncthreads();
   }
-  // The block's rows are one contiguous span starting 16-byte aligned
-  // (64 d sizeof(T) bytes per block): coalesced 16-byte loads, four in
-  // flight per thread, each decoded into EPV elements; a tail shorter than
-  // 16 bytes is read element by element.
   constexpr int S = (int)sizeof(T), EPV = 16 / S;
   const int cnt = np * d;
   const int nvec = cnt * S / 16;
@@ -262,6 +212,76 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
   }
   for (int e = nvec * EPV + threadIdx.x; e < cnt; e += 256)
     xs[e + (e / d) * pad] = Elem<T>::get(X, (int64_t)p0 * d + e, row_scale_of<T>(row_scale, p0 + e / d));
+}
+
+// ||x||^2 of a staged row: FP32 fmas over the coordinates in ascending order.
+__device__ __forceinline__ float staged_norm(const float* xr, int d) {
+  float nx = 0.0f;
+#pragma unroll 8
+  for (int e = 0; e < d; ++e) nx = fmaf(xr[e], xr[e], nx);
+  return nx;
+}
+
+// --------------------------------------------------------------- A operands
+// The point side of the screen, built once per call: for every tile of 16
+// points and k-step s, 64 lanes x 8 bf16 in the lane order of the MFMA A
+// operand (lane l: point l%16, k = s*32 + (l/16)*8 + e), and ||x||^2 when
+// norms != nullptr.  Rows are staged through LDS as FP32 with coalesced
+// loads.  Tiles past n are zero.  Without PREP only the norms are written.
+template <int SPLIT, int KS, typename T, bool PREP>
+__global__ __launch_bounds__(256) void k_prep_a(const T* X, const float* row_scale, int n, int d,
+                                                float* norms, u16x8* Apre) {
+  extern __shared__ float xs[];  // [64][XS], XS = d + 1 when d is a multiple of 32
+  __shared__ float ss[64];       // FP8 row scales
+  const int pad = d % 32 == 0 ? 1 : 0, XS = d + pad;
+  const int p0 = blockIdx.x * 64;
+  const int np = max(0, min(64, n - p0));
+  stage_rows<T>(X, row_scale, p0, np, d, pad, ss, xs);
+  __syncthreads();
+  if (norms && threadIdx.x < np) norms[p0 + threadIdx.x] = staged_norm(xs + threadIdx.x * XS, d);
+  if constexpr (PREP) {
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    const int row = w * 16 + (lane % 16);
+    const bool valid = row < np;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      u16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = s * 32 + (lane / 16) * 8 + e;
+        const int part = k / d, coord = k - part * d;
+        v[e] = (valid && part < SPLIT)
+                   ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * XS + coord]), part)
+                   : (uint16_t)0;
+      }
+      Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------ first pass
+// Algorithm 2 step 2 (the first pass, m = 1) fused with the preparation of
+// the A operands: one coalesced read of each block of 64 rows of X gives
+// D^2 to the first center (FP32 direct form, coordinates ascending, as the
+// fold computes it), A = its id, ||x||^2 (when norms != nullptr) and, when
+// PREP, the A operands exactly as k_prep_a writes them.
+template <int SPLIT, int KS, typename T, bool PREP>
+__global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row_scale, int n,
+                                                    int d, int DP, const float* C, const int* rs,
+                                                    float* D2, int* A, float* norms,
+                                                    u16x8* Apre) {
+  // [64][XS] rows, then the first center [DP]; XS = d + 1 when d is a
+  // multiple of 32, so the 64 threads that walk one row each do not all read
+  // the same bank
+  extern __shared__ float xs[];
+  __shared__ float ss[64];       // FP8 row scales
+  const int pad = d % 32 == 0 ? 1 : 0, XS = d + pad;
+  float* c0 = xs + 64 * XS;
+  const int p0 = blockIdx.x * 64;
+  const int np = max(0, min(64, n - p0));
+  const int id0 = rs[0];
+  for (int e = threadIdx.x; e < DP; e += 256) c0[e] = C[(int64_t)id0 * DP + e];
+  stage_rows<T>(X, row_scale, p0, np, d, pad, ss, xs);
   __syncthreads();
   if (threadIdx.x < np) {
     const float* xr = xs + threadIdx.x * XS;
@@ -769,26 +789,28 @@ static hipError_t launch_split(int KS, const ScreenArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int SPLIT, int KS, typename T>
-static hipError_t launch_prep_a_one(const void* X, const float* rsc, int n, int d, void* Apre,
-                                    hipStream_t s) {
-  const int blocks = (n + kBlockPts - 1) / kBlockPts * (kBlockPts / 64);
+// PREP: A operands for every 256-point block (tiles past n zero) plus the
+// norms; otherwise the norms alone, one block per 64 rows.
+template <int SPLIT, int KS, typename T, bool PREP = true>
+static hipError_t launch_prep_a_one(const void* X, const float* rsc, int n, int d, float* norms,
+                                    void* Apre, hipStream_t s) {
+  const int blocks = PREP ? (n + kBlockPts - 1) / kBlockPts * (kBlockPts / 64) : (n + 63) / 64;
   const size_t lds = (size_t)64 * (d + (d % 32 == 0 ? 1 : 0)) * 4;
-  hipError_t e = hipFuncSetAttribute((const void*)k_prep_a<SPLIT, KS, T>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_prep_a<SPLIT, KS, T, PREP>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_prep_a<SPLIT, KS, T>), dim3(blocks), dim3(256), lds, s,
-                     static_cast<const T*>(X), rsc, n, d, static_cast<u16x8*>(Apre));
+  hipLaunchKernelGGL((k_prep_a<SPLIT, KS, T, PREP>), dim3(blocks), dim3(256), lds, s,
+                     static_cast<const T*>(X), rsc, n, d, norms, static_cast<u16x8*>(Apre));
   return hipGetLastError();
 }
 
 template <int SPLIT, typename T, int MAXKS = kScreenMaxKS>
 static hipError_t launch_prep_a_split(int KS, const void* X, const float* rsc, int n, int d,
-                                      void* Apre, hipStream_t s) {
+                                      float* norms, void* Apre, hipStream_t s) {
   if (KS < 1 || KS > MAXKS) return hipErrorInvalidValue;
   switch (KS) {
 #define KMPAR_PA(V) \
-  case V: if constexpr (V <= MAXKS) return launch_prep_a_one<SPLIT, V, T>(X, rsc, n, d, Apre, s); break;
+  case V: if constexpr (V <= MAXKS) return launch_prep_a_one<SPLIT, V, T>(X, rsc, n, d, norms, Apre, s); break;
     KMPAR_PA(1) KMPAR_PA(2) KMPAR_PA(3) KMPAR_PA(4) KMPAR_PA(5) KMPAR_PA(6) KMPAR_PA(7)
     KMPAR_PA(8) KMPAR_PA(9) KMPAR_PA(10) KMPAR_PA(11) KMPAR_PA(12) KMPAR_PA(13) KMPAR_PA(14)
     KMPAR_PA(15) KMPAR_PA(16)
@@ -877,10 +899,23 @@ size_t screen_a_bytes(int n, int KS) {
 }
 
 hipError_t launch_prep_a(kmpar_dtype dt, int split, int KS, const void* X, const float* rsc, int n,
-                         int d, void* Apre, hipStream_t s) {
-  if (dt == KMPAR_F32 && split == 3) return launch_prep_a_split<3, float>(KS, X, rsc, n, d, Apre, s);
-  if (dt == KMPAR_BF16 && split == 1) return launch_prep_a_split<1, bf16_t>(KS, X, rsc, n, d, Apre, s);
-  if (dt == KMPAR_BF16 && split == 2) return launch_prep_a_split<2, bf16_t>(KS, X, rsc, n, d, Apre, s);
+                         int d, float* norms, void* Apre, hipStream_t s) {
+  if (dt == KMPAR_F32 && split == 3)
+    return launch_prep_a_split<3, float>(KS, X, rsc, n, d, norms, Apre, s);
+  if (dt == KMPAR_BF16 && split == 1)
+    return launch_prep_a_split<1, bf16_t>(KS, X, rsc, n, d, norms, Apre, s);
+  if (dt == KMPAR_BF16 && split == 2)
+    return launch_prep_a_split<2, bf16_t>(KS, X, rsc, n, d, norms, Apre, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rownorm(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
+                          float* norms, hipStream_t s) {
+  switch (dt) {
+    case KMPAR_F32: return launch_prep_a_one<1, 1, float, false>(X, row_scale, n, d, norms, nullptr, s);
+    case KMPAR_BF16: return launch_prep_a_one<1, 1, bf16_t, false>(X, row_scale, n, d, norms, nullptr, s);
+    case KMPAR_FP8_E4M3: return launch_prep_a_one<1, 1, fp8_t, false>(X, row_scale, n, d, norms, nullptr, s);
+  }
   return hipErrorInvalidValue;
 }
 
