@@ -84,6 +84,7 @@ struct InitLayout {
   int* A;
   double* phi_part;
   int* cnt;
+  uint64_t* keep;  // per-round masks of kept points, one bit per point
   int* rs;
   int* scan_total;
   int* cand_point;
@@ -127,6 +128,7 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.A = c.take<int>(n);
   L.phi_part = c.take<double>((n + kPhiChunk - 1) / kPhiChunk);
   L.cnt = c.take<int>((n + kDrawChunk - 1) / kDrawChunk + 1);
+  L.keep = c.take<uint64_t>((n + kDrawChunk - 1) / kDrawChunk * (kDrawChunk / 64));
   L.rs = c.take<int>(rounds + 2);
   L.scan_total = c.take<int>(4);
   L.cand_point = c.take<int>(capT);
@@ -582,7 +584,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   // Steps 3-6: rounds.
   fa.first = 0;
   for (int t = 1; t <= rounds; ++t) {
-    KMPAR_HIP(launch_draw(L.D2, N, &st->phi[t - 1], ell, seed, t, inst, L.cnt, L.scan_total, L.rs,
+    KMPAR_HIP(launch_draw(L.D2, N, &st->phi[t - 1], ell, seed, t, inst, L.cnt, L.keep, L.scan_total, L.rs,
                           cap_round, L.cand_point, st, s));
     KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, t, cap_round, L.Call,
                             L.CallT, capT, s));

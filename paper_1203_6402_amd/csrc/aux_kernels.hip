@@ -124,6 +124,16 @@ hipError_t launch_phi(const float* D2, int n, double* part, double* out, hipStre
 }
 
 // ---------------------------------------------------------------------- draw
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x % kWave;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ uint64_t lanemask_gt() {
+  const int lane = threadIdx.x % kWave;
+  return lane == kWave - 1 ? 0ull : (~0ull << (lane + 1));
+}
+
 // Algorithm 2 step 4: point i is kept in round t iff u < p with
 // p = min(1, ell * D2_i / phi) and u = U(seed, ROUND, (i, t, inst)).
 __device__ __forceinline__ int keep_point(const float* D2, int i, double phi, double ell,
@@ -135,17 +145,26 @@ __device__ __forceinline__ int keep_point(const float* D2, int i, double phi, do
   return u < p ? 1 : 0;
 }
 
+// Masks of kept points per block: word j covers points base + 64 j + lane.
+constexpr int kDrawMasks = kDrawChunk / 64;
+
+// Counts the points a block keeps and records them as one ballot per wave and
+// 64 points, so the write pass needs neither D^2 nor the draws again.
 __global__ __launch_bounds__(256) void k_draw_count(const float* D2, int n, const double* phi,
                                                     double ell, uint64_t seed, int t,
-                                                    uint64_t inst, int* cnt) {
+                                                    uint64_t inst, int* cnt, uint64_t* keep) {
   __shared__ int sh[8];
   const double ph = *phi;
   const int base = blockIdx.x * kDrawChunk;
+  const int w = threadIdx.x / kWave;
   int c = 0;
 #pragma unroll
   for (int r = 0; r < kDrawChunk / 256; ++r) {
     const int i = base + r * 256 + threadIdx.x;
-    if (i < n) c += keep_point(D2, i, ph, ell, seed, t, inst);
+    const int kp = (i < n) ? keep_point(D2, i, ph, ell, seed, t, inst) : 0;
+    c += kp;
+    const uint64_t b = __ballot(kp);
+    if (threadIdx.x % kWave == 0) keep[(int64_t)blockIdx.x * kDrawMasks + r * 4 + w] = b;
   }
   const int tot = block_sum<int, 256>(c, sh);
   if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
@@ -178,35 +197,45 @@ __global__ void k_round_commit(const int* total, int* rs, int t, int cap, kmpar_
   if (tot > cap) st->status = KMPAR_E_OVERFLOW;
 }
 
-// Writes the kept point indices in increasing point order.
-__global__ __launch_bounds__(256) void k_draw_write(const float* D2, int n, const double* phi,
-                                                    double ell, uint64_t seed, int t,
-                                                    uint64_t inst, const int* off, const int* rs,
-                                                    int cap, int* cand_point) {
-  __shared__ int sh[8];
-  const double ph = *phi;
-  const int base = blockIdx.x * kDrawChunk;
-  int run = off[blockIdx.x];
-  const int start = rs[t];
-  for (int r = 0; r < kDrawChunk / 256; ++r) {
-    const int i = base + r * 256 + threadIdx.x;
-    const int keep = (i < n) ? keep_point(D2, i, ph, ell, seed, t, inst) : 0;
-    int tot;
-    const int rank = block_excl_scan<int, 256>(keep, sh, &tot);
-    if (keep && run + rank < cap) cand_point[start + run + rank] = i;
-    run += tot;
+// Writes the kept point indices in increasing point order, ranked from the
+// block's masks.
+__global__ __launch_bounds__(256) void k_draw_write(const uint64_t* keep, const int* off,
+                                                    const int* rs, int t, int cap,
+                                                    int* cand_point) {
+  __shared__ uint64_t m[kDrawMasks];
+  __shared__ int pre[kDrawMasks];
+  if (threadIdx.x < kDrawMasks) m[threadIdx.x] = keep[(int64_t)blockIdx.x * kDrawMasks + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int j = 0; j < kDrawMasks; ++j) {
+      pre[j] = run;
+      run += __popcll(m[j]);
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int run0 = off[blockIdx.x], start = rs[t];
+  for (int r = 0; r < kDrawMasks / 4; ++r) {
+    const int j = r * 4 + w;
+    const uint64_t mk = m[j];
+    if ((mk >> lane) & 1) {
+      const int pos = run0 + pre[j] + __popcll(mk & lanemask_lt());
+      if (pos < cap) cand_point[start + pos] = blockIdx.x * kDrawChunk + j * kWave + lane;
+    }
   }
 }
 
 hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, uint64_t seed, int t,
-                       uint64_t inst, int* cnt, int* scan_total, int* rs, int cap_round,
-                       int* cand_point, kmpar_stats* st, hipStream_t s) {
+                       uint64_t inst, int* cnt, uint64_t* keep, int* scan_total, int* rs,
+                       int cap_round, int* cand_point, kmpar_stats* st, hipStream_t s) {
   const int nb = (n + kDrawChunk - 1) / kDrawChunk;
-  hipLaunchKernelGGL(k_draw_count, dim3(nb), dim3(256), 0, s, D2, n, phi, ell, seed, t, inst, cnt);
+  hipLaunchKernelGGL(k_draw_count, dim3(nb), dim3(256), 0, s, D2, n, phi, ell, seed, t, inst, cnt,
+                     keep);
   hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, cnt, nb, scan_total);
   hipLaunchKernelGGL(k_round_commit, dim3(1), dim3(64), 0, s, scan_total, rs, t, cap_round, st);
-  hipLaunchKernelGGL(k_draw_write, dim3(nb), dim3(256), 0, s, D2, n, phi, ell, seed, t, inst, cnt,
-                     rs, cap_round, cand_point);
+  hipLaunchKernelGGL(k_draw_write, dim3(nb), dim3(256), 0, s, keep, cnt, rs, t, cap_round,
+                     cand_point);
   KMPAR_RET_LAST();
 }
 
@@ -727,16 +756,6 @@ __global__ __launch_bounds__(256) void k_scan_apply(int* a, int64_t L, const int
     if (j < L) a[j] = run + ex;
     run += tot;
   }
-}
-
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  const int lane = threadIdx.x % kWave;
-  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-__device__ __forceinline__ uint64_t lanemask_gt() {
-  const int lane = threadIdx.x % kWave;
-  return lane == kWave - 1 ? 0ull : (~0ull << (lane + 1));
 }
 
 // One wave per block scatters its chunk in point order, a 64-point tile at a

@@ -145,8 +145,8 @@ hipError_t launch_gather(kmpar_dtype dt, const void* X, const float* row_scale, 
                          float* CallT, int ldT, hipStream_t s);
 hipError_t launch_phi(const float* D2, int n, double* part, double* out, hipStream_t s);
 hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, uint64_t seed, int t,
-                       uint64_t inst, int* cnt, int* scan_total, int* rs, int cap_round,
-                       int* cand_point, kmpar_stats* st, hipStream_t s);
+                       uint64_t inst, int* cnt, uint64_t* keep, int* scan_total, int* rs,
+                       int cap_round, int* cand_point, kmpar_stats* st, hipStream_t s);
 hipError_t launch_finish_rounds(const int* rs, int rounds, kmpar_stats* st, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s);
 hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s);
