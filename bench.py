@@ -243,6 +243,21 @@ def pmc_probe(kmpar, synth, torch, args):
     log("pmc probe done")
 
 
+def lloyd_probe(kmpar, synth, torch, args, iters=4):
+    """Profiling workload for row a9 at full size: one REFINED init on the
+    C1 input, then `iters` Lloyd steps from its centers."""
+    X = synth.heavy_tailed(args.n, args.d, seed=args.seed)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    ctx = kmpar.Context(0, kmpar.MODE_REFINED)
+    r = ctx.init(Xd, k=args.k, ell=args.ell_mult * args.k, rounds=args.rounds, seed=args.seed)
+    C = r.centers.clone()
+    torch.cuda.synchronize()
+    for _ in range(iters):
+        _, phi = ctx.lloyd_step(Xd, C)
+    torch.cuda.synchronize()
+    log(f"lloyd probe done: {iters} steps, phi {float(phi.item()):.6g}")
+
+
 def screen_traffic():
     """HBM bytes per k_screen launch from the committed counter summary, or
     None when the summary is missing or the kernel source changed since."""
@@ -287,6 +302,8 @@ def main():
                     help="also time the 4,096-instance batched workload (FP32 and BF16)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--recluster-path", type=int, default=0, choices=[0, 1, 2])
+    ap.add_argument("--lloyd-probe", action="store_true",
+                    help="profiling workload: one REFINED init then 4 Lloyd steps on the C1 input")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run only a 1 GiB copy (counter calibration) and one step, for rocprofv3 --pmc")
     args = ap.parse_args()
@@ -304,6 +321,9 @@ def main():
     ell = args.ell_mult * k
     if args.pmc_probe:
         pmc_probe(kmpar, synth, torch, args)
+        return
+    if args.lloyd_probe:
+        lloyd_probe(kmpar, synth, torch, args)
         return
     log(f"generating heavy-tailed input n={n} d={d}")
     X = synth.heavy_tailed(n, d, seed=args.seed)
