@@ -162,6 +162,48 @@ def test_lloyd_empty_cluster_and_bf16(ctx):
     np.testing.assert_allclose(C.cpu().numpy(), Co.astype(np.float32), rtol=1e-6, atol=1e-6)
 
 
+@pytest.mark.parametrize("case", ["big_cluster_wide", "many_keys_narrow", "fp8"])
+def test_lloyd_update_shapes(ctx, case):
+    # The centroid update against the oracle's FP64 means (following the GPU's
+    # assignment): clusters spanning many sorted chunks and rows wider than
+    # one 64-lane slice; k above 1,024 with d = 2 (eleven key bits, 128
+    # slices per block); FP8 rows. Two runs give bitwise-equal centers.
+    rng = np.random.default_rng(11)
+    rs = None
+    if case == "big_cluster_wide":
+        sizes, d = (40000, 15000, 5001), 100
+        means = rng.normal(size=(3, d)) * 20.0
+        X = np.concatenate([means[c] + rng.normal(size=(sz, d)) for c, sz in enumerate(sizes)])
+        X = X[rng.permutation(len(X))].astype(np.float32)
+        k = 3
+    elif case == "many_keys_narrow":
+        X = rng.uniform(-100.0, 100.0, size=(50000, 2)).astype(np.float32)
+        k = 1500
+    else:
+        X = synth.gauss_mixture_sigma(30000, 16, 40, seed=5)
+        k = 40
+    n, d = X.shape
+    if case == "fp8":
+        q, sc = to_e4m3(X)
+        Xd, rs = _dev(q), _dev(sc)
+        X64 = decoded_fp64(q, "fp8", sc)
+    else:
+        Xd, X64 = _dev(X), X.astype(np.float64)
+    C0 = X64[rng.choice(n, k, replace=False)].astype(np.float32)
+    outs = []
+    for rep in range(2):
+        C = torch.from_numpy(C0.copy()).to("cuda:0")
+        a, phi = ctx.lloyd_step(Xd, C, row_scale=rs, want_assign=True)
+        torch.cuda.synchronize()
+        outs.append((a.cpu().numpy(), C.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    a, Cg = outs[0]
+    Co, cnt = O.lloyd_update(X64, a, C0.astype(np.float64))
+    if case == "big_cluster_wide":
+        assert cnt.max() > 8 * 2048
+    np.testing.assert_allclose(Cg, Co.astype(np.float32), rtol=1e-6, atol=1e-6)
+
+
 def test_init_large_candidate_set_multiworkgroup_recluster(ctx):
     # ell = 4000 over 5 rounds gives a candidate capacity above what one
     # workgroup's LDS holds, so the recluster runs over several workgroups.
