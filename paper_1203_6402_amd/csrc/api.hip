@@ -99,6 +99,7 @@ struct InitLayout {
   float* norms;
   int* list;
   int* list_len;
+  int2* rescan_part;  // slice winners of a split rescan
   void* B;
   float* ncg;
   float* scg;
@@ -148,6 +149,7 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.norms = c.take<float>(n);
   L.list = c.take<int>(n);
   L.list_len = c.take<int>(4);
+  L.rescan_part = c.take<int2>((size_t)kRescanMaxItems * kRescanPts);
   L.B = c.take<char>(screen_b_bytes(tiles, d));
   L.ncg = c.take<float>((size_t)tiles * 16);
   L.scg = c.take<float>((size_t)tiles * 16);
@@ -166,6 +168,7 @@ struct AssignLayout {
   float* norms;
   int* list;
   int* list_len;
+  int2* rescan_part;  // slice winners of a split rescan
   void* B;
   float* ncg;
   float* scg;
@@ -196,6 +199,7 @@ AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op, kmpar
   L.norms = c.take<float>(n);
   L.list = c.take<int>(n);
   L.list_len = c.take<int>(4);
+  L.rescan_part = c.take<int2>((size_t)kRescanMaxItems * kRescanPts);
   L.B = c.take<char>(screen_b_bytes(tiles, d));
   L.ncg = c.take<float>((size_t)tiles * 16);
   L.scg = c.take<float>((size_t)tiles * 16);
@@ -296,8 +300,8 @@ hipError_t timed_fold(kmpar_ctx* ctx, int slot, kmpar_dtype dt, int DP, const Fo
 // B operands, and their scales (scg).
 hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const FoldArgs& fa,
                         int max_tiles, const float* norms, const void* Apre, void* B, float* ncg,
-                        const int* cand, float* scg, int* list, int* list_len, kmpar_stats* st,
-                        hipStream_t s) {
+                        const int* cand, float* scg, int* list, int* list_len, int2* rpart,
+                        kmpar_stats* st, hipStream_t s) {
   const int KS = screen_ksteps(split, fa.d);
   const float om2g = 1.0f - 2.0f * screen_g(dt, split, fa.d);
   const bool fp8 = dt == KMPAR_FP8_E4M3;
@@ -335,6 +339,7 @@ hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const
   rf.list_len = list_len;
   rf.list_cap = fa.n;
   rf.norms = nullptr;
+  rf.rpart = rpart;
   return timed(ctx, kSlotRescan, 0, list_len, fa.rs, fa.m_host, s,
                [&] { return launch_rescan(dt, DP, rf, s); });
 }
@@ -591,7 +596,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
     fa.rs = L.rs + t;
     if (refined) {
       KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (cap_round + 15) / 16, L.norms, Apre, L.B,
-                             L.ncg, L.cand_point, L.scg, L.list, L.list_len, st, s));
+                             L.ncg, L.cand_point, L.scg, L.list, L.list_len, L.rescan_part, st, s));
     } else {
       KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
     }
@@ -670,7 +675,7 @@ static int assign_pass(kmpar_ctx* ctx, kmpar_dtype dtype, const AssignLayout& L,
       KMPAR_HIP(launch_rownorm(dtype, fa.X, fa.row_scale, fa.n, d, L.norms, s));
     }
     KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (m + 15) / 16, L.norms, Apre, L.B, L.ncg,
-                           nullptr, L.scg, L.list, L.list_len, nullptr, s));
+                           nullptr, L.scg, L.list, L.list_len, L.rescan_part, nullptr, s));
   } else {
     KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
   }

@@ -132,19 +132,67 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
 // candidate, and the eight slots' winners are merged by (distance, id): per
 // point the smallest distance, the lowest id on ties, which is the decision
 // the one-thread-per-point fold takes.
-constexpr int kRescanPts = 32;    // listed points per block step
+// A short list leaves most CUs idle, so when the groups of 32 points number
+// at most half the grid, each group's candidates are cut into S slices of
+// whole chunks (S a power of two, at most 8, with groups * S within the
+// grid), one block per (group, slice); the slices' winners go to a.rpart and
+// k_rescan_merge combines them in slice order by (distance, id), the same
+// decision. Both kernels derive S from the device-side list length alone.
 constexpr int kRescanCands = 32;  // candidate rows per LDS chunk
+constexpr int kRescanMaxSplit = 8;
+
+__device__ __forceinline__ int rescan_split(int groups, int grid, bool can_split) {
+  int S = 1;
+  if (can_split)
+    while (S < kRescanMaxSplit && groups * S * 2 <= grid) S *= 2;
+  return S;
+}
+
+// Keeps (b, j) as the better of itself and (ob, oj): smaller distance, then
+// lower id (j = -1, no candidate, compares above every id).
+__device__ __forceinline__ void rescan_better(float ob, int oj, float& b, int& j) {
+  if (ob < b || (ob == b && (unsigned)oj < (unsigned)j)) {
+    b = ob;
+    j = oj;
+  }
+}
+
+// The fold's update of point p by its best listed-pass candidate.
+__device__ __forceinline__ void rescan_apply(const FoldArgs& a, int p, int id0, float best, int bj) {
+  if (a.first) {
+    a.D2[p] = best;
+    a.A[p] = bj >= 0 ? id0 + bj : -1;
+  } else if (bj >= 0 && best < a.D2[p]) {
+    a.D2[p] = best;
+    a.A[p] = id0 + bj;
+  }
+}
 
 template <int DP, typename T>
 __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
   constexpr int P = kRescanPts, CC = kRescanCands, XS = DP + 1, CSTR = DP + 4;
   constexpr int NS = 256 / P, NI = CC / NS;  // candidate slots, candidates per slot
+  constexpr int NV = (CC * (DP / 4) + 255) / 256;  // float4 of a chunk per thread
+  // This thread's share of candidate rows c0 .. c0+CC-1 (zeros past m).
+  auto load_chunk = [](const float* C, int c0, int m, float4 (&v)[NV]) {
+    const int nc = min(CC, m - c0);
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int idx = threadIdx.x + u * 256;
+      const int j = idx / (DP / 4), e4 = idx - j * (DP / 4);
+      v[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (idx < CC * (DP / 4) && j < nc)
+        v[u] = reinterpret_cast<const float4*>(C + (int64_t)(c0 + j) * DP)[e4];
+    }
+  };
   __shared__ float xs[P * XS];
   __shared__ __attribute__((aligned(16))) float cs[CC * CSTR];
   __shared__ float rb[NS][P];
   __shared__ int rj[NS][P];
   const int r = threadIdx.x % P, slot = threadIdx.x / P;
   const int nlist = *a.list_len;
+  const int groups = (nlist + P - 1) / P;
+  const int S = rescan_split(groups, gridDim.x, a.rpart != nullptr);
   int id0, m;
   if (a.rs) {
     id0 = a.rs[0];
@@ -155,8 +203,12 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
   }
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const float* __restrict__ C = a.C + (int64_t)id0 * DP;
-  for (int g = blockIdx.x; g * P < nlist; g += gridDim.x) {
+  const int nch = (m + CC - 1) / CC;
+  for (int it = blockIdx.x; it < groups * S; it += gridDim.x) {
+    const int g = it / S, sl = it - g * S;
     const int np = min(P, nlist - g * P);
+    // this slice's candidates: chunks [sl nch / S, (sl + 1) nch / S)
+    const int cbeg = (sl * nch / S) * CC, cend = min(m, ((sl + 1) * nch / S) * CC);
     __syncthreads();  // the previous group is merged and written
     for (int idx = threadIdx.x; idx < P * DP; idx += 256) {
       const int q = idx / DP, e = idx - q * DP;
@@ -170,16 +222,23 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
     float best = INFINITY;
     int bj = -1;
     const float* xr = xs + r * XS;
-    for (int c0 = 0; c0 < m; c0 += CC) {
-      const int nc = min(CC, m - c0);
+    // Candidate chunks go global -> registers -> LDS; the next chunk's loads
+    // are issued before the current chunk is computed.
+    float4 pre[NV];
+    if (cbeg < cend) load_chunk(C, cbeg, cend, pre);
+    for (int c0 = cbeg; c0 < cend; c0 += CC) {
+      const int nc = min(CC, cend - c0);
       __syncthreads();  // the previous chunk is consumed (and xs is written)
-      for (int idx = threadIdx.x; idx < CC * (DP / 4); idx += 256) {
-        const int j = idx / (DP / 4), e4 = idx - j * (DP / 4);
-        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (j < nc) v = reinterpret_cast<const float4*>(C + (int64_t)(c0 + j) * DP)[e4];
-        reinterpret_cast<float4*>(cs + j * CSTR)[e4] = v;
+#pragma unroll
+      for (int u = 0; u < NV; ++u) {
+        const int idx = threadIdx.x + u * 256;
+        if (idx < CC * (DP / 4)) {
+          const int j = idx / (DP / 4), e4 = idx - j * (DP / 4);
+          reinterpret_cast<float4*>(cs + j * CSTR)[e4] = pre[u];
+        }
       }
       __syncthreads();
+      if (c0 + CC < cend) load_chunk(C, c0 + CC, cend, pre);
       float acc[NI];
 #pragma unroll
       for (int i = 0; i < NI; ++i) acc[i] = 0.0f;
@@ -212,23 +271,31 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
     rj[slot][r] = bj;
     __syncthreads();
     if (slot == 0 && r < np) {
-      for (int q = 1; q < NS; ++q) {
-        const float ob = rb[q][r];
-        const int oj = rj[q][r];
-        if (ob < best || (ob == best && (unsigned)oj < (unsigned)bj)) {
-          best = ob;
-          bj = oj;
-        }
-      }
-      const int p = a.list[g * P + r];
-      if (a.first) {
-        a.D2[p] = best;
-        a.A[p] = bj >= 0 ? id0 + bj : -1;
-      } else if (bj >= 0 && best < a.D2[p]) {
-        a.D2[p] = best;
-        a.A[p] = id0 + bj;
-      }
+      for (int q = 1; q < NS; ++q) rescan_better(rb[q][r], rj[q][r], best, bj);
+      if (S == 1) rescan_apply(a, a.list[g * P + r], id0, best, bj);
+      else a.rpart[(int64_t)it * P + r] = make_int2(__float_as_int(best), bj);
     }
+  }
+}
+
+// Merges the slices of a split rescan (nothing to do when S = 1). grid is the
+// rescan's launch grid, from which S is derived again.
+__global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
+  constexpr int P = kRescanPts;
+  const int nlist = *a.list_len;
+  const int groups = (nlist + P - 1) / P;
+  const int S = rescan_split(groups, grid, a.rpart != nullptr);
+  if (S == 1) return;
+  const int id0 = a.rs ? a.rs[0] : a.id0_host;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nlist; i += gridDim.x * 256) {
+    const int g = i / P, r = i - g * P;
+    float best = INFINITY;
+    int bj = -1;
+    for (int sl = 0; sl < S; ++sl) {
+      const int2 v = a.rpart[(int64_t)(g * S + sl) * P + r];
+      rescan_better(__int_as_float(v.x), v.y, best, bj);
+    }
+    rescan_apply(a, a.list[i], id0, best, bj);
   }
 }
 
@@ -267,7 +334,7 @@ static hipError_t launch_rescan_t(int DP, const FoldArgs& a, hipStream_t s) {
   // the listed count is only known on the device: enough blocks for the
   // largest list up to four per CU, each looping over groups of points
   int blocks = (a.list_cap + kRescanPts - 1) / kRescanPts;
-  if (blocks > 1024) blocks = 1024;
+  if (blocks > kRescanMaxItems) blocks = kRescanMaxItems;
   if (blocks < 1) return hipSuccess;
   const dim3 grid(blocks), block(256);
   switch (DP) {
@@ -282,6 +349,10 @@ static hipError_t launch_rescan_t(int DP, const FoldArgs& a, hipStream_t s) {
 #undef KMPAR_CASE
     default:
       return hipErrorInvalidValue;
+  }
+  if (a.rpart) {
+    const int mb = (min(a.list_cap, kRescanMaxItems * kRescanPts) + 255) / 256;
+    hipLaunchKernelGGL(k_rescan_merge, dim3(mb), dim3(256), 0, s, a, blocks);
   }
   return hipGetLastError();
 }

@@ -63,7 +63,11 @@ struct FoldArgs {
   const int* list_len;
   int list_cap;          // upper bound of *list_len
   float* norms;          // nullable: also write ||x||^2 (FP32) of every point
+  int2* rpart;           // nullable: kRescanMaxItems * kRescanPts slice winners of a split rescan
 };
+
+constexpr int kRescanPts = 32;        // listed points per rescan block step
+constexpr int kRescanMaxItems = 1024; // rescan grid limit (and slice-winner slots / 32)
 
 hipError_t launch_fold_direct(kmpar_dtype dt, int DP, const FoldArgs& a, hipStream_t s);
 // Listed points only (a.list, a.list_len, a.list_cap), one wave per point.
