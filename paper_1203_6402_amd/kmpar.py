@@ -146,7 +146,7 @@ class Context:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:  # _lib is gone at interpreter exit
             _lib.kmpar_destroy(h)
             self._h = None
 

@@ -1,0 +1,41 @@
+"""Independent kmpar_init calls in flight on two streams at once (two
+contexts, each with its own workspace): one call's step-8 recluster runs
+beside the other's distance passes, and every call gives the result it gives
+alone on one stream."""
+import pytest
+import torch
+
+from paper_1203_6402_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("mode", ["refined", "plain"])
+def test_two_streams_interleaved_equal_single_stream(mode):
+    from paper_1203_6402_amd import kmpar
+    m = kmpar.MODE_REFINED if mode == "refined" else kmpar.MODE_PLAIN_FP32
+    X = torch.from_numpy(synth.heavy_tailed(200000, 42, seed=3)).to("cuda:0")
+    Y = torch.from_numpy(synth.gauss_mixture(150000, 24, 60, 10.0, seed=4)).to("cuda:0")
+    args = {"X": (X, dict(k=100, ell=200.0, rounds=5, seed=1)),
+            "Y": (Y, dict(k=60, ell=120.0, rounds=4, seed=2))}
+    alone = kmpar.Context(0, m)
+    ref = {name: alone.init(D, **kw) for name, (D, kw) in args.items()}
+    torch.cuda.synchronize()
+    ctxs = [kmpar.Context(0, m) for _ in range(2)]
+    strs = [torch.cuda.Stream() for _ in range(2)]
+    cur = torch.cuda.current_stream()
+    for s in strs:
+        s.wait_stream(cur)
+    outs = []
+    for i in range(6):
+        name = "X" if i % 2 == 0 else "Y"
+        D, kw = args[name]
+        outs.append((name, ctxs[i % 2].init(D, stream=strs[i % 2], check=False, **kw)))
+    for s in strs:
+        cur.wait_stream(s)
+    torch.cuda.synchronize()
+    for name, o in outs:
+        st = kmpar.parse_stats(o.stats["_raw"], args[name][1]["rounds"])
+        assert st["status"] == 0, (name, st["status"])
+        assert st["n_centers"] == ref[name].stats["n_centers"]
+        assert torch.equal(o.centers[:st["n_centers"]], ref[name].centers), name
