@@ -24,7 +24,13 @@
  *    rounds <= KMPAR_MAX_ROUNDS.
  *  - Results are deterministic: the same inputs, seed, mode and device give
  *    bit-identical outputs (every reduction runs in a fixed order).
- *  - Calls that share one workspace or one context must not overlap.
+ *  - Calls that share one workspace or one context must not overlap.  Calls
+ *    with their own context and workspace may run concurrently on different
+ *    streams of one device, and give the results they give alone.  Step 8 of
+ *    kmpar_init runs on a few workgroups that wait for one another; a
+ *    concurrent kernel that holds the compute units can delay them, and a
+ *    wait that exceeds its bound (seconds) ends the call with status
+ *    KMPAR_E_HIP in kmpar_stats rather than hanging.
  */
 #ifndef KMPAR_H_
 #define KMPAR_H_
