@@ -1,5 +1,5 @@
-"""Independent kmpar_init calls in flight on two streams at once (two
-contexts, each with its own workspace): one call's step-8 recluster runs
+"""Independent kmpar_init calls in flight on several streams at once (one
+context and workspace per stream): one call's step-8 recluster runs
 beside the other's distance passes, and every call gives the result it gives
 alone on one stream."""
 import pytest
@@ -10,8 +10,8 @@ from paper_1203_6402_amd import synth
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("mode", ["refined", "plain"])
-def test_two_streams_interleaved_equal_single_stream(mode):
+@pytest.mark.parametrize("mode,nstr", [("refined", 2), ("refined", 3), ("plain", 3)])
+def test_streams_interleaved_equal_single_stream(mode, nstr):
     from paper_1203_6402_amd import kmpar
     m = kmpar.MODE_REFINED if mode == "refined" else kmpar.MODE_PLAIN_FP32
     X = torch.from_numpy(synth.heavy_tailed(200000, 42, seed=3)).to("cuda:0")
@@ -21,8 +21,8 @@ def test_two_streams_interleaved_equal_single_stream(mode):
     alone = kmpar.Context(0, m)
     ref = {name: alone.init(D, **kw) for name, (D, kw) in args.items()}
     torch.cuda.synchronize()
-    ctxs = [kmpar.Context(0, m) for _ in range(2)]
-    strs = [torch.cuda.Stream() for _ in range(2)]
+    ctxs = [kmpar.Context(0, m) for _ in range(nstr)]
+    strs = [torch.cuda.Stream() for _ in range(nstr)]
     cur = torch.cuda.current_stream()
     for s in strs:
         s.wait_stream(cur)
@@ -30,7 +30,7 @@ def test_two_streams_interleaved_equal_single_stream(mode):
     for i in range(6):
         name = "X" if i % 2 == 0 else "Y"
         D, kw = args[name]
-        outs.append((name, ctxs[i % 2].init(D, stream=strs[i % 2], check=False, **kw)))
+        outs.append((name, ctxs[i % nstr].init(D, stream=strs[i % nstr], check=False, **kw)))
     for s in strs:
         cur.wait_stream(s)
     torch.cuda.synchronize()
