@@ -219,7 +219,8 @@ def batched_bench(kmpar, synth, torch, seed, count, steps=2):
                 f"{bad} instances with a non-OK status")
         if conv is not None:
             del Xv
-    out["tuned_tiles"] = [{"dtype": dt, "padded_d": dp, "candidates_per_step": cb}
+    out["tuned_tiles"] = [{"dtype": dt, "padded_d": dp, "candidates_per_step": 1 if cb == 200 else cb,
+                           "row_split_over_two_waves": cb == 200}
                           for dt, dp, cb in tuned.batch_tiles()]
     log(f"batched tiles: {out['tuned_tiles']}")
     del Xs

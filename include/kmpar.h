@@ -125,8 +125,9 @@ int kmpar_set_option(kmpar_ctx* ctx, kmpar_option opt, int64_t value);
 
 /* The batched tile shapes tuned so far, one entry per (dtype, padded row
  * length): up to `cap` entries are written to dtype[], dp[] (padded row
- * length) and cb[] (candidates per step); *count receives the number of
- * entries.  Host memory; no device work. */
+ * length) and cb[] (the fold variant: 1, 2, 4 or 8 candidates per step, or
+ * 200 for rows of 65 to 128 elements split over two waves); *count receives
+ * the number of entries.  Host memory; no device work. */
 int kmpar_batch_tiles(const kmpar_ctx* ctx, int32_t* dtype, int32_t* dp, int32_t* cb, int32_t cap,
                       int32_t* count);
 

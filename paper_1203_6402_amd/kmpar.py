@@ -178,8 +178,9 @@ class Context:
         self._check(_lib.kmpar_set_option(self._h, opt, int(value)), "kmpar_set_option")
 
     def batch_tiles(self) -> list:
-        """[(dtype code, padded row length, candidates per step)] the batched
-        tuner has chosen so far."""
+        """[(dtype code, padded row length, fold variant)] the batched tuner
+        has chosen so far: 1, 2, 4 or 8 candidates per step, or 200 for rows
+        split over two waves."""
         cnt = _i32(0)
         self._check(_lib.kmpar_batch_tiles(self._h, None, None, None, 0, ctypes.byref(cnt)),
                     "kmpar_batch_tiles")

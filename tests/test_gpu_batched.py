@@ -66,6 +66,26 @@ def test_batch_of_one_equals_single_instance(ctx):
     assert sts[0]["phi"] == single.stats["phi"]
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_row_split_fold_equals_single_instance(ctx, dtype):
+    # Rows of 65 to 128 padded elements are folded with each row split over
+    # two waves (the first 64 elements, then the rest from the partial sum).
+    # For every padded length of that range, a batch of one (Philox instance
+    # 0, as a single call uses) equals the single-instance init bit for bit.
+    for j, d in enumerate((65, 72, 90, 100, 113, 127)):
+        X = _dev(synth.gauss_mixture(4000 + 997 * j, d, 12, 10.0, seed=30 + j))
+        if dtype == "bf16":
+            X = X.to(torch.bfloat16)
+        k = 12 + 3 * j
+        single = ctx.init(X, k=k, ell=2.0 * k, rounds=4, seed=17, trace=True)
+        cs, sts, trs = ctx.init_batched([X], [k], [2.0 * k], 4, seed=17, trace=True)
+        torch.cuda.synchronize()
+        for key in ("cand_point", "cand_weight", "assign", "d2"):
+            assert torch.equal(single.trace[key], trs[0][key]), (d, key)
+        assert torch.equal(single.centers, cs[0]), d
+        assert sts[0]["phi"] == single.stats["phi"], d
+
+
 def _same_batches(a, b):
     (ca, sa, ta), (cb, sb, tb) = a, b
     for i in range(len(ca)):
@@ -133,7 +153,12 @@ def test_batched_autotune_keeps_results():
     dps = sorted({kmpar_dp(int(d)) for d in ds})
     assert sorted(t[1] for t in tiles) == dps
     for dt, dp, cb in tiles:
-        assert cb in ((1, 2, 4) if dp <= 128 else (4, 8))
+        # candidates per step (whole rows up to 128 elements, halves beyond);
+        # 200: each row split over two waves (65 to 128 elements)
+        if dp > 128:
+            assert cb in (4, 8)
+        else:
+            assert cb in ((1, 2, 4, 200) if dp > 64 else (1, 2, 4))
 
 
 def kmpar_dp(d):
