@@ -299,11 +299,111 @@ __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
   }
 }
 
+// The fold for rows of more than 128 padded elements (no list, no norms),
+// each row split over W = ceil(DP / 64) waves: a block of 256 W threads holds its
+// 256 points in four groups of W waves, wave s of a group keeping elements
+// [64 s, min(64 s + 64, DP)) of its 64 points' rows in registers, decoded
+// once. Per chunk of CH candidates, stage s continues the FMA chain of stage
+// s - 1 (a partial sum left in LDS, double buffered, one chunk behind) over
+// its elements and the last stage keeps the best candidate; one barrier per
+// step of the pipeline. The chain and the candidate order are the fold's, so
+// the result is bitwise the same. Read in halves by one thread, such rows
+// were re-read and re-decoded every 8 candidates (C3, 256 FP8 elements: a
+// PLAIN init took 121 s, 29 s split). At 96 to 128 elements whole rows in one
+// thread measured faster (C2, 128 FP32 elements: 1.6 s against 2.1 s split),
+// so they keep k_fold_direct.
+template <int DP, typename T>
+__global__ __launch_bounds__(kFoldBlock * ((DP + 63) / 64)) void k_fold_split(FoldArgs a) {
+  constexpr int W = (DP + 63) / 64;
+  constexpr int CH = 8;
+  static_assert(W >= 3 && W <= 4, "rows of 129 to 256 padded elements");
+  __shared__ float part[2][CH][W - 1][kFoldBlock];  // [buffer][candidate][stage][point]
+  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int st = wv / 4;                      // pipeline stage: elements [64 st, 64 st + 64)
+  const int pl = (wv % 4) * kWave + lane;     // the point within the block
+  const int i = blockIdx.x * kFoldBlock + pl;
+  const bool live = i < a.n;                  // every wave takes part in the barriers
+  int id0, m;
+  if (a.rs) {
+    id0 = a.rs[0];
+    m = a.rs[1] - id0;
+  } else {
+    id0 = a.id0_host;
+    m = a.m_host;
+  }
+  const float* __restrict__ C = a.C + (int64_t)id0 * DP + st * 64;
+  const T* __restrict__ X = static_cast<const T*>(a.X);
+  const float sc = live ? row_scale_of<T>(a.row_scale, i) : 1.0f;
+  const int d = a.d;
+  const int64_t row = (int64_t)i * d;
+  const int e0 = st * 64;
+  constexpr int NL = DP - 64 * (W - 1);       // elements of the last stage
+  float x[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) x[j] = (live && e0 + j < d) ? Elem<T>::get(X, row + e0 + j, sc) : 0.0f;
+  float best = INFINITY;
+  int bj = -1;
+  const int nch = (m + CH - 1) / CH;
+  for (int it = 0; it < nch + W - 1; ++it) {
+    const int c = it - st;                    // the chunk this stage takes now
+    if (c >= 0 && c < nch) {
+      const int c0 = c * CH, nc = min(CH, m - c0);
+      const int b = c & 1;
+      if (st == W - 1) {
+        for (int jj = 0; jj < nc; ++jj) {
+          const float* __restrict__ cr = C + (int64_t)(c0 + jj) * DP;
+          float acc = part[b][jj][W - 2][pl];
+#pragma unroll
+          for (int e = 0; e < NL; ++e) {
+            const float t = x[e] - cr[e];
+            acc = fmaf(t, t, acc);
+          }
+          if (acc < best) {
+            best = acc;
+            bj = c0 + jj;
+          }
+        }
+      } else {
+        for (int jj = 0; jj < nc; ++jj) {
+          const float* __restrict__ cr = C + (int64_t)(c0 + jj) * DP;
+          float acc = st == 0 ? 0.0f : part[b][jj][st - 1][pl];
+#pragma unroll
+          for (int e = 0; e < 64; ++e) {
+            const float t = x[e] - cr[e];
+            acc = fmaf(t, t, acc);
+          }
+          part[b][jj][st][pl] = acc;
+        }
+      }
+    }
+    __syncthreads();  // stage outputs of this step visible; inputs of the last step consumed
+  }
+  if (st != W - 1 || !live) return;
+  if (a.first) {
+    a.D2[i] = best;
+    a.A[i] = bj >= 0 ? id0 + bj : -1;
+  } else if (bj >= 0 && best < a.D2[i]) {
+    a.D2[i] = best;
+    a.A[i] = id0 + bj;
+  }
+}
+
 template <typename T>
 static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
   const int work = a.list ? a.list_cap : a.n;
   if (work <= 0) return hipSuccess;
   const dim3 grid((work + kFoldBlock - 1) / kFoldBlock), block(kFoldBlock);
+  if (!a.list && !a.norms && DP > 128) {
+    switch (DP) {
+#define KMPAR_SPLIT(V)                                                            \
+  case V:                                                                  \
+    hipLaunchKernelGGL((k_fold_split<V, T>), grid, dim3(kFoldBlock * ((V + 63) / 64)), 0, s, a); \
+    return hipGetLastError();
+      KMPAR_SPLIT(160) KMPAR_SPLIT(192) KMPAR_SPLIT(224) KMPAR_SPLIT(256)
+#undef KMPAR_SPLIT
+      default: break;
+    }
+  }
   switch (DP) {
 #define KMPAR_CASE(V) \
   case V:             \
