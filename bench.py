@@ -121,11 +121,13 @@ def c0_lloyd(kmpar, synth, torch, seed, iters=20, reps=5):
     return out
 
 
-def c3_compare(kmpar, synth, torch, seed, steps=2, with_plain=True):
+def c3_compare(kmpar, synth, torch, seed, steps=2, with_plain=True, lloyd_iters=0):
     """FP8 precision workload: n = 50M, d = 256, e4m3 codes with per-row
     scales max|x|/448 from a 2,000-component Gaussian mixture (centers
     N(0, 25 I), sigma logU[0.5, 4]), k = 2000, ell = 2k, r = 5; REFINED init
-    against PLAIN (PLAIN takes about a minute here and runs once)."""
+    against PLAIN (PLAIN takes about half a minute here and runs once); then,
+    when asked, Lloyd iterations from the REFINED centers (FP8 assignment
+    passes run the direct form, a few seconds each)."""
     n, d, k, rounds = 50_000_000, 256, 2000, 5
     ell = 2.0 * k
     log("C3: generating 50M x 256 e4m3 rows on the device")
@@ -162,10 +164,27 @@ def c3_compare(kmpar, synth, torch, seed, steps=2, with_plain=True):
     out["rescanned_points"] = rp.stats["n_rescanned"]
     log(f"C3 screen: {p['launches']} launches, avg {dur*1e6:.1f} us, "
         f"{flops/dur/1e12:.1f} TFLOP/s algorithmic")
+    if lloyd_iters > 0:
+        C = r.centers.clone()
+        phi0 = float(ctx.cost(Q, C, row_scale=S).item())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for it in range(lloyd_iters):
+            _, phi = ctx.lloyd_step(Q, C, row_scale=S)
+            torch.cuda.synchronize()
+            log(f"C3 Lloyd iteration {it + 1}/{lloyd_iters}: phi of its input centers {float(phi.item()):.6g}")
+        e1.record()
+        torch.cuda.synchronize()
+        out["lloyd_iterations"] = lloyd_iters
+        out["lloyd_ms_per_iter"] = e0.elapsed_time(e1) / lloyd_iters
+        out["lloyd_phi_init"] = phi0
+        out["lloyd_phi_last_input"] = float(phi.item())
+        log(f"C3 Lloyd: {out['lloyd_ms_per_iter']:.1f} ms per iteration")
     del ctx
     if with_plain:
         pctx = kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
-        log("C3 plain: one init (about a minute)")
+        log("C3 plain: one init (about half a minute)")
         holder = {}
         out["plain_init_ms"] = timed(lambda: holder.__setitem__(
             "r", pctx.init(Q, k=k, ell=ell, rounds=rounds, seed=seed, row_scale=S)), 1)
@@ -293,6 +312,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of the input the oracle baseline runs on (0: all of them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--c3-lloyd", type=int, default=0,
+                    help="with --c3: Lloyd iterations from the REFINED centers (the paper runs 10)")
     ap.add_argument("--no-lloyd", action="store_true",
                     help="skip the Lloyd legs (C1 full size and C0)")
     ap.add_argument("--no-precision", action="store_true",
@@ -469,7 +490,8 @@ def main():
 
     c3 = None
     if args.c3:
-        c3 = c3_compare(kmpar, synth, torch, args.seed, with_plain=not args.c3_no_plain)
+        c3 = c3_compare(kmpar, synth, torch, args.seed, with_plain=not args.c3_no_plain,
+                        lloyd_iters=args.c3_lloyd)
 
     batched = None
     if args.batched:
