@@ -333,8 +333,8 @@ def main():
                     help="run only a 1 GiB copy (counter calibration) and one step, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "row-sharded design is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); a row-sharded "
+              "multi-GPU path is not part of this library.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
