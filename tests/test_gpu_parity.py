@@ -48,6 +48,8 @@ def test_init_gaussmixture_c0(ctx):
     (4099, 44, 25, 12.5, 5, "heavy"),
     (2500, 128, 30, 60.0, 4, "sigma"),
     (1500, 256, 20, 40.0, 3, "sigma"),
+    (1801, 150, 20, 40.0, 3, "sigma"),   # rows of 160 padded elements: three waves, last one 32
+    (1601, 200, 20, 40.0, 3, "heavy"),   # 224: four waves, last one 32
     (777, 7, 6, 1e9, 1, "gauss"),        # every point kept in round 1: C = X
 ])
 def test_init_shapes(ctx, n, d, k, ell, rounds, kind):
@@ -63,6 +65,21 @@ def test_init_shapes(ctx, n, d, k, ell, rounds, kind):
     if ell >= 1e9:
         assert r.stats["n_candidates"] == n
         assert np.all(tr["cand_weight"] == 1)
+
+
+@pytest.mark.parametrize("dtype,d", [("bf16", 160), ("fp8", 200), ("fp8", 256)])
+def test_init_wide_rows_low_precision(ctx, dtype, d):
+    # The direct-form fold of rows over 128 elements (each row split over
+    # three or four waves) on BF16 and FP8 storage, against the oracle.
+    X = synth.gauss_mixture_sigma(2203, d, 30, seed=d)
+    if dtype == "bf16":
+        Xb = to_bf16_bits(X)
+        r, tr = gpu_init(ctx, _dev(Xb).view(torch.bfloat16), 25, 50.0, 3, 4)
+        compare_init(decoded_fp64(Xb, "bf16"), r, tr, 25, 50.0, 3, 4)
+    else:
+        q, s = to_e4m3(X)
+        r, tr = gpu_init(ctx, _dev(q), 25, 50.0, 3, 4, row_scale=_dev(s))
+        compare_init(decoded_fp64(q, "fp8", s), r, tr, 25, 50.0, 3, 4)
 
 
 def test_init_bf16_and_fp8_inputs(ctx):
