@@ -309,9 +309,10 @@ __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
 // step of the pipeline. The chain and the candidate order are the fold's, so
 // the result is bitwise the same. Read in halves by one thread, such rows
 // were re-read and re-decoded every 8 candidates (C3, 256 FP8 elements: a
-// PLAIN init took 121 s, 29 s split). At 96 to 128 elements whole rows in one
-// thread measured faster (C2, 128 FP32 elements: 1.6 s against 2.1 s split),
-// so they keep k_fold_direct.
+// PLAIN init took 121 s, 29 s split). Rows of 65 to 128 elements use the
+// two-wave form below (k_fold_pair), whose registers allow seven waves per
+// SIMD (C2, 128 BF16 elements: a PLAIN init 1.6 s with whole rows in one
+// thread, 0.7 s).
 template <int DP, typename T>
 __global__ __launch_bounds__(kFoldBlock * ((DP + 63) / 64)) void k_fold_split(FoldArgs a) {
   constexpr int W = (DP + 63) / 64;
@@ -388,11 +389,105 @@ __global__ __launch_bounds__(kFoldBlock * ((DP + 63) / 64)) void k_fold_split(Fo
   }
 }
 
+// The fold for rows of 65 to 128 padded elements (no list, no norms), each
+// row split over two waves: a block of 2 * kFoldBlock threads holds its 256
+// points in four pairs of waves, the first wave of a pair with elements
+// [0, 64) of its 64 rows in registers, the second with [64, DP). Per chunk
+// of 16 candidates the first wave runs the FMA chain over its elements and
+// leaves each partial sum in LDS; one chunk later the second wave continues
+// the chain over the rest of the row and keeps the best candidate. Same chain
+// and candidate order as k_fold_direct, so the result is bitwise the same.
+template <int DP, typename T>
+__global__ __launch_bounds__(2 * kFoldBlock) void k_fold_pair(FoldArgs a) {
+  static_assert(DP > 64 && DP <= 128, "rows of 65 to 128 padded elements");
+  constexpr int H1 = DP - 64, CH = 16;
+  __shared__ float part[2][CH][kFoldBlock];  // [buffer][candidate of the chunk][point]
+  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int half = wv / 4;                    // 0: elements [0, 64); 1: [64, DP)
+  const int pl = (wv % 4) * kWave + lane;     // the point within the block
+  const int i = blockIdx.x * kFoldBlock + pl;
+  const bool live = i < a.n;                  // every wave takes part in the barriers
+  int id0, m;
+  if (a.rs) {
+    id0 = a.rs[0];
+    m = a.rs[1] - id0;
+  } else {
+    id0 = a.id0_host;
+    m = a.m_host;
+  }
+  const float* __restrict__ C = a.C + (int64_t)id0 * DP;
+  const T* __restrict__ X = static_cast<const T*>(a.X);
+  const float sc = live ? row_scale_of<T>(a.row_scale, i) : 1.0f;
+  const int d = a.d;
+  const int64_t row = (int64_t)i * d;
+  const int e0 = half ? 64 : 0;
+  float x[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) x[j] = (live && e0 + j < d) ? Elem<T>::get(X, row + e0 + j, sc) : 0.0f;
+  float best = INFINITY;
+  int bj = -1;
+  const int nch = (m + CH - 1) / CH;
+  for (int it = 0; it <= nch; ++it) {
+    if (half == 0) {
+      if (it < nch) {
+        const int c0 = it * CH, nc = min(CH, m - c0);
+        float* dst = &part[it & 1][0][pl];
+        for (int jj = 0; jj < nc; ++jj) {
+          const float* __restrict__ cr = C + (int64_t)(c0 + jj) * DP;
+          float acc = 0.0f;
+#pragma unroll
+          for (int e = 0; e < 64; ++e) {
+            const float t = x[e] - cr[e];
+            acc = fmaf(t, t, acc);
+          }
+          dst[jj * kFoldBlock] = acc;
+        }
+      }
+    } else if (it > 0) {
+      const int c0 = (it - 1) * CH, nc = min(CH, m - c0);
+      const float* src = &part[(it - 1) & 1][0][pl];
+      for (int jj = 0; jj < nc; ++jj) {
+        const float* __restrict__ cr = C + (int64_t)(c0 + jj) * DP + 64;
+        float acc = src[jj * kFoldBlock];
+#pragma unroll
+        for (int e = 0; e < H1; ++e) {
+          const float t = x[e] - cr[e];
+          acc = fmaf(t, t, acc);
+        }
+        if (acc < best) {
+          best = acc;
+          bj = c0 + jj;
+        }
+      }
+    }
+    __syncthreads();  // chunk it written, chunk it - 1 consumed
+  }
+  if (half == 0 || !live) return;
+  if (a.first) {
+    a.D2[i] = best;
+    a.A[i] = bj >= 0 ? id0 + bj : -1;
+  } else if (bj >= 0 && best < a.D2[i]) {
+    a.D2[i] = best;
+    a.A[i] = id0 + bj;
+  }
+}
+
 template <typename T>
 static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
   const int work = a.list ? a.list_cap : a.n;
   if (work <= 0) return hipSuccess;
   const dim3 grid((work + kFoldBlock - 1) / kFoldBlock), block(kFoldBlock);
+  if (!a.list && !a.norms && DP > 64 && DP <= 128) {
+    switch (DP) {
+#define KMPAR_PAIR(V)                                                             \
+  case V:                                                                  \
+    hipLaunchKernelGGL((k_fold_pair<V, T>), grid, dim3(2 * kFoldBlock), 0, s, a);      \
+    return hipGetLastError();
+      KMPAR_PAIR(80) KMPAR_PAIR(96) KMPAR_PAIR(112) KMPAR_PAIR(128)
+#undef KMPAR_PAIR
+      default: break;
+    }
+  }
   if (!a.list && !a.norms && DP > 128) {
     switch (DP) {
 #define KMPAR_SPLIT(V)                                                            \
