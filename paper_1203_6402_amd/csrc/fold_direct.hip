@@ -308,11 +308,11 @@ __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
 // its elements and the last stage keeps the best candidate; one barrier per
 // step of the pipeline. The chain and the candidate order are the fold's, so
 // the result is bitwise the same. Read in halves by one thread, such rows
-// were re-read and re-decoded every 8 candidates (C3, 256 FP8 elements: a
-// PLAIN init took 121 s, 29 s split). Rows of 65 to 128 elements use the
-// two-wave form below (k_fold_pair), whose registers allow seven waves per
-// SIMD (C2, 128 BF16 elements: a PLAIN init 1.6 s with whole rows in one
-// thread, 0.7 s).
+// were re-read and re-decoded every 8 candidates (n = 50M rows of 256 FP8
+// elements, k = 2000: a PLAIN init took 121 s, 29 s split). Rows of 65 to
+// 128 elements use the two-wave form below (k_fold_pair), whose registers
+// allow seven waves per SIMD (n = 16M rows of 128 BF16 elements, k = 1000: a
+// PLAIN init 1.6 s with whole rows in one thread, 0.7 s).
 template <int DP, typename T>
 __global__ __launch_bounds__(kFoldBlock * ((DP + 63) / 64)) void k_fold_split(FoldArgs a) {
   constexpr int W = (DP + 63) / 64;
