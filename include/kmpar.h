@@ -209,6 +209,18 @@ int lloyd_step(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
                int64_t n, int32_t d, float* C, int32_t k, int32_t* assign, double* phi, void* ws,
                size_t ws_bytes, void* stream);
 
+/* `iters` Lloyd iterations (Section 1; Section 3.1) in one call, each exactly
+ * as lloyd_step computes it, so the result equals `iters` lloyd_step calls
+ * bit for bit; X's own preparation (its norms and, in REFINED mode, the
+ * screen's operands) is done once for all of them.  C [k x d FP32] is
+ * updated in place; assign [n] (nullable) receives the last iteration's
+ * assignment (to its input centers) and phi (device, nullable) the cost of
+ * each iteration's input centers, phi[0 .. iters-1].  iters = 0 does
+ * nothing.  Workspace: kmpar_workspace_size(KMPAR_OP_LLOYD, ...). */
+int kmpar_lloyd(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                int64_t n, int32_t d, float* C, int32_t k, int32_t iters, int32_t* assign,
+                double* phi, void* ws, size_t ws_bytes, void* stream);
+
 /* One independent clustering instance of kmpar_init_batched (64 bytes). */
 typedef struct kmpar_instance {
   const void* X;          /* device: n x d rows, the call's dtype            */

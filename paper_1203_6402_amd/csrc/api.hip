@@ -660,18 +660,21 @@ static int assign_common(kmpar_ctx* ctx, kmpar_op op, const void* X, const float
 }
 
 // Assignment pass against m FP32 centers (first = 1), REFINED when possible.
+// prepared: L.norms (and L.Apre) already hold X's norms and A operands from
+// an earlier pass of the same call.
 static int assign_pass(kmpar_ctx* ctx, kmpar_dtype dtype, const AssignLayout& L, const FoldArgs& fa,
-                       int m, hipStream_t s) {
+                       int m, hipStream_t s, bool prepared = false) {
   const int d = fa.d, DP = padded_dim(d);
   if (ctx->mode == KMPAR_MODE_REFINED && screen_supported(dtype, false, d) && m >= kScreenMinM) {
     const int split = screen_split(dtype, false);
     KMPAR_HIP(launch_fill_i32(L.list_len, 0, 1, s));
     const void* Apre = nullptr;
     if (!screen_a_direct(dtype, split, d)) {  // one read of X: norms and A operands
-      KMPAR_HIP(launch_prep_a(dtype, split, screen_ksteps(split, d), fa.X, fa.row_scale, fa.n, d,
-                              L.norms, L.Apre, s));
+      if (!prepared)
+        KMPAR_HIP(launch_prep_a(dtype, split, screen_ksteps(split, d), fa.X, fa.row_scale, fa.n, d,
+                                L.norms, L.Apre, s));
       Apre = L.Apre;
-    } else {
+    } else if (!prepared) {
       KMPAR_HIP(launch_rownorm(dtype, fa.X, fa.row_scale, fa.n, d, L.norms, s));
     }
     KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (m + 15) / 16, L.norms, Apre, L.B, L.ncg,
@@ -739,6 +742,32 @@ int lloyd_step(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   if ((rc = assign_pass(ctx, dtype, L, fa, k, s))) return rc;
   if (phi) KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi, s));
   KMPAR_HIP(launch_lloyd_update(dtype, X, row_scale, (int)n, d, fa.A, k, C, L.lw, s));
+  return KMPAR_OK;
+}
+
+int kmpar_lloyd(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                int64_t n, int32_t d, float* C, int32_t k, int32_t iters, int32_t* assign,
+                double* phi, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  if (iters < 0) return set_err(ctx, KMPAR_E_INVAL, "iters=%d < 0", iters);
+  if (assign && !aligned16(assign)) return set_err(ctx, KMPAR_E_INVAL, "assign misaligned");
+  if (phi && ((uintptr_t)phi & 7u)) return set_err(ctx, KMPAR_E_INVAL, "phi misaligned");
+  if (k > n) return set_err(ctx, KMPAR_E_INVAL, "k=%d > n", k);
+  AssignLayout L;
+  FoldArgs fa;
+  int rc = assign_common(ctx, KMPAR_OP_LLOYD, X, row_scale, dtype, n, d, C, k, ws, ws_bytes, &L, &fa);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  for (int it = 0; it < iters; ++it) {
+    FoldArgs fi = fa;
+    if (assign && it == iters - 1) fi.A = assign;  // the last assignment goes to the caller
+    KMPAR_HIP(launch_pad_rows(C, k, d, padded_dim(d), L.Cpad, s));
+    if ((rc = assign_pass(ctx, dtype, L, fi, k, s, it > 0))) return rc;
+    if (phi) KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi + it, s));
+    KMPAR_HIP(launch_lloyd_update(dtype, X, row_scale, (int)n, d, fi.A, k, C, L.lw, s));
+  }
   return KMPAR_OK;
 }
 

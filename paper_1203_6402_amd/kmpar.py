@@ -63,6 +63,8 @@ _lib.kmpar_assign.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32
                               _sz, _vp]
 _lib.lloyd_step.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _vp, _vp, _vp,
                             _sz, _vp]
+_lib.kmpar_lloyd.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _i32, _vp, _vp,
+                             _vp, _sz, _vp]
 _lib.kmpar_workspace_size_batched.argtypes = [_vp, _vp, _i32, ctypes.c_int, ctypes.POINTER(_sz)]
 _lib.kmpar_init_batched.argtypes = [_vp, _vp, _vp, _i32, ctypes.c_int, _u64, _vp, _sz, _vp, _vp]
 _lib.kmpar_set_option.argtypes = [_vp, ctypes.c_int, _i64]
@@ -74,7 +76,7 @@ assert _lib.kmpar_sizeof_stats() == ctypes.sizeof(Stats), "kmpar_stats layout mi
 
 EXPORTED = ["kmpar_create", "kmpar_destroy", "kmpar_strerror", "kmpar_last_error",
             "kmpar_sizeof_stats", "kmpar_max_candidates", "kmpar_workspace_size", "kmpar_init",
-            "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_profile_enable",
+            "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_lloyd", "kmpar_profile_enable",
             "kmpar_profile_read", "kmpar_workspace_size_batched", "kmpar_init_batched",
             "kmpar_set_option", "kmpar_batch_tiles"]
 OPT_RECLUSTER_PATH = 0
@@ -294,6 +296,22 @@ class Context:
                                     C.data_ptr(), k, _ptr(a), phi.data_ptr(), ws.data_ptr(),
                                     ws.numel(), _stream(stream)), "lloyd_step")
         return a, phi
+
+    def lloyd(self, X, C, iters: int, row_scale=None, want_assign=False, stream=None):
+        """kmpar_lloyd: `iters` Lloyd iterations in one call (X prepared once).
+        Updates C in place; returns (last assignment|None, phi[iters])."""
+        dt = self._x(X, row_scale)
+        n, d = X.shape
+        if C.dtype != torch.float32 or not C.is_contiguous():
+            raise ValueError("C must be contiguous float32")
+        k = C.shape[0]
+        ws = self._workspace(self.workspace_size(OP_LLOYD, n, d, k, dtype=dt), X.device)
+        a = torch.empty(n, dtype=torch.int32, device=X.device) if want_assign else None
+        phi = torch.empty(max(1, int(iters)), dtype=torch.float64, device=X.device)
+        self._check(_lib.kmpar_lloyd(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d,
+                                     C.data_ptr(), k, int(iters), _ptr(a), phi.data_ptr(),
+                                     ws.data_ptr(), ws.numel(), _stream(stream)), "kmpar_lloyd")
+        return a, phi[:max(0, int(iters))]
 
 
 class CapturedInit:

@@ -239,3 +239,40 @@ def test_recluster_paths_match_oracle(K, path):
     X = synth.heavy_tailed(30000, 42, seed=21)
     r, tr = gpu_init(c, _dev(X), 100, 200.0, 5, 4)
     compare_init(X.astype(np.float64), r, tr, 100, 200.0, 5, 4)
+
+
+@pytest.mark.parametrize("mode,dtype", [("refined", "f32"), ("plain", "f32"), ("refined", "bf16"),
+                                        ("refined", "fp8")])
+def test_lloyd_iterations_equal_single_steps(K, mode, dtype):
+    # kmpar_lloyd prepares X once for all its iterations; its centers, costs and
+    # last assignment equal those of the same number of lloyd_step calls bit
+    # for bit (each of which is checked against the oracle above).
+    c = K.Context(0, K.MODE_REFINED if mode == "refined" else K.MODE_PLAIN_FP32)
+    X = synth.gauss_mixture_sigma(30011, 48, 120, seed=9)
+    rs = None
+    if dtype == "bf16":
+        Xd = _dev(to_bf16_bits(X)).view(torch.bfloat16)
+    elif dtype == "fp8":
+        q, sc = to_e4m3(X)
+        Xd, rs = _dev(q), _dev(sc)
+    else:
+        Xd = _dev(X)
+    rng = np.random.default_rng(3)
+    C0 = X[rng.choice(len(X), 120, replace=False)].copy()
+    iters = 5
+    Cs = torch.from_numpy(C0.copy()).to("cuda:0")
+    phis = []
+    for it in range(iters):
+        a_s, p = c.lloyd_step(Xd, Cs, row_scale=rs, want_assign=True)
+        phis.append(p.item())
+    Cm = torch.from_numpy(C0.copy()).to("cuda:0")
+    a_m, phi_m = c.lloyd(Xd, Cm, iters, row_scale=rs, want_assign=True)
+    torch.cuda.synchronize()
+    assert torch.equal(Cs, Cm)
+    assert torch.equal(a_s, a_m)
+    assert phi_m.cpu().tolist() == phis
+    assert all(phis[i + 1] <= phis[i] * (1 + 1e-6) for i in range(iters - 1))
+    C1 = Cm.clone()
+    _, phi0 = c.lloyd(Xd, Cm, 0, row_scale=rs)
+    torch.cuda.synchronize()
+    assert phi0.numel() == 0 and torch.equal(C1, Cm)
