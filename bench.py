@@ -268,15 +268,20 @@ def pmc_probe(kmpar, synth, torch, args):
 
 def lloyd_probe(kmpar, synth, torch, args, iters=4):
     """Profiling workload for row a9 at full size: one REFINED init on the
-    C1 input, then `iters` Lloyd steps from its centers."""
+    C1 input, then `iters` Lloyd steps from its centers (`iters` lloyd_step
+    calls, or with --lloyd-one-call one kmpar_lloyd call)."""
     X = synth.heavy_tailed(args.n, args.d, seed=args.seed)
     Xd = torch.from_numpy(X).to("cuda:0")
     ctx = kmpar.Context(0, kmpar.MODE_REFINED)
     r = ctx.init(Xd, k=args.k, ell=args.ell_mult * args.k, rounds=args.rounds, seed=args.seed)
     C = r.centers.clone()
     torch.cuda.synchronize()
-    for _ in range(iters):
-        _, phi = ctx.lloyd_step(Xd, C)
+    if args.lloyd_one_call:
+        _, phis = ctx.lloyd(Xd, C, iters)
+        phi = phis[-1]
+    else:
+        for _ in range(iters):
+            _, phi = ctx.lloyd_step(Xd, C)
     torch.cuda.synchronize()
     log(f"lloyd probe done: {iters} steps, phi {float(phi.item()):.6g}")
 
@@ -329,6 +334,8 @@ def main():
     ap.add_argument("--recluster-path", type=int, default=0, choices=[0, 1, 2])
     ap.add_argument("--lloyd-probe", action="store_true",
                     help="profiling workload: one REFINED init then 4 Lloyd steps on the C1 input")
+    ap.add_argument("--lloyd-one-call", action="store_true",
+                    help="with --lloyd-probe: the 4 iterations as one kmpar_lloyd call")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run only a 1 GiB copy (counter calibration) and one step, for rocprofv3 --pmc")
     args = ap.parse_args()

@@ -113,6 +113,12 @@ def test_assign_cost_lloyd_validation(K):
     assert L.lloyd_step(h, 16, None, K.F32, 100, 8, 32, 101, None, None, 8192, 1 << 30, None) == K.E_INVAL
     assert L.lloyd_step(h, 16, None, K.F32, 100, 8, 32, 5, None, 12, 8192, 1 << 30, None) == K.E_INVAL
     assert L.lloyd_step(h, 16, None, K.F32, 100, 8, 32, 5, None, None, 8192, 1 << 30, None) == K.E_NODEVICE
+    assert L.kmpar_lloyd(h, 16, None, K.F32, 100, 8, 32, 5, -1, None, None, 8192, 1 << 30, None) == K.E_INVAL
+    assert L.kmpar_lloyd(h, 16, None, K.F32, 100, 8, 32, 101, 3, None, None, 8192, 1 << 30, None) == K.E_INVAL
+    assert L.kmpar_lloyd(h, 16, None, K.F32, 100, 8, 32, 5, 3, 20, None, 8192, 1 << 30, None) == K.E_INVAL
+    assert L.kmpar_lloyd(h, 16, None, K.F32, 100, 8, 32, 5, 3, None, 12, 8192, 1 << 30, None) == K.E_INVAL
+    assert L.kmpar_lloyd(h, 16, None, K.F32, 100, 8, 32, 5, 3, None, None, 8192, 10, None) == K.E_WORKSPACE
+    assert L.kmpar_lloyd(h, 16, None, K.F32, 100, 8, 32, 5, 3, None, None, 8192, 1 << 30, None) == K.E_NODEVICE
     assert L.kmpar_last_error(h).decode() != ""
 
 
