@@ -54,7 +54,7 @@ typedef enum kmpar_dtype { KMPAR_F32 = 0, KMPAR_BF16 = 1, KMPAR_FP8_E4M3 = 2 } k
  * every decision the band cannot settle recomputed in FP32 direct form, so
  * both modes return the same results bit for bit.  FP8 rows are screened in
  * kmpar_init; their assignment passes (kmpar_assign, kmpar_cost,
- * lloyd_step) use the direct form in both modes. */
+ * lloyd_step, kmpar_lloyd) use the direct form in both modes. */
 typedef enum kmpar_mode { KMPAR_MODE_PLAIN_FP32 = 0, KMPAR_MODE_REFINED = 1 } kmpar_mode;
 
 typedef enum kmpar_status {
