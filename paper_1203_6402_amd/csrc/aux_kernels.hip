@@ -710,7 +710,8 @@ hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, cons
 //  4. cluster chunks of kSegChunk sorted points, each split into fixed
 //     consecutive slices summed in FP64 in point order, the slices then
 //     added in slice order
-//  5. per cluster: sum of its chunk sums in order, divided by the count.
+//  5. per cluster: its chunk sums added in fixed consecutive slices, each in
+//     chunk order, the slices then in slice order; divided by the count.
 // Every sum runs in an order fixed by (n, d, k, assignment) alone, so the
 // update is reproducible run to run.
 __global__ __launch_bounds__(256) void k_sort_count(const int* A, int n, int k, int* bcnt,
@@ -759,34 +760,49 @@ __global__ __launch_bounds__(256) void k_scan_apply(int* a, int64_t L, const int
 }
 
 // One wave per block scatters its chunk in point order, a 64-point tile at a
-// time. The lanes holding the same key are found with one ballot per key bit
+// time; the keys of kSortAhead tiles are loaded before the first of them is
+// placed. The lanes holding the same key are found with one ballot per key bit
 // (nbits = bits of k - 1); a lane's slot is its key's cursor plus the number
 // of lower lanes with that key, and the highest such lane advances the cursor
 // by the group's size once every lane has read it.
+constexpr int kSortAhead = 16;
+static_assert(kSortChunk % (64 * kSortAhead) == 0, "sort chunk must hold whole key batches");
+
 __global__ __launch_bounds__(64) void k_sort_scatter(const int* A, int n, int k, int nbits,
                                                      const int* bbase, int nbs, int* sorted) {
   extern __shared__ int cur[];
   for (int c = threadIdx.x; c < k; c += 64) cur[c] = bbase[(int64_t)c * nbs + blockIdx.x];
   __syncthreads();
   const int base = blockIdx.x * kSortChunk;
-  for (int tile = 0; tile < kSortChunk && base + tile < n; tile += 64) {
-    const int i = base + tile + threadIdx.x;
-    const int key0 = (i < n) ? A[i] : -1;
-    const bool valid = key0 >= 0 && key0 < k;
-    const int key = valid ? key0 : 0;
-    uint64_t grp = __ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = (key >> b) & 1;
-      const uint64_t on = __ballot(valid && bit);
-      grp &= bit ? on : ~on;
+  for (int t0 = 0; t0 < kSortChunk && base + t0 < n; t0 += 64 * kSortAhead) {
+    int keys[kSortAhead];
+#pragma unroll
+    for (int u = 0; u < kSortAhead; ++u) {
+      const int i = base + t0 + u * 64 + threadIdx.x;
+      keys[u] = (i < n) ? A[i] : -1;
     }
-    const int pos0 = valid ? cur[key] : 0;
-    __syncthreads();
-    if (valid) {
-      sorted[pos0 + __popcll(grp & lanemask_lt())] = i;
-      if ((grp & lanemask_gt()) == 0) cur[key] = pos0 + __popcll(grp);
+#pragma unroll
+    for (int u = 0; u < kSortAhead; ++u) {
+      const int i0 = base + t0 + u * 64;
+      if (i0 >= n) break;
+      const int i = i0 + threadIdx.x;
+      const int key0 = keys[u];
+      const bool valid = key0 >= 0 && key0 < k;
+      const int key = valid ? key0 : 0;
+      uint64_t grp = __ballot(valid);
+      for (int b = 0; b < nbits; ++b) {
+        const bool bit = (key >> b) & 1;
+        const uint64_t on = __ballot(valid && bit);
+        grp &= bit ? on : ~on;
+      }
+      const int pos0 = valid ? cur[key] : 0;
+      __syncthreads();
+      if (valid) {
+        sorted[pos0 + __popcll(grp & lanemask_lt())] = i;
+        if ((grp & lanemask_gt()) == 0) cur[key] = pos0 + __popcll(grp);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -818,6 +834,8 @@ __global__ __launch_bounds__(1024) void k_chunk_list(const int* bbase, int nbs, 
   }
 }
 
+constexpr int kSegAhead = 16;  // rows whose loads a slice issues before adding them
+
 // Lanes per slice row: the power of two covering d, at most 64.
 __host__ __device__ __forceinline__ int seg_width(int d) {
   int w = 1;
@@ -827,7 +845,7 @@ __host__ __device__ __forceinline__ int seg_width(int d) {
 
 // Block q sums chunk q of its cluster: 256 threads form 256 / DW slices of DW
 // lanes (lane = element), slice s owns the s-th of that many consecutive
-// pieces of the chunk and adds its rows in point order, eight rows' loads
+// pieces of the chunk and adds its rows in point order, kSegAhead rows' loads
 // issued ahead of their adds; the slices' sums are then added in slice order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_seg_sum(const T* X, const float* row_scale, int d,
@@ -853,16 +871,16 @@ __global__ __launch_bounds__(256) void k_seg_sum(const T* X, const float* row_sc
     double acc = 0.0;
     if (e < d) {
       int p = a;
-      for (; p + 8 <= b; p += 8) {
-        int idx[8];
-        float v[8];
+      for (; p + kSegAhead <= b; p += kSegAhead) {
+        int idx[kSegAhead];
+        float v[kSegAhead];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) idx[u] = sorted[p + u];
+        for (int u = 0; u < kSegAhead; ++u) idx[u] = sorted[p + u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < kSegAhead; ++u)
           v[u] = Elem<T>::get(X, (int64_t)idx[u] * d + e, row_scale_of<T>(row_scale, idx[u]));
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += (double)v[u];
+        for (int u = 0; u < kSegAhead; ++u) acc += (double)v[u];
       }
       for (; p < b; ++p) {
         const int i = sorted[p];
@@ -880,25 +898,45 @@ __global__ __launch_bounds__(256) void k_seg_sum(const T* X, const float* row_sc
   }
 }
 
-__global__ __launch_bounds__(64) void k_centroid(const double* part, const int* coff,
-                                                 const int* cstart, int d, float* C) {
+// Block c divides cluster c: 256 threads form 256 / DW slices of DW lanes
+// (lane = element); slice s adds the s-th of that many consecutive pieces of
+// the cluster's chunk sums in chunk order, eight loads issued ahead of their
+// adds; the slices' sums are then added in slice order.  A cluster of a
+// million points has about 500 chunk sums, which one chain would add one
+// batch of loads at a time.
+__global__ __launch_bounds__(256) void k_centroid(const double* part, const int* coff,
+                                                  const int* cstart, int d, float* C) {
+  __shared__ double red[256];
   const int c = blockIdx.x;
   const int cnt = coff[c + 1] - coff[c];
   if (cnt == 0) return;  // an empty cluster keeps its center
   const int q0 = cstart[c], q1 = cstart[c + 1];
-  for (int e = threadIdx.x; e < d; e += 64) {
-    // chunk sums added in chunk order; eight loads issued ahead of their adds
+  const int DW = seg_width(d), NS = 256 / DW;
+  const int t = threadIdx.x, sl = t / DW, el = t % DW;
+  const int len = q1 - q0, per = (len + NS - 1) / NS;
+  const int a = q0 + min(len, sl * per), b = q0 + min(len, (sl + 1) * per);
+  for (int e0 = 0; e0 < d; e0 += DW) {
+    const int e = e0 + el;
     double s = 0.0;
-    int q = q0;
-    for (; q + 8 <= q1; q += 8) {
-      double v[8];
+    if (e < d) {
+      int q = a;
+      for (; q + 8 <= b; q += 8) {
+        double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * d + e];
+        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * d + e];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += v[u];
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+      for (; q < b; ++q) s += part[(int64_t)q * d + e];
     }
-    for (; q < q1; ++q) s += part[(int64_t)q * d + e];
-    C[(int64_t)c * d + e] = (float)(s / (double)cnt);
+    red[t] = s;
+    __syncthreads();
+    if (t < DW && e0 + t < d) {
+      double sum = 0.0;
+      for (int j = 0; j < NS; ++j) sum += red[j * DW + t];
+      C[(int64_t)c * d + e0 + t] = (float)(sum / (double)cnt);
+    }
+    __syncthreads();
   }
 }
 
@@ -931,7 +969,7 @@ hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_s
                          row_scale, d, w.sorted, w.coff, w.cstart, k, w.part);
       break;
   }
-  hipLaunchKernelGGL(k_centroid, dim3(k), dim3(64), 0, s, w.part, w.coff, w.cstart, d, C);
+  hipLaunchKernelGGL(k_centroid, dim3(k), dim3(256), 0, s, w.part, w.coff, w.cstart, d, C);
   KMPAR_RET_LAST();
 }
 
