@@ -223,11 +223,50 @@ __device__ __forceinline__ float staged_norm(const float* xr, int d) {
 }
 
 // --------------------------------------------------------------- A operands
-// The point side of the screen, built once per call: for every tile of 16
-// points and k-step s, 64 lanes x 8 bf16 in the lane order of the MFMA A
-// operand (lane l: point l%16, k = s*32 + (l/16)*8 + e), and ||x||^2 when
-// norms != nullptr.  Rows are staged through LDS as FP32 with coalesced
-// loads.  Tiles past n are zero.  Without PREP only the norms are written.
+// The A operands of a block's 64 staged rows: for every tile of 16 points and
+// k-step s, 64 lanes x 8 bf16 in the lane order of the MFMA A operand (lane
+// l: point l%16, k = s*32 + (l/16)*8 + e, split term k / d of coordinate
+// k % d).  The (term, coordinate) pair is walked forward from the lane's
+// first k rather than divided out per element.  Rows past np are zero.
+template <int SPLIT, int KS, typename T>
+__device__ __forceinline__ void write_a_operands(const T* X, int p0, int np, int d, int XS,
+                                                 const float* xs, u16x8* Apre) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int row = w * 16 + (lane % 16);
+  const bool valid = row < np;
+  int part = 0, coord = (lane / 16) * 8;
+  while (coord >= d) {
+    coord -= d;
+    ++part;
+  }
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    u16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      v[e] = (valid && part < SPLIT)
+                 ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * XS + coord]), part)
+                 : (uint16_t)0;
+      if (++coord == d) {
+        coord = 0;
+        ++part;
+      }
+    }
+    if (s + 1 < KS) {  // on to k = (s + 1) * 32 + (lane / 16) * 8
+      coord += 24;
+      while (coord >= d) {
+        coord -= d;
+        ++part;
+      }
+    }
+    Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
+  }
+}
+
+// The point side of the screen, built once per call: the A operands above
+// for every tile of 16 points, and ||x||^2 when norms != nullptr.  Rows are
+// staged through LDS as FP32 with coalesced loads.  Tiles past n are zero.
+// Without PREP only the norms are written.
 template <int SPLIT, int KS, typename T, bool PREP>
 __global__ __launch_bounds__(256) void k_prep_a(const T* X, const float* row_scale, int n, int d,
                                                 float* norms, u16x8* Apre) {
@@ -239,24 +278,7 @@ __global__ __launch_bounds__(256) void k_prep_a(const T* X, const float* row_sca
   stage_rows<T>(X, row_scale, p0, np, d, pad, ss, xs);
   __syncthreads();
   if (norms && threadIdx.x < np) norms[p0 + threadIdx.x] = staged_norm(xs + threadIdx.x * XS, d);
-  if constexpr (PREP) {
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    const int row = w * 16 + (lane % 16);
-    const bool valid = row < np;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      u16x8 v;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = s * 32 + (lane / 16) * 8 + e;
-        const int part = k / d, coord = k - part * d;
-        v[e] = (valid && part < SPLIT)
-                   ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * XS + coord]), part)
-                   : (uint16_t)0;
-      }
-      Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
-    }
-  }
+  if constexpr (PREP) write_a_operands<SPLIT, KS, T>(X, p0, np, d, XS, xs, Apre);
 }
 
 // ------------------------------------------------------------ first pass
@@ -298,24 +320,7 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
     D2[i] = acc;
     A[i] = id0;
   }
-  if constexpr (PREP) {
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    const int row = w * 16 + (lane % 16);
-    const bool valid = row < np;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      u16x8 v;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = s * 32 + (lane / 16) * 8 + e;
-        const int part = k / d, coord = k - part * d;
-        v[e] = (valid && part < SPLIT)
-                   ? a_elem<SPLIT>(op_elem<T>(X, (int64_t)(p0 + row) * d + coord, xs[row * XS + coord]), part)
-                   : (uint16_t)0;
-      }
-      Apre[((int64_t)(p0 / 16 + w) * KS + s) * 64 + lane] = v;
-    }
-  }
+  if constexpr (PREP) write_a_operands<SPLIT, KS, T>(X, p0, np, d, XS, xs, Apre);
 }
 
 // --------------------------------------------------------------- the screen
