@@ -300,8 +300,8 @@ __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
 }
 
 // The fold for rows of more than 128 padded elements (no list, no norms),
-// each row split over W = ceil(DP / 64) waves: a block of 256 W threads holds its
-// 256 points in four groups of W waves, wave s of a group keeping elements
+// each row split over W = ceil(DP / 64) waves: a block of 128 W threads holds its
+// kSplitPts = 128 points in two groups of W waves, wave s of a group keeping elements
 // [64 s, min(64 s + 64, DP)) of its 64 points' rows in registers, decoded
 // once. Per chunk of CH candidates, stage s continues the FMA chain of stage
 // s - 1 (a partial sum left in LDS, double buffered, one chunk behind) over
@@ -309,20 +309,26 @@ __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
 // step of the pipeline. The chain and the candidate order are the fold's, so
 // the result is bitwise the same. Read in halves by one thread, such rows
 // were re-read and re-decoded every 8 candidates (n = 50M rows of 256 FP8
-// elements, k = 2000: a PLAIN init took 121 s, 29 s split). Rows of 65 to
+// elements, k = 2000: a PLAIN init took 121 s, 10.6 s split). Rows of 65 to
 // 128 elements use the two-wave form below (k_fold_pair), whose registers
 // allow seven waves per SIMD (n = 16M rows of 128 BF16 elements, k = 1000: a
 // PLAIN init 1.6 s with whole rows in one thread, 0.7 s).
+constexpr int kSplitPts = 128;                 // points per block of k_fold_split
+constexpr int kSplitGroups = kSplitPts / 64;   // waves per pipeline stage
+
 template <int DP, typename T>
-__global__ __launch_bounds__(kFoldBlock * ((DP + 63) / 64)) void k_fold_split(FoldArgs a) {
+__global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) void k_fold_split(FoldArgs a) {
   constexpr int W = (DP + 63) / 64;
   constexpr int CH = 8;
   static_assert(W >= 3 && W <= 4, "rows of 129 to 256 padded elements");
-  __shared__ float part[2][CH][W - 1][kFoldBlock];  // [buffer][candidate][stage][point]
+  __shared__ float part[2][CH][W - 1][kSplitPts];  // [buffer][candidate][stage][point]
   const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int st = wv / 4;                      // pipeline stage: elements [64 st, 64 st + 64)
-  const int pl = (wv % 4) * kWave + lane;     // the point within the block
-  const int i = blockIdx.x * kFoldBlock + pl;
+  // pipeline stage: elements [64 st, 64 st + 64); the same for the whole
+  // wave, which readfirstlane tells the compiler, so that the candidate rows
+  // are read with scalar loads rather than 64 lanes' vector loads
+  const int st = __builtin_amdgcn_readfirstlane(wv / kSplitGroups);
+  const int pl = (wv % kSplitGroups) * kWave + lane;  // the point within the block
+  const int i = blockIdx.x * kSplitPts + pl;
   const bool live = i < a.n;                  // every wave takes part in the barriers
   int id0, m;
   if (a.rs) {
@@ -492,7 +498,8 @@ static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
     switch (DP) {
 #define KMPAR_SPLIT(V)                                                            \
   case V:                                                                  \
-    hipLaunchKernelGGL((k_fold_split<V, T>), grid, dim3(kFoldBlock * ((V + 63) / 64)), 0, s, a); \
+    hipLaunchKernelGGL((k_fold_split<V, T>), dim3((work + kSplitPts - 1) / kSplitPts),   \
+                       dim3(kSplitPts * ((V + 63) / 64)), 0, s, a);                         \
     return hipGetLastError();
       KMPAR_SPLIT(160) KMPAR_SPLIT(192) KMPAR_SPLIT(224) KMPAR_SPLIT(256)
 #undef KMPAR_SPLIT
