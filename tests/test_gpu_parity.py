@@ -276,3 +276,34 @@ def test_lloyd_iterations_equal_single_steps(K, mode, dtype):
     _, phi0 = c.lloyd(Xd, Cm, 0, row_scale=rs)
     torch.cuda.synchronize()
     assert phi0.numel() == 0 and torch.equal(C1, Cm)
+
+
+@pytest.mark.parametrize("dtype,d", [("f32", 200), ("bf16", 256), ("fp8", 160)])
+def test_lloyd_wide_rows_split_fold(ctx, dtype, d):
+    # Rows of 129 to 256 padded elements go through the fold that splits each
+    # row over three or four waves; one Lloyd step against the oracle: the
+    # assignment (outside the FP32 band), the cost of the input centers and
+    # the centroid update that follows the GPU's assignment.
+    X = synth.gauss_mixture_sigma(5003, d, 37, seed=13)
+    rs = None
+    if dtype == "bf16":
+        bits = to_bf16_bits(X)
+        Xd, X64 = _dev(bits).view(torch.bfloat16), decoded_fp64(bits, "bf16")
+    elif dtype == "fp8":
+        q, sc = to_e4m3(X)
+        Xd, rs, X64 = _dev(q), _dev(sc), decoded_fp64(q, "fp8", sc)
+    else:
+        Xd, X64 = _dev(X), X.astype(np.float64)
+    rng = np.random.default_rng(21)
+    C0 = X64[rng.choice(len(X64), 37, replace=False)].astype(np.float32)
+    C = torch.from_numpy(C0.copy()).to("cuda:0")
+    a, phi = ctx.lloyd_step(Xd, C, row_scale=rs, want_assign=True)
+    torch.cuda.synchronize()
+    oa, od2, osnd = O.nearest(X64, C0.astype(np.float64))
+    a = a.cpu().numpy()
+    diff = a != oa
+    gap = (osnd - od2) / np.maximum(od2, 1e-300)
+    assert np.all(gap[diff] <= O.fp32_band(d)), "argmin differs outside the band"
+    assert phi.item() == pytest.approx(O.total(od2), rel=D2_RTOL)
+    Co, _ = O.lloyd_update(X64, a, C0.astype(np.float64))
+    np.testing.assert_allclose(C.cpu().numpy(), Co.astype(np.float32), rtol=1e-6, atol=1e-6)
