@@ -61,3 +61,35 @@ def test_batched_graph_replays_match_eager(K):
         # eager work on the same context (its own workspace) between replays
         ctx.init(Y, k=30, ell=60.0, rounds=3, seed=rep)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode", ["plain", "refined"])
+def test_lloyd_graph_replays_match_eager(K, mode):
+    # kmpar_lloyd (three iterations) captured once: every replay from the same
+    # starting centers gives the eager centers, last assignment and costs,
+    # with eager library work on another context between replays.
+    m = K.MODE_REFINED if mode == "refined" else K.MODE_PLAIN_FP32
+    X = torch.from_numpy(synth.heavy_tailed(40000, 42, seed=17)).to("cuda:0")
+    Y = torch.from_numpy(synth.gauss_mixture(20000, 15, 30, 10.0, seed=2)).to("cuda:0")
+    ctx = K.Context(0, m)
+    C0 = X[torch.arange(0, 40000, 400, device="cuda:0")].clone()   # 100 centers
+    Ce = C0.clone()
+    ae, pe = ctx.lloyd(X, Ce, 3, want_assign=True)
+    torch.cuda.synchronize()
+    C = C0.clone()
+    graph, s = torch.cuda.CUDAGraph(), torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            a, p = ctx.lloyd(X, C, 3, want_assign=True, stream=s)
+    other = K.Context(0, m)
+    Cy = torch.from_numpy(synth.gauss_mixture(30, 15, 30, 10.0, seed=3)).to("cuda:0")
+    for rep in range(4):
+        C.copy_(C0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(C, Ce), rep
+        assert torch.equal(a, ae), rep
+        assert torch.equal(p, pe), rep
+        other.lloyd_step(Y, Cy)
+        torch.cuda.synchronize()
