@@ -39,3 +39,42 @@ def test_streams_interleaved_equal_single_stream(mode, nstr):
         assert st["status"] == 0, (name, st["status"])
         assert st["n_centers"] == ref[name].stats["n_centers"]
         assert torch.equal(o.centers[:st["n_centers"]], ref[name].centers), name
+
+
+@pytest.mark.parametrize("mode", ["refined", "plain"])
+def test_lloyd_streams_beside_init(mode):
+    # kmpar_lloyd on two streams (one context and workspace each) while a
+    # kmpar_init runs on a third: every Lloyd call gives its one-stream
+    # centers, costs and assignment.
+    from paper_1203_6402_amd import kmpar
+    m = kmpar.MODE_REFINED if mode == "refined" else kmpar.MODE_PLAIN_FP32
+    X = torch.from_numpy(synth.heavy_tailed(200000, 42, seed=3)).to("cuda:0")
+    Y = torch.from_numpy(synth.gauss_mixture(150000, 24, 60, 10.0, seed=4)).to("cuda:0")
+    CX = X[torch.arange(0, 200000, 2000, device="cuda:0")].clone()
+    CY = Y[torch.arange(0, 150000, 2500, device="cuda:0")].clone()
+    alone = kmpar.Context(0, m)
+    ref = {}
+    for name, D, C0 in (("X", X, CX), ("Y", Y, CY)):
+        C = C0.clone()
+        a, p = alone.lloyd(D, C, 4, want_assign=True)
+        ref[name] = (C, a, p)
+    rinit = alone.init(X, k=100, ell=200.0, rounds=5, seed=1)
+    torch.cuda.synchronize()
+    ctxs = [kmpar.Context(0, m) for _ in range(3)]
+    strs = [torch.cuda.Stream() for _ in range(3)]
+    Cs = {"X": CX.clone(), "Y": CY.clone()}
+    cur = torch.cuda.current_stream()
+    for s in strs:
+        s.wait_stream(cur)
+    oi = ctxs[2].init(X, k=100, ell=200.0, rounds=5, seed=1, stream=strs[2], check=False)
+    ax, px = ctxs[0].lloyd(X, Cs["X"], 4, want_assign=True, stream=strs[0])
+    ay, py = ctxs[1].lloyd(Y, Cs["Y"], 4, want_assign=True, stream=strs[1])
+    for s in strs:
+        cur.wait_stream(s)
+    torch.cuda.synchronize()
+    for name, a, p in (("X", ax, px), ("Y", ay, py)):
+        C, ra, rp = ref[name]
+        assert torch.equal(Cs[name], C), name
+        assert torch.equal(a, ra), name
+        assert torch.equal(p, rp), name
+    assert torch.equal(oi.centers, rinit.centers)
