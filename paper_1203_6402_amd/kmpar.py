@@ -7,6 +7,7 @@ kernels.  Importing this module fails loudly when the library is missing.
 from __future__ import annotations
 
 import ctypes
+import functools
 from types import SimpleNamespace
 import os
 from dataclasses import dataclass
@@ -103,6 +104,21 @@ def _ptr(t) -> int | None:
 def _stream(stream) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
+
+
+def _on_stream(method):
+    """Runs a call's own tensor work (output allocation, zero fills, input
+    conversions) on the stream the call is given, so that it is ordered
+    before the library's kernels there rather than racing them from the
+    current stream."""
+    @functools.wraps(method)
+    def wrapped(self, *args, **kwargs):
+        stream = kwargs.get("stream")
+        if stream is None:
+            return method(self, *args, **kwargs)
+        with torch.cuda.stream(stream):
+            return method(self, *args, **kwargs)
+    return wrapped
 
 
 def dtype_code(X: torch.Tensor, row_scale) -> int:
@@ -204,6 +220,7 @@ class Context:
         return {"launches": int(la.value), "ms": float(ms.value), "pairs": float(pr.value)}
 
     # ----------------------------------------------------------------- calls
+    @_on_stream
     def init(self, X: torch.Tensor, k: int, ell: float, rounds: int, seed: int = 0,
              row_scale: torch.Tensor | None = None, trace: bool = False,
              stream=None, check: bool = True) -> InitResult:
@@ -239,6 +256,7 @@ class Context:
             tr["center_cand"] = tr["center_cand"][:stats["n_centers"]]
         return InitResult(centers[:stats["n_centers"]], stats, tr)
 
+    @_on_stream
     def cost(self, X, C, row_scale=None, stream=None) -> torch.Tensor:
         dt = self._x(X, row_scale)
         n, d = X.shape
@@ -250,6 +268,7 @@ class Context:
                                     ws.numel(), _stream(stream)), "kmpar_cost")
         return phi
 
+    @_on_stream
     def assign(self, X, C, row_scale=None, stream=None):
         dt = self._x(X, row_scale)
         n, d = X.shape
@@ -262,6 +281,7 @@ class Context:
                                       ws.data_ptr(), ws.numel(), _stream(stream)), "kmpar_assign")
         return a, d2
 
+    @_on_stream
     def init_batched(self, Xs, ks, ells, rounds: int, seed: int = 0, row_scales=None,
                      stream=None, check: bool = True, trace: bool = False):
         """kmpar_init_batched: instance i uses Philox inst = i.  Returns
@@ -282,6 +302,7 @@ class Context:
                 t["center_cand"] = t["center_cand"][:s_["n_centers"]]
         return centers, st, traces
 
+    @_on_stream
     def lloyd_step(self, X, C, row_scale=None, want_assign=False, stream=None):
         """Updates C (k x d FP32, contiguous) in place; returns (assign|None, phi)."""
         dt = self._x(X, row_scale)
@@ -297,6 +318,7 @@ class Context:
                                     ws.numel(), _stream(stream)), "lloyd_step")
         return a, phi
 
+    @_on_stream
     def lloyd(self, X, C, iters: int, row_scale=None, want_assign=False, stream=None):
         """kmpar_lloyd: `iters` Lloyd iterations in one call (X prepared once).
         Updates C in place; returns (last assignment|None, phi[iters])."""
