@@ -78,3 +78,34 @@ def test_lloyd_streams_beside_init(mode):
         assert torch.equal(a, ra), name
         assert torch.equal(p, rp), name
     assert torch.equal(oi.centers, rinit.centers)
+
+
+def test_outputs_prepared_on_the_call_stream():
+    # With the current stream kept busy, calls on side streams must not have
+    # their outputs zeroed by work queued behind the current stream's: every
+    # init's stats record holds its own figures once all streams are done.
+    # Four side streams, so that some run on another hardware queue than the
+    # current stream (a binding that zeroed the stats on the current stream
+    # left n_centers = 0 on one of the four).
+    from paper_1203_6402_amd import kmpar
+    X = torch.from_numpy(synth.gauss_mixture(50000, 16, 40, 10.0, seed=8)).to("cuda:0")
+    ctxs = [kmpar.Context(0, kmpar.MODE_REFINED) for _ in range(4)]
+    ref = ctxs[0].init(X, k=40, ell=80.0, rounds=4, seed=6)
+    torch.cuda.synchronize()
+    a = torch.rand(2048, 2048, device="cuda:0") / 2048.0
+    b = torch.empty_like(a)
+    sides = [torch.cuda.Stream() for _ in range(4)]
+    cur = torch.cuda.current_stream()
+    for s in sides:
+        s.wait_stream(cur)
+    for _ in range(40):          # keeps the current stream busy for several ms
+        torch.mm(a, a, out=b)
+    rs = [c.init(X, k=40, ell=80.0, rounds=4, seed=6, stream=s, check=False)
+          for c, s in zip(ctxs, sides)]
+    for s in sides:
+        cur.wait_stream(s)
+    torch.cuda.synchronize()
+    for r in rs:
+        st = kmpar.parse_stats(r.stats["_raw"], 4)
+        assert st["status"] == 0 and st["n_centers"] == ref.stats["n_centers"]
+        assert torch.equal(r.centers[:st["n_centers"]], ref.centers)
