@@ -228,31 +228,40 @@ class InitResult:
     bad: dict = field(default_factory=dict)
 
 
-def kmeans_parallel_init(X, k, ell, rounds, seed, inst=0, follow=None, band=None):
-    """Algorithm 2 (Section 3.3) with k-means++ as the Step-8 recluster.
+@dataclass
+class RoundState:
+    """State of Algorithm 2 after some rounds: enough to resume the rounds
+    (the draws of round t depend only on (seed, t, point), not on history)."""
+    cand: list                        # candidate point indices, id order
+    D2: np.ndarray                    # d^2(x, C) per point
+    A: np.ndarray                     # nearest candidate id per point
+    phi: list                         # phi after the first center and each round
+    counts: list                      # |C'_t| per round (entry 0 is the first center)
+    rounds_done: int
 
-    ``follow`` (optional) is a dict with any of
-      ``rounds``: list of arrays, the point indices kept in round t=1..r,
-      ``assign``: the other side's nearest-candidate id per point,
-      ``picks``:  the other side's recluster picks (candidate ids),
-    and ``band`` the relative error band of the other side's distances
-    (default: ``fp32_band(d)``).
-    """
+
+def first_round_state(X, seed, inst=0) -> RoundState:
+    """Algorithm 2 steps 1-2: the uniform first center, D^2 against it, psi."""
     X = _f64(X)
-    n, d = X.shape
-    band = fp32_band(d) if band is None else band
-    flags = {"draw": 0, "argmin": 0, "pick": 0}
-    bad = {"draw": 0, "argmin": 0, "pick": 0}
-
+    n = X.shape[0]
     i0 = first_center(n, seed, inst)
-    cand = [i0]
     D2 = np.full(n, np.inf)
     A = np.zeros(n, np.int64)
     fold(X, X[i0:i0 + 1], 0, D2, A)
-    phi = [total(D2)]
-    counts = [1]
-    for t in range(1, rounds + 1):
-        sel, p, u = select(D2, phi[-1], ell, seed, t, inst)
+    return RoundState(cand=[i0], D2=D2, A=A, phi=[total(D2)], counts=[1], rounds_done=0)
+
+
+def run_rounds(X, state: RoundState, t_end, ell, seed, inst=0, follow=None, band=None,
+               flags=None, bad=None) -> RoundState:
+    """Algorithm 2 steps 3-6 for rounds state.rounds_done+1 .. t_end, updating
+    ``state`` in place (a checkpoint taken after any round resumes to the
+    same result).  ``follow``/``band``/``flags``/``bad`` as in
+    ``kmeans_parallel_init``."""
+    X = _f64(X)
+    n, d = X.shape
+    band = fp32_band(d) if band is None else band
+    for t in range(state.rounds_done + 1, t_end + 1):
+        sel, p, u = select(state.D2, state.phi[-1], ell, seed, t, inst)
         if follow is not None and "rounds" in follow:
             other = np.zeros(n, bool)
             other[np.asarray(follow["rounds"][t - 1], dtype=np.int64)] = True
@@ -263,12 +272,36 @@ def kmeans_parallel_init(X, k, ell, rounds, seed, inst=0, follow=None, band=None
                 bad["draw"] += int((~within).sum())
                 sel = other
         new = np.nonzero(sel)[0]
-        fold(X, X[new], len(cand), D2, A)
-        cand.extend(new.tolist())
-        counts.append(int(new.size))
-        phi.append(total(D2))
+        fold(X, X[new], len(state.cand), state.D2, state.A)
+        state.cand.extend(new.tolist())
+        state.counts.append(int(new.size))
+        state.phi.append(total(state.D2))
+        state.rounds_done = t
+    return state
 
-    cand = np.asarray(cand, dtype=np.int64)
+
+def kmeans_parallel_init(X, k, ell, rounds, seed, inst=0, follow=None, band=None, state=None):
+    """Algorithm 2 (Section 3.3) with k-means++ as the Step-8 recluster.
+
+    ``follow`` (optional) is a dict with any of
+      ``rounds``: list of arrays, the point indices kept in round t=1..r,
+      ``assign``: the other side's nearest-candidate id per point,
+      ``picks``:  the other side's recluster picks (candidate ids),
+    and ``band`` the relative error band of the other side's distances
+    (default: ``fp32_band(d)``).  ``state`` (optional) is a ``RoundState``
+    checkpoint to resume from instead of starting at step 1.
+    """
+    X = _f64(X)
+    n, d = X.shape
+    band = fp32_band(d) if band is None else band
+    flags = {"draw": 0, "argmin": 0, "pick": 0}
+    bad = {"draw": 0, "argmin": 0, "pick": 0}
+
+    st = first_round_state(X, seed, inst) if state is None else state
+    run_rounds(X, st, rounds, ell, seed, inst, follow, band, flags, bad)
+    D2, A, phi, counts = st.D2, st.A, st.phi, st.counts
+
+    cand = np.asarray(st.cand, dtype=np.int64)
     if follow is not None and "assign" in follow:
         other = np.asarray(follow["assign"], dtype=np.int64)
         diff = np.nonzero(other != A)[0]

@@ -55,7 +55,8 @@ def test_select_probabilities_and_clamp(orc):
 
 def test_select_inclusion_frequencies(orc):
     # Each point is kept independently with probability p_i (step 4):
-    # per-point frequencies over seeds, and the count's mean sum(p).
+    # per-point frequencies over seeds, and the count's mean sum(p) (Section 3.3:
+    # Algorithm 2 keeps ell points per round in expectation).
     rng = np.random.default_rng(5)
     D2 = rng.exponential(size=40) ** 2
     phi, ell, S = D2.sum(), 6.0, 4000
@@ -120,7 +121,8 @@ def test_init_invariants(orc, ell, rounds):
 
 
 def test_expected_round_size(orc):
-    # each round keeps ell points in expectation (no clamping here).
+    # Section 3.3 (Algorithm 2): each round keeps ell points in expectation (no
+    # clamping here).
     X = synth.gauss_mixture(4000, 15, 50, 1.0, seed=2)
     counts = []
     for s in range(60):
