@@ -91,7 +91,16 @@ typedef struct kmpar_stats {
   int32_t n_rescanned;                       /* REFINED: point passes the screen
                                                 could not settle (recomputed in
                                                 direct form), summed over passes  */
-  int32_t reserved[4];
+  /* Decisions taken inside the FP32 error band, band = 2 (d + 2) 2^-24 (the
+   * relative error bound of an FP32 direct-form squared distance, doubled):
+   * they may legitimately differ from exact arithmetic and are counted, not
+   * hidden (the replay of an FP64 reference accepts exactly these). */
+  int32_t flagged_draws;                     /* round draws with |u - p| <= band p,
+                                                summed over rounds (step 4)       */
+  int32_t flagged_picks;                     /* recluster picks whose u T lies
+                                                within band T of an end of the
+                                                picked interval (step 8)          */
+  int32_t reserved[2];
 } kmpar_stats;
 
 /* Optional device outputs of kmpar_init for inspection (each may be NULL). */
@@ -135,10 +144,13 @@ int kmpar_batch_tiles(const kmpar_ctx* ctx, int32_t* dtype, int32_t* dp, int32_t
  * kernel (the fold of Algorithm 2 steps 4-5 and of the assignment passes) is
  * bracketed by two hipEvents recorded on the call's stream.
  * kmpar_profile_read() synchronises on those events and reports, for kernel
- * slot `slot` (0 = direct-form fold), the number of launches, their summed
- * duration in milliseconds and their summed algorithmic work in point-center
- * pairs (n * m per launch, m read back from the device after the call);
- * reading also clears the slot.  Disabled by default; enabling adds one
+ * slot `slot` (0 = direct-form fold, 1 = REFINED screen, 2 = rescan of the
+ * points the screen listed, 3 = the grouped folds of kmpar_init_batched),
+ * the number of launches, their summed duration in milliseconds and their
+ * summed algorithmic work in point-center pairs (n * m per launch, m read
+ * back from the device after the call; 0 for slot 3, whose launches cover
+ * many instances: the caller sums n_i |C_i| from the stats); reading also
+ * clears the slot.  Disabled by default; enabling adds one
  * event pair per launch and must not be used under graph capture. */
 int kmpar_profile_enable(kmpar_ctx* ctx, int on);
 int kmpar_profile_read(kmpar_ctx* ctx, int slot, int64_t* launches, double* total_ms,

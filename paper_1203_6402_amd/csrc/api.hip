@@ -176,7 +176,10 @@ struct AssignLayout {
   size_t bytes;
 };
 
-AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op, kmpar_dtype dt) {
+// refined: the context screens assignment passes (REFINED mode), so the
+// screen's buffers (norms, list, operands) are carved as well.
+AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op, kmpar_dtype dt,
+                           bool refined) {
   const int DP = padded_dim(d);
   Carver c(ws);
   AssignLayout L{};
@@ -195,18 +198,24 @@ AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op, kmpar
     L.lw.coff = c.take<int>(k + 1);
     L.lw.part = c.take<double>(((n + kSegChunk - 1) / kSegChunk + k) * (int64_t)d);
   }
-  const int tiles = (k + 15) / 16;
-  L.norms = c.take<float>(n);
-  L.list = c.take<int>(n);
-  L.list_len = c.take<int>(4);
-  L.rescan_part = c.take<int2>((size_t)kRescanMaxItems * kRescanPts);
-  L.B = c.take<char>(screen_b_bytes(tiles, d));
-  L.ncg = c.take<float>((size_t)tiles * 16);
-  L.scg = c.take<float>((size_t)tiles * 16);
-  L.Apre = c.take<char>(a_bytes(dt, false, n, d));
+  if (refined && screen_supported(dt, false, d)) {
+    const int tiles = (k + 15) / 16;
+    L.norms = c.take<float>(n);
+    L.list = c.take<int>(n);
+    L.list_len = c.take<int>(4);
+    L.rescan_part = c.take<int2>((size_t)kRescanMaxItems * kRescanPts);
+    L.B = c.take<char>(screen_b_bytes(tiles, d));
+    L.ncg = c.take<float>((size_t)tiles * 16);
+    L.scg = c.take<float>((size_t)tiles * 16);
+    L.Apre = c.take<char>(a_bytes(dt, false, n, d));
+  }
   L.bytes = c.off;
   return L;
 }
+
+// Whether assignment passes of this context screen (sizes its workspace
+// for it); a null context sizes for the screen.
+bool ctx_refined(const kmpar_ctx* ctx) { return !ctx || ctx->mode == KMPAR_MODE_REFINED; }
 
 int check_common(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dt, int64_t n,
                  int32_t d) {
@@ -286,7 +295,7 @@ hipError_t timed(kmpar_ctx* ctx, int slot, int64_t npts, const int* npts_dev, co
 }
 
 // Slots of kmpar_profile_read.
-enum { kSlotDirect = 0, kSlotScreen = 1, kSlotRescan = 2 };
+enum { kSlotDirect = 0, kSlotScreen = 1, kSlotRescan = 2, kSlotBatchFold = 3 };
 
 hipError_t timed_fold(kmpar_ctx* ctx, int slot, kmpar_dtype dt, int DP, const FoldArgs& fa,
                       hipStream_t s) {
@@ -348,6 +357,11 @@ int device_ready(kmpar_ctx* ctx) {
   if (ctx->device < 0) return set_err(ctx, KMPAR_E_NODEVICE, "context has no device");
   return KMPAR_OK;
 }
+
+// kmpar_cost's launch sequence on the workspace ws (validated by the caller).
+int cost_run(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype, int64_t n,
+             int32_t d, const float* C, int32_t m, double* phi, void* ws, size_t ws_bytes,
+             void* stream);
 
 }  // namespace
 
@@ -506,7 +520,7 @@ int kmpar_workspace_size(const kmpar_ctx* cctx, kmpar_op op, int64_t n, int32_t 
     case KMPAR_OP_COST:
     case KMPAR_OP_ASSIGN:
     case KMPAR_OP_LLOYD:
-      *bytes_out = assign_layout(nullptr, n, d, k, op, dtype).bytes;
+      *bytes_out = assign_layout(nullptr, n, d, k, op, dtype, ctx_refined(ctx)).bytes;
       return KMPAR_OK;
   }
   return set_err(ctx, KMPAR_E_INVAL, "unknown op");
@@ -589,8 +603,8 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   // Steps 3-6: rounds.
   fa.first = 0;
   for (int t = 1; t <= rounds; ++t) {
-    KMPAR_HIP(launch_draw(L.D2, N, &st->phi[t - 1], ell, seed, t, inst, L.cnt, L.keep, L.scan_total, L.rs,
-                          cap_round, L.cand_point, st, s));
+    KMPAR_HIP(launch_draw(L.D2, N, &st->phi[t - 1], ell, seed, t, inst, fp32_flag_band(d), L.cnt,
+                          L.keep, L.scan_total, L.rs, cap_round, L.cand_point, st, s));
     KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, t, cap_round, L.Call,
                             L.CallT, capT, s));
     fa.rs = L.rs + t;
@@ -605,7 +619,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   if (refined) KMPAR_HIP(launch_list_reset(L.list_len, st, s));
   KMPAR_HIP(launch_finish_rounds(L.rs, rounds, st, s));
   // Step 7: weights.
-  KMPAR_HIP(launch_hist(L.A, N, L.w, capT, s));
+  KMPAR_HIP(launch_hist(L.A, N, L.w, capT, ctx->num_cu, s));
   // Step 8: weighted k-means++.
   int* picks = (trace && trace->center_cand) ? trace->center_cand : L.picks;
   // Automatic: several workgroups (measured faster for a single instance at
@@ -615,10 +629,10 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
       !recl_ok || (ctx->recl_path == 1 && recluster_block_lds(capT, k) <= kReclBlockLdsMax);
   if (one_wg) {
     KMPAR_HIP(launch_recluster_block(L.CallT, capT, d, L.w, L.rs + rounds + 1, k, seed, inst,
-                                     picks, centers, st, s));
+                                     picks, centers, st, fp32_flag_band(d), s));
   } else {
     KMPAR_HIP(launch_recluster(L.Call, DP, d, L.w, L.rs + rounds + 1, k, seed, inst, recl,
-                               L.udraw, L.rpart, L.prow, picks, centers, st, s));
+                               L.udraw, L.rpart, L.prow, picks, centers, st, fp32_flag_band(d), s));
   }
   if (trace) {
     if (trace->cand_point) KMPAR_HIP(launch_copy_i32(L.cand_point, trace->cand_point, capT, s));
@@ -643,7 +657,7 @@ static int assign_common(kmpar_ctx* ctx, kmpar_op op, const void* X, const float
   if (ws_bytes < need)
     return set_err(ctx, KMPAR_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   if ((rc = device_ready(ctx))) return rc;
-  *L = assign_layout(ws, n, d, m, op, dtype);
+  *L = assign_layout(ws, n, d, m, op, dtype, ctx_refined(ctx));
   *fa = FoldArgs{};
   fa->X = X;
   fa->row_scale = row_scale;
@@ -690,6 +704,17 @@ int kmpar_cost(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
                void* stream) {
   if (!ctx) return KMPAR_E_INVAL;
   if (!phi || ((uintptr_t)phi & 7u)) return set_err(ctx, KMPAR_E_INVAL, "phi NULL/misaligned");
+  return cost_run(ctx, X, row_scale, dtype, n, d, C, m, phi, ws, ws_bytes, stream);
+}
+
+
+}  // extern "C"
+
+namespace {
+
+int cost_run(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype, int64_t n,
+             int32_t d, const float* C, int32_t m, double* phi, void* ws, size_t ws_bytes,
+             void* stream) {
   AssignLayout L;
   FoldArgs fa;
   int rc = assign_common(ctx, KMPAR_OP_COST, X, row_scale, dtype, n, d, C, m, ws, ws_bytes, &L, &fa);
@@ -702,6 +727,10 @@ int kmpar_cost(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi, s));
   return KMPAR_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int kmpar_assign(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
                  int64_t n, int32_t d, const float* C, int32_t m, int32_t* assign, float* d2,
@@ -815,8 +844,12 @@ int kmpar_init_batched(kmpar_ctx* ctx, const kmpar_instance* inst_host,
   if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
   if (traces_dev && ((uintptr_t)traces_dev & 7u))
     return set_err(ctx, KMPAR_E_INVAL, "traces_dev misaligned");
+  hipStream_t s = (hipStream_t)stream;
+  const LaunchTimer fold_timer = [&](const std::function<hipError_t()>& launch) {
+    return timed(ctx, kSlotBatchFold, 0, nullptr, nullptr, 0, s, launch);
+  };
   KMPAR_HIP(launch_batched(dtype, inst_host, inst_dev, count, inst_host[0].rounds, seed, ws,
-                           traces_dev, &ctx->tuner, (hipStream_t)stream));
+                           traces_dev, &ctx->tuner, ctx->prof ? &fold_timer : nullptr, s));
   return KMPAR_OK;
 }
 

@@ -27,6 +27,8 @@ __global__ void k_first(int n, uint64_t seed, uint64_t inst, int* cand_point, in
   st->round_count[0] = 1;
   st->status = KMPAR_OK;
   st->n_rescanned = 0;
+  st->flagged_draws = 0;
+  st->flagged_picks = 0;
 }
 
 hipError_t launch_first(int n, uint64_t seed, uint64_t inst, int* cand_point, int* rs,
@@ -136,12 +138,17 @@ __device__ __forceinline__ uint64_t lanemask_gt() {
 
 // Algorithm 2 step 4: point i is kept in round t iff u < p with
 // p = min(1, ell * D2_i / phi) and u = U(seed, ROUND, (i, t, inst)).
+// *flag is set when |u - p| <= band * p: a draw that D^2 within its FP32
+// error band could have decided the other way.
 __device__ __forceinline__ int keep_point(const float* D2, int i, double phi, double ell,
-                                          uint64_t seed, int t, uint64_t inst) {
+                                          uint64_t seed, int t, uint64_t inst, double band,
+                                          int* flag) {
+  *flag = 0;
   if (!(phi > 0.0)) return 0;
   double p = ell * (double)D2[i] / phi;
   if (p > 1.0) p = 1.0;
   const double u = philox_uniform(seed, kTagRound, (uint64_t)i, (uint64_t)t, inst);
+  *flag = (p > 0.0 && fabs(u - p) <= band * p) ? 1 : 0;
   return u < p ? 1 : 0;
 }
 
@@ -152,22 +159,27 @@ constexpr int kDrawMasks = kDrawChunk / 64;
 // 64 points, so the write pass needs neither D^2 nor the draws again.
 __global__ __launch_bounds__(256) void k_draw_count(const float* D2, int n, const double* phi,
                                                     double ell, uint64_t seed, int t,
-                                                    uint64_t inst, int* cnt, uint64_t* keep) {
+                                                    uint64_t inst, double band, int* cnt,
+                                                    uint64_t* keep, kmpar_stats* st) {
   __shared__ int sh[8];
   const double ph = *phi;
   const int base = blockIdx.x * kDrawChunk;
   const int w = threadIdx.x / kWave;
-  int c = 0;
+  int c = 0, nf = 0;
 #pragma unroll
   for (int r = 0; r < kDrawChunk / 256; ++r) {
     const int i = base + r * 256 + threadIdx.x;
-    const int kp = (i < n) ? keep_point(D2, i, ph, ell, seed, t, inst) : 0;
+    int fl = 0;
+    const int kp = (i < n) ? keep_point(D2, i, ph, ell, seed, t, inst, band, &fl) : 0;
     c += kp;
+    nf += fl;
     const uint64_t b = __ballot(kp);
     if (threadIdx.x % kWave == 0) keep[(int64_t)blockIdx.x * kDrawMasks + r * 4 + w] = b;
   }
   const int tot = block_sum<int, 256>(c, sh);
   if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+  const int ftot = block_sum<int, 256>(nf, sh);
+  if (threadIdx.x == 0 && ftot) atomicAdd(&st->flagged_draws, ftot);
 }
 
 // In-place exclusive scan of a[0..L) by one block; *total = sum.
@@ -227,11 +239,11 @@ __global__ __launch_bounds__(256) void k_draw_write(const uint64_t* keep, const 
 }
 
 hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, uint64_t seed, int t,
-                       uint64_t inst, int* cnt, uint64_t* keep, int* scan_total, int* rs,
-                       int cap_round, int* cand_point, kmpar_stats* st, hipStream_t s) {
+                       uint64_t inst, double band, int* cnt, uint64_t* keep, int* scan_total,
+                       int* rs, int cap_round, int* cand_point, kmpar_stats* st, hipStream_t s) {
   const int nb = (n + kDrawChunk - 1) / kDrawChunk;
-  hipLaunchKernelGGL(k_draw_count, dim3(nb), dim3(256), 0, s, D2, n, phi, ell, seed, t, inst, cnt,
-                     keep);
+  hipLaunchKernelGGL(k_draw_count, dim3(nb), dim3(256), 0, s, D2, n, phi, ell, seed, t, inst, band,
+                     cnt, keep, st);
   hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, cnt, nb, scan_total);
   hipLaunchKernelGGL(k_round_commit, dim3(1), dim3(64), 0, s, scan_total, rs, t, cap_round, st);
   hipLaunchKernelGGL(k_draw_write, dim3(nb), dim3(256), 0, s, keep, cnt, rs, t, cap_round,
@@ -272,12 +284,32 @@ hipError_t launch_copy_i32(const int* src, int* dst, int64_t count, hipStream_t 
 
 // ------------------------------------------------------------- Step 7 weights
 // w_c = |{i : A_i = c}|, counted in LDS per block, then merged with integer
-// atomics (exact, so the result does not depend on their order).
+// atomics (exact, so the result does not depend on their order).  A is read
+// four values per 16-byte load with four loads in flight per thread.
 __global__ __launch_bounds__(256) void k_hist_lds(const int* A, int n, int* w, int nbins) {
   extern __shared__ int h[];
   for (int b = threadIdx.x; b < nbins; b += 256) h[b] = 0;
   __syncthreads();
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+  const int n4 = n / 4;
+  const int4* A4 = reinterpret_cast<const int4*>(A);
+  const int stride = gridDim.x * 256;
+  constexpr int U = 4;
+  for (int i0 = blockIdx.x * 256 + threadIdx.x; i0 < n4; i0 += U * stride) {
+    int4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * stride;
+      v[u] = idx < n4 ? A4[idx] : make_int4(-1, -1, -1, -1);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int a[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (a[q] >= 0 && a[q] < nbins) atomicAdd(&h[a[q]], 1);
+    }
+  }
+  for (int i = 4 * n4 + blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const int a = A[i];
     if (a >= 0 && a < nbins) atomicAdd(&h[a], 1);
   }
@@ -293,16 +325,22 @@ __global__ __launch_bounds__(256) void k_hist_global(const int* A, int n, int* w
   }
 }
 
-constexpr int kLdsBudget = 64 * 1024;
+// A block's LDS histogram may take up to this much of a CU's 160 KB (one
+// block per CU above 80 KB, two below).
+constexpr int kLdsBudget = 156 * 1024;
 
-hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s) {
+hipError_t launch_hist(const int* A, int n, int* w, int nbins, int num_cu, hipStream_t s) {
   hipError_t e = launch_fill_i32(w, 0, nbins, s);
   if (e != hipSuccess) return e;
-  const int blocks = 512;
-  if ((size_t)nbins * 4 <= (size_t)kLdsBudget) {
-    hipLaunchKernelGGL(k_hist_lds, dim3(blocks), dim3(256), (size_t)nbins * 4, s, A, n, w, nbins);
+  const size_t lds = (size_t)nbins * 4;
+  if (lds <= (size_t)kLdsBudget) {
+    const int blocks = std::max(1, num_cu) * (lds <= 80 * 1024 ? 2 : 1);
+    e = hipFuncSetAttribute((const void*)k_hist_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hist_lds, dim3(blocks), dim3(256), lds, s, A, n, w, nbins);
   } else {
-    hipLaunchKernelGGL(k_hist_global, dim3(blocks), dim3(256), 0, s, A, n, w, nbins);
+    hipLaunchKernelGGL(k_hist_global, dim3(512), dim3(256), 0, s, A, n, w, nbins);
   }
   KMPAR_RET_LAST();
 }
@@ -378,6 +416,7 @@ struct ReclArgs {
   int* picks;          // [k] output: candidate ids
   float* centers;      // [k][d] output rows
   kmpar_stats* st;
+  double band;         // picks with u*T within band*T of an interval end are flagged
 };
 
 // The recluster's draws, one thread each, ahead of the sequential picks.
@@ -394,8 +433,8 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
   float* lds = reinterpret_cast<float*>(lds4);
   __shared__ double wtot[kReclBlock / kWave];
   __shared__ double gpart[kReclMaxBlocks];
-  __shared__ double sh_u, sh_base, sh_top;
-  __shared__ int sh_pick, sh_owner, sh_failed, sh_stop;
+  __shared__ double sh_u, sh_base, sh_top, sh_T, sh_plo, sh_phi;
+  __shared__ int sh_pick, sh_owner, sh_failed, sh_stop, sh_pflag;
   constexpr int NW = kReclBlock / kWave;
   const int b = blockIdx.x, tid = threadIdx.x, DP = a.DP, d = a.d;
   const int lane = tid % kWave, wv = tid / kWave;
@@ -541,13 +580,20 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
         sh_base = lo_b;
         sh_top = hi_b;
         sh_u = thr;
+        sh_T = T;
         sh_pick = 0x7fffffff;
+        sh_pflag = 0;
       }
     }
     __syncthreads();
     if (sh_stop) break;
     if (sh_owner == b) {
       const double thr = sh_u, base = sh_base;
+      // The picked interval [lo, hi) of the running sums (recorded by the
+      // thread that found the pick) decides whether u*T lay within the band
+      // of one of its ends; a pick made by a rounding fallback always is.
+      int my_pick = -1;
+      double my_lo = 0.0, my_hi = 0.0;
       if (isinf(base)) {
         // rounding fallback: the last candidate with positive mass
         if (tid == 0) {
@@ -558,6 +604,7 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
               break;
             }
           }
+          sh_pflag = 1;
         }
       } else {
         const double b0 = base + ex;
@@ -567,16 +614,28 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
           int pick = -1, last = -1;
           for (int j = rlo; j < rhi; ++j) {
             const double g = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+            const double before = run;
             run += g;
             if (g > 0.0) last = j;
             if (g > 0.0 && run > thr) {
               pick = j;
+              my_lo = before;
+              my_hi = run;
               break;
             }
           }
-          if (pick < 0) pick = last;
+          if (pick < 0) {  // u*T at the end of this run by rounding
+            pick = last;
+            my_lo = my_hi = thr;
+          }
+          my_pick = pick;
           if (pick >= 0) atomicMin(&sh_pick, pick);
         }
+      }
+      __syncthreads();
+      if (my_pick >= 0 && my_pick == sh_pick) {
+        sh_plo = my_lo;
+        sh_phi = my_hi;
       }
       __syncthreads();
       if (sh_pick == 0x7fffffff) {
@@ -587,16 +646,26 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
           int last = -1;
           for (int j = 0; j < ns; ++j) {
             const double g = (s == 0) ? (double)wl[j] : (double)wl[j] * (double)E[j];
+            const double before = run;
             run += g;
             if (g > 0.0) last = j;
             if (g > 0.0 && run > thr) {
               sh_pick = j;
+              sh_plo = before;
+              sh_phi = run;
               break;
             }
           }
-          if (sh_pick == 0x7fffffff) sh_pick = last;
+          if (sh_pick == 0x7fffffff) {
+            sh_pick = last;
+            sh_pflag = 1;
+          }
         }
         __syncthreads();
+      }
+      if (tid == 0) {
+        const double bt = a.band * sh_T;
+        if (sh_pflag || thr - sh_plo <= bt || sh_phi - thr <= bt) atomicAdd(&a.st->flagged_picks, 1);
       }
       const int jl = sh_pick;
       // hop 2 of round s: publish the row, then the outputs
@@ -621,22 +690,24 @@ __global__ __launch_bounds__(1024) void k_recluster_block(const float* CallT, in
                                                           const int* w, const int* rs_end, int k,
                                                           uint64_t seed, uint64_t inst, int* picks,
                                                           float* centers, kmpar_stats* st,
-                                                          int cap_lds) {
+                                                          int cap_lds, double band) {
   extern __shared__ float lds[];
-  recluster_block<1024>(CallT, ldT, d, w, *rs_end, k, seed, inst, picks, centers, st, lds, cap_lds);
+  recluster_block<1024>(CallT, ldT, d, w, *rs_end, k, seed, inst, picks, centers, st, lds, cap_lds,
+                        band);
 }
 
 size_t recluster_block_lds(int capT, int k) { return (size_t)capT * 8 + (size_t)k * 8; }
 
 hipError_t launch_recluster_block(const float* CallT, int capT, int d, const int* w,
                                   const int* rs_end, int k, uint64_t seed, uint64_t inst,
-                                  int* picks, float* centers, kmpar_stats* st, hipStream_t s) {
+                                  int* picks, float* centers, kmpar_stats* st, double band,
+                                  hipStream_t s) {
   const size_t lds = recluster_block_lds(capT, k);
   hipError_t e = hipFuncSetAttribute((const void*)k_recluster_block,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_recluster_block, dim3(1), dim3(1024), lds, s, CallT, capT, d, w, rs_end, k,
-                     seed, inst, picks, centers, st, capT);
+                     seed, inst, picks, centers, st, capT, band);
   KMPAR_RET_LAST();
 }
 
@@ -666,7 +737,7 @@ bool recluster_plan(int capT, int DP, int num_cu, bool global_rows, ReclPlan* p)
 hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, const int* rs_end,
                             int k, uint64_t seed, uint64_t inst, const ReclPlan& plan,
                             double* udraw, double* part, float* prow, int* picks,
-                            float* centers, kmpar_stats* st, hipStream_t s) {
+                            float* centers, kmpar_stats* st, double band, hipStream_t s) {
   const int G = plan.G;
   hipLaunchKernelGGL(k_recl_draws, dim3((k + 255) / 256), dim3(256), 0, s, seed, inst, k, udraw);
   // every slot starts empty (all-ones); fill kernels, not memsets, so the
@@ -691,6 +762,7 @@ hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, cons
   a.picks = picks;
   a.centers = centers;
   a.st = st;
+  a.band = band;
   const void* fn = plan.lds_rows ? (const void*)k_recluster_grid<true>
                                  : (const void*)k_recluster_grid<false>;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds);

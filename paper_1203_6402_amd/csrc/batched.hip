@@ -192,6 +192,8 @@ __global__ void kb_first(const kmpar_instance* inst, int count, int rounds, Plan
   st->round_count[0] = 1;
   st->status = KMPAR_OK;
   st->n_rescanned = 0;
+  st->flagged_draws = 0;
+  st->flagged_picks = 0;
 }
 
 // ------------------------------------------------------------------ gather
@@ -434,12 +436,17 @@ __global__ __launch_bounds__(256) void kb_phi_final(const kmpar_instance* inst, 
 }
 
 // -------------------------------------------------------------------- draw
+// Round t's draw of point i (Algorithm 2 step 4); *flag as in the
+// single-instance draw: |u - p| <= band * p.
 __device__ __forceinline__ int bkeep(const float* D2, int i, double phi, double ell, uint64_t seed,
-                                     int t, uint64_t inst) {
+                                     int t, uint64_t inst, double band = 0.0,
+                                     int* flag = nullptr) {
+  if (flag) *flag = 0;
   if (!(phi > 0.0)) return 0;
   double pr = ell * (double)D2[i] / phi;
   if (pr > 1.0) pr = 1.0;
   const double u = philox_uniform(seed, kTagRound, (uint64_t)i, (uint64_t)t, inst);
+  if (flag) *flag = (pr > 0.0 && fabs(u - pr) <= band * pr) ? 1 : 0;
   return u < pr ? 1 : 0;
 }
 
@@ -451,14 +458,22 @@ __global__ __launch_bounds__(256) void kb_draw_count(const kmpar_instance* inst,
   const int chunk = blockIdx.x - p.pre_draw[ii];
   const int n = (int)v.I->n;
   const float* D2 = v.at<float>(v.r.D2);
-  const double phi = v.at<kmpar_stats>(v.r.st)->phi[t - 1];
-  int c = 0;
+  kmpar_stats* st = v.at<kmpar_stats>(v.r.st);
+  const double phi = st->phi[t - 1];
+  const double band = fp32_flag_band(v.I->d);
+  int c = 0, nf = 0;
   for (int r = 0; r < kDrawChunk / 256; ++r) {
     const int i = chunk * kDrawChunk + r * 256 + threadIdx.x;
-    if (i < n) c += bkeep(D2, i, phi, v.I->ell, seed, t, (uint64_t)ii);
+    if (i < n) {
+      int fl = 0;
+      c += bkeep(D2, i, phi, v.I->ell, seed, t, (uint64_t)ii, band, &fl);
+      nf += fl;
+    }
   }
   const int tot = block_sum<int, 256>(c, sh);
   if (threadIdx.x == 0) v.at<int>(v.r.cnt)[chunk] = tot;
+  const int ftot = block_sum<int, 256>(nf, sh);
+  if (threadIdx.x == 0 && ftot) atomicAdd(&st->flagged_draws, ftot);
 }
 
 // Per instance: exclusive scan of its chunk counts and commit of round t.
@@ -551,7 +566,7 @@ __global__ __launch_bounds__(kBRecl) void kb_recluster(const kmpar_instance* ins
   recluster_block<kBRecl>(v.at<const float>(v.r.CallT), (int)v.r.capT, d, v.at<const int>(v.r.w),
                           v.at<int>(v.r.rs)[rounds + 1], v.I->k, seed, (uint64_t)ii,
                           v.at<int>(v.r.picks), v.I->centers, v.at<kmpar_stats>(v.r.st), lds,
-                          cap_lds);
+                          cap_lds, fp32_flag_band(d));
 }
 
 // Optional per-instance trace copies (one workgroup per instance).
@@ -721,7 +736,11 @@ static hipError_t tune_bfold(int DP, const kmpar_instance* inst, int rounds, con
 template <typename T>
 static hipError_t run_batched_t(kmpar_dtype dt, const kmpar_instance* ih, const kmpar_instance* idev,
                                 int count, int rounds, uint64_t seed, void* ws,
-                                const kmpar_trace* tr, BatchTuner* tuner, hipStream_t s) {
+                                const kmpar_trace* tr, BatchTuner* tuner,
+                                const LaunchTimer* fold_timer, hipStream_t s) {
+  auto fold = [&](const std::function<hipError_t()>& launch) {
+    return fold_timer ? (*fold_timer)(launch) : launch();
+  };
   int dps[kBatchMaxGroups];
   int G = 0;
   (void)batched_workspace(ih, count, rounds, &G, dps);
@@ -764,7 +783,9 @@ static hipError_t run_batched_t(kmpar_dtype dt, const kmpar_instance* ih, const 
   hipLaunchKernelGGL(kb_first, inst_threads, dim3(256), 0, s, idev, count, rounds, p, seed);
   hipLaunchKernelGGL(kb_gather<T>, per_inst, dim3(256), 0, s, idev, rounds, p, 0);
   for (int g = 0; g < G; ++g) {
-    hipError_t e = launch_bfold_dp<T>(dps[g], gcb[g], idev, rounds, p, g, 0, 1, gtiles[g], s);
+    hipError_t e = fold([&] {
+      return launch_bfold_dp<T>(dps[g], gcb[g], idev, rounds, p, g, 0, 1, gtiles[g], s);
+    });
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(kb_phi_partial, dim3((unsigned)phi_blocks), dim3(256), 0, s, idev, count,
@@ -783,7 +804,9 @@ static hipError_t run_batched_t(kmpar_dtype dt, const kmpar_instance* ih, const 
         e = tune_bfold<T>(dps[g], idev, rounds, p, g, t, gtiles[g], s, &gcb[g]);
         if (e == hipSuccess) tuner->cb[BatchTuner::key((int)dt, dps[g])] = gcb[g];
       } else {
-        e = launch_bfold_dp<T>(dps[g], gcb[g], idev, rounds, p, g, t, 0, gtiles[g], s);
+        e = fold([&] {
+          return launch_bfold_dp<T>(dps[g], gcb[g], idev, rounds, p, g, t, 0, gtiles[g], s);
+        });
       }
       if (e != hipSuccess) return e;
     }
@@ -806,11 +829,14 @@ static hipError_t run_batched_t(kmpar_dtype dt, const kmpar_instance* ih, const 
 
 hipError_t launch_batched(kmpar_dtype dt, const kmpar_instance* ih, const kmpar_instance* idev,
                           int count, int rounds, uint64_t seed, void* ws, const kmpar_trace* tr,
-                          BatchTuner* tuner, hipStream_t s) {
+                          BatchTuner* tuner, const LaunchTimer* fold_timer, hipStream_t s) {
   switch (dt) {
-    case KMPAR_F32: return run_batched_t<float>(dt, ih, idev, count, rounds, seed, ws, tr, tuner, s);
-    case KMPAR_BF16: return run_batched_t<bf16_t>(dt, ih, idev, count, rounds, seed, ws, tr, tuner, s);
-    case KMPAR_FP8_E4M3: return run_batched_t<fp8_t>(dt, ih, idev, count, rounds, seed, ws, tr, tuner, s);
+    case KMPAR_F32:
+      return run_batched_t<float>(dt, ih, idev, count, rounds, seed, ws, tr, tuner, fold_timer, s);
+    case KMPAR_BF16:
+      return run_batched_t<bf16_t>(dt, ih, idev, count, rounds, seed, ws, tr, tuner, fold_timer, s);
+    case KMPAR_FP8_E4M3:
+      return run_batched_t<fp8_t>(dt, ih, idev, count, rounds, seed, ws, tr, tuner, fold_timer, s);
   }
   return hipErrorInvalidValue;
 }

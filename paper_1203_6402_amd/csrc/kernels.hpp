@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <map>
 
 #include "../../include/kmpar.h"
@@ -148,18 +149,27 @@ hipError_t launch_gather(kmpar_dtype dt, const void* X, const float* row_scale, 
                          const int* cand_point, const int* rs, int t, int cap_round, float* Call,
                          float* CallT, int ldT, hipStream_t s);
 hipError_t launch_phi(const float* D2, int n, double* part, double* out, hipStream_t s);
+// Round t's Bernoulli draws (Algorithm 2 step 4) and their ordered
+// compaction; draws within `band` (relative to p) are counted in
+// st->flagged_draws.
 hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, uint64_t seed, int t,
-                       uint64_t inst, int* cnt, uint64_t* keep, int* scan_total, int* rs,
-                       int cap_round, int* cand_point, kmpar_stats* st, hipStream_t s);
+                       uint64_t inst, double band, int* cnt, uint64_t* keep, int* scan_total,
+                       int* rs, int cap_round, int* cand_point, kmpar_stats* st, hipStream_t s);
+// Relative error band of an FP32 direct-form squared distance over d
+// coordinates, doubled: 2 (d + 2) 2^-24.
+__host__ __device__ inline double fp32_flag_band(int d) { return 2.0 * (d + 2) * 0x1.0p-24; }
 hipError_t launch_finish_rounds(const int* rs, int rounds, kmpar_stats* st, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s);
-hipError_t launch_hist(const int* A, int n, int* w, int nbins, hipStream_t s);
+// Step-7 weights w[0 .. nbins) of the assignment A (an LDS histogram per
+// block while nbins fits a CU's LDS, else global atomics).
+hipError_t launch_hist(const int* A, int n, int* w, int nbins, int num_cu, hipStream_t s);
 // Step-8 recluster in one workgroup when E and the nearest-pick ids fit LDS.
 constexpr size_t kReclBlockLdsMax = 140 * 1024;
 size_t recluster_block_lds(int capT, int k);
 hipError_t launch_recluster_block(const float* CallT, int capT, int d, const int* w,
                                   const int* rs_end, int k, uint64_t seed, uint64_t inst,
-                                  int* picks, float* centers, kmpar_stats* st, hipStream_t s);
+                                  int* picks, float* centers, kmpar_stats* st, double band,
+                                  hipStream_t s);
 // Step-8 recluster over G workgroups (see aux_kernels.hip).
 // Grid of the multi-workgroup recluster for up to capT candidates of DP
 // floats on num_cu CUs: G blocks of at most `fit` candidates each, rows in
@@ -176,7 +186,7 @@ bool recluster_plan(int capT, int DP, int num_cu, bool global_rows, ReclPlan* p)
 hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, const int* rs_end,
                             int k, uint64_t seed, uint64_t inst, const ReclPlan& plan,
                             double* udraw, double* part, float* prow, int* picks,
-                            float* centers, kmpar_stats* st, hipStream_t s);
+                            float* centers, kmpar_stats* st, double band, hipStream_t s);
 hipError_t launch_pad_rows(const float* C, int m, int d, int DP, float* Cpad, hipStream_t s);
 hipError_t launch_copy_i32(const int* src, int* dst, int64_t count, hipStream_t s);
 
@@ -203,8 +213,12 @@ struct BatchTuner {
   std::map<int, int> cb;  // key(dtype, DP) -> candidates per step
   static int key(int dt, int DP) { return dt * 4096 + DP; }
 };
+// Runs one launch, bracketed by the caller's timing when it profiles.
+using LaunchTimer = std::function<hipError_t(const std::function<hipError_t()>&)>;
+// fold_timer (nullable) brackets every grouped fold launch except the
+// tuner's trial launches.
 hipError_t launch_batched(kmpar_dtype dt, const kmpar_instance* ih, const kmpar_instance* idev,
                           int count, int rounds, uint64_t seed, void* ws, const kmpar_trace* tr,
-                          BatchTuner* tuner, hipStream_t s);
+                          BatchTuner* tuner, const LaunchTimer* fold_timer, hipStream_t s);
 
 }  // namespace kmpar

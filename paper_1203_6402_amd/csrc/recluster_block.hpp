@@ -48,12 +48,13 @@ template <int BS>
 __device__ void recluster_block(const float* __restrict__ CallT, int ldT, int d,
                                 const int* __restrict__ w, int m, int k, uint64_t seed,
                                 uint64_t inst, int* picks, float* centers, kmpar_stats* st,
-                                float* lds, int cap_lds) {
+                                float* lds, int cap_lds, double band) {
   __shared__ double shd[BS / kWave + 1];
   __shared__ long long shl[BS / kWave + 1];
   __shared__ double bounds[BS + 1];
   __shared__ float cp[256];
-  __shared__ int pick_sh;
+  __shared__ int pick_sh, flag_sh;
+  __shared__ double plo_sh, phi_sh;
   float* E = lds;                                        // [cap_lds]
   int* near = reinterpret_cast<int*>(lds + cap_lds);     // [cap_lds] pick number
   float* pd = reinterpret_cast<float*>(near + cap_lds);  // [k] D_pa of the current pick
@@ -87,27 +88,48 @@ __device__ void recluster_block(const float* __restrict__ CallT, int ldT, int d,
     __syncthreads();
     if (!(T > 0.0)) break;
     const double thr = u * T;
+    // The picked interval [lo, hi) of the running sums, recorded by the
+    // thread that found the pick, decides whether u*T lay within band*T of
+    // one of its ends (counted in flagged_picks); a pick made by a rounding
+    // fallback always does.
+    int my_pick = -1;
+    double my_lo = 0.0, my_hi = 0.0;
+    if (tid == 0) flag_sh = 0;
     if (bounds[tid] <= thr && thr < bounds[tid + 1]) {
       double run = bounds[tid];
       int pick = -1, last = -1;
       for (int j = lo; j < hi; ++j) {
         const double vv = (s == 0) ? (double)w[j] : (double)w[j] * (double)E[j];
+        const double before = run;
         run += vv;
         if (vv > 0.0) last = j;
         if (vv > 0.0 && run > thr) {
           pick = j;
+          my_lo = before;
+          my_hi = run;
           break;
         }
       }
+      if (pick < 0) {  // u*T at the end of this run by rounding
+        pick = last;
+        my_lo = my_hi = thr;
+      }
+      my_pick = pick;
       // Bounds of neighbouring runs come from different FP64 association
       // orders; should two runs claim u*T, the lower candidate id wins.
-      atomicMin(&pick_sh, pick >= 0 ? pick : (last >= 0 ? last : 0x7fffffff));
+      atomicMin(&pick_sh, pick >= 0 ? pick : 0x7fffffff);
+    }
+    __syncthreads();
+    if (my_pick >= 0 && my_pick == pick_sh) {
+      plo_sh = my_lo;
+      phi_sh = my_hi;
     }
     __syncthreads();
     if (pick_sh == 0x7fffffff) {
       // u*T at or past the total by rounding: the last candidate with mass.
       if (tid == 0) {
         pick_sh = -1;
+        flag_sh = 1;
         for (int j = m - 1; j >= 0; --j) {
           const double vv = (s == 0) ? (double)w[j] : (double)w[j] * (double)E[j];
           if (vv > 0.0) {
@@ -120,6 +142,8 @@ __device__ void recluster_block(const float* __restrict__ CallT, int ldT, int d,
     }
     const int pick = pick_sh;
     if (pick < 0) break;
+    if (tid == 0 && (flag_sh || thr - plo_sh <= band * T || phi_sh - thr <= band * T))
+      st->flagged_picks += 1;
     for (int e = tid; e < d; e += BS) {
       const float x = CallT[(int64_t)e * ldT + pick];
       cp[e] = x;

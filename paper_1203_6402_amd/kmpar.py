@@ -36,7 +36,9 @@ class Stats(ctypes.Structure):
                 ("n_centers", ctypes.c_int32),
                 ("status", ctypes.c_int32),
                 ("n_rescanned", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("flagged_draws", ctypes.c_int32),
+                ("flagged_picks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Trace(ctypes.Structure):
@@ -88,7 +90,7 @@ INSTANCE_DTYPE = np.dtype([("X", "<u8"), ("row_scale", "<u8"), ("centers", "<u8"
                            ("n", "<i8"), ("d", "<i4"), ("k", "<i4"), ("ell", "<f8"),
                            ("rounds", "<i4"), ("reserved", "<i4")])
 assert INSTANCE_DTYPE.itemsize == 64
-SLOT_FOLD_DIRECT, SLOT_SCREEN, SLOT_RESCAN = 0, 1, 2
+SLOT_FOLD_DIRECT, SLOT_SCREEN, SLOT_RESCAN, SLOT_BATCH_FOLD = 0, 1, 2, 3
 
 
 class KmparError(RuntimeError):
@@ -223,7 +225,12 @@ class Context:
     @_on_stream
     def init(self, X: torch.Tensor, k: int, ell: float, rounds: int, seed: int = 0,
              row_scale: torch.Tensor | None = None, trace: bool = False,
-             stream=None, check: bool = True) -> InitResult:
+             stream=None, check: bool = True, allow_toofew: bool = False) -> InitResult:
+        """kmpar_init.  With check (the default) the call synchronises, reads
+        the stats and raises KmparError for any device status other than OK;
+        allow_toofew accepts KMPAR_E_TOOFEW (fewer than k distinct candidates:
+        the |C| centers found are returned).  check=False returns at once with
+        the raw stats record (the caller reads it after synchronising)."""
         dt = self._x(X, row_scale)
         n, d = X.shape
         ws = self._workspace(self.workspace_size(OP_INIT, n, d, k, ell, rounds, dt), X.device)
@@ -247,8 +254,7 @@ class Context:
         if not check:
             return InitResult(centers, {"_raw": st}, tr)
         stats = parse_stats(st, rounds)
-        if stats["status"] == E_OVERFLOW:
-            raise KmparError(E_OVERFLOW, "a round exceeded the candidate capacity")
+        check_status(stats["status"], allow_toofew, "kmpar_init")
         if tr is not None:
             nc = stats["n_candidates"]
             tr["cand_point"] = tr["cand_point"][:nc]
@@ -283,10 +289,12 @@ class Context:
 
     @_on_stream
     def init_batched(self, Xs, ks, ells, rounds: int, seed: int = 0, row_scales=None,
-                     stream=None, check: bool = True, trace: bool = False):
+                     stream=None, check: bool = True, trace: bool = False,
+                     allow_toofew: bool = False):
         """kmpar_init_batched: instance i uses Philox inst = i.  Returns
         (list of k_i x d_i center tensors, list of stats dicts, list of traces
-        or None)."""
+        or None).  With check, any instance whose status is not OK (TOOFEW
+        allowed with allow_toofew) raises KmparError naming the instance."""
         b = _batched_impl(self, Xs, ks, ells, rounds, seed, row_scales, stream, trace)
         self._batch_keep = b                      # device tables live until the next call
         traces = b.traces
@@ -295,6 +303,8 @@ class Context:
                      .view(int(ks[i]), Xs[i].shape[1]) for i in range(len(Xs))]
             return views, b.stats, traces
         centers, st = _batched_results(b, ks, Xs, rounds)
+        for i, s_ in enumerate(st):
+            check_status(s_["status"], allow_toofew, f"kmpar_init_batched instance {i}")
         if traces is not None:
             for t, s_ in zip(traces, st):
                 t["cand_point"] = t["cand_point"][:s_["n_candidates"]]
@@ -456,10 +466,19 @@ class CapturedBatch:
         return _batched_results(self.batch, ks, self._keep[1], rounds)
 
 
+def check_status(status: int, allow_toofew: bool, what: str):
+    """Raises KmparError for a device status other than OK (and TOOFEW when
+    allowed)."""
+    if status == OK or (allow_toofew and status == E_TOOFEW):
+        return
+    raise KmparError(status, f"{what}: device status")
+
+
 def parse_stats(st: torch.Tensor, rounds: int) -> dict:
     raw = st.cpu().numpy().tobytes()
     s = Stats.from_buffer_copy(raw)
     return {"phi": [s.phi[i] for i in range(rounds + 1)],
             "round_count": [s.round_count[i] for i in range(rounds + 1)],
             "n_candidates": s.n_candidates, "n_centers": s.n_centers, "status": s.status,
-            "n_rescanned": s.n_rescanned}
+            "n_rescanned": s.n_rescanned, "flagged_draws": s.flagged_draws,
+            "flagged_picks": s.flagged_picks}

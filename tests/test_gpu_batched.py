@@ -42,6 +42,28 @@ def test_batched_f32_matches_oracle_per_instance(ctx):
     _replay_all([X.astype(np.float64) for X in Xs], cs, sts, trs, ks, ells, 5, 11)
 
 
+def test_batched_c4_draw_sample_matches_oracle(ctx):
+    # The batching workload itself: 4,096 instances with n log-uniform in
+    # [2,000, 200,000], d in {32, 64, 128}, k = ceil(sqrt(n)/2), ell = 2k,
+    # r = 5, GaussMixture data (R = 10), made on the device exactly as the
+    # benchmark makes them and run as one batch; 64 instances drawn at random
+    # are replayed by the oracle with their own Philox instance index.
+    ns, ds, ks = synth.batch_instances(4096, seed=0)
+    ells = 2.0 * ks
+    Xs = synth.batch_gauss_mixture_torch(ns, ds, ks, seed=0, device="cuda:0")
+    cs, sts, trs = ctx.init_batched(Xs, ks, ells, 5, seed=0, trace=True)
+    torch.cuda.synchronize()
+    assert all(s_["status"] == 0 for s_ in sts)
+    pick = np.sort(np.random.default_rng(7).choice(4096, 64, replace=False))
+    print(f"C4: replaying instances with n = {int(ns[pick].min())} .. {int(ns[pick].max())}",
+          flush=True)
+    for i in pick:
+        tr = {key: v.cpu().numpy() for key, v in trs[i].items()}
+        r = SimpleNamespace(stats=sts[i], centers=cs[i])
+        compare_init(Xs[i].cpu().numpy().astype(np.float64), r, tr, int(ks[i]), float(ells[i]), 5, 0,
+                     inst=int(i))
+
+
 def test_batched_bf16_and_ragged_dims(ctx):
     ns = np.array([300, 4097, 999, 1, 2600])
     ds = np.array([128, 42, 7, 5, 256])

@@ -18,7 +18,7 @@ import torch
 
 from oracle import oracle as O
 from paper_1203_6402_amd import synth
-from tests.gpu_util import decoded_fp64
+from tests.gpu_util import compare_init, decoded_fp64
 
 pytestmark = pytest.mark.gpu
 
@@ -60,8 +60,12 @@ def _check_sampled(X64_rows, sample, cand_rows, tr, st, ell, seed, band):
     return flagged
 
 
-def test_c1_kdd_shaped_full_size(K):
-    n, d, k, ell, rounds, seed = 4_800_000, 42, 500, 1000.0, 5, 0
+@pytest.mark.parametrize("ell", [250.0, 1000.0])
+def test_c1_kdd_shaped_full_size(K, ell):
+    # The whole input (n = 4.8M, d = 42, k = 500, ell = k/2 and 2k) replayed
+    # by the FP64 oracle: every round's draws, every point's D^2 and nearest
+    # candidate, the weights and the recluster picks.
+    n, d, k, rounds, seed = 4_800_000, 42, 500, 5, 0
     X = synth.heavy_tailed(n, d, seed=seed)
     Xd = torch.from_numpy(X).to("cuda:0")
     plain = K.Context(0, K.MODE_PLAIN_FP32)
@@ -77,20 +81,13 @@ def test_c1_kdd_shaped_full_size(K):
     tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
     cp = tr["cand_point"]
     assert len(np.unique(cp)) == cp.size == st["n_candidates"]
-    assert np.all(np.diff(st["phi"]) <= 0)
-    assert np.array_equal(np.bincount(tr["assign"], minlength=cp.size), tr["cand_weight"])
-    assert tr["cand_weight"].sum() == n
     # Table 5's qualitative effect: clamped probabilities keep |C| below 1 + r*ell.
     assert cp.size < 1 + rounds * ell
-    rng = np.random.default_rng(1)
-    sample = np.sort(np.concatenate([rng.choice(n, 1500, replace=False), cp[:200]]))
-    cand_rows = X[cp].astype(np.float64)
-    _check_sampled(X[sample].astype(np.float64), sample, cand_rows, tr, st, ell, seed,
-                   O.fp32_band(d))
-    picks, nf, nb = O.kpp_weighted(cand_rows, tr["cand_weight"], k, seed, follow=tr["center_cand"],
-                                   tol=O.fp32_band(d))
-    assert nb == 0
-    np.testing.assert_array_equal(b.centers.cpu().numpy(), X[cp[tr["center_cand"]]])
+    del Xd
+    print(f"C1 ell={ell:g}: oracle replay of all {n} points", flush=True)
+    o = compare_init(X.astype(np.float64), b, tr, k, ell, rounds, seed)
+    print(f"C1 ell={ell:g}: flagged {o.flags}, GPU counted draws {st['flagged_draws']} "
+          f"picks {st['flagged_picks']}", flush=True)
 
 
 def test_c2_precision_full_size(K):
@@ -156,6 +153,52 @@ def test_c3_fp8_full_size(K):
     picks, nf, nb = O.kpp_weighted(cand_rows, tr["cand_weight"], k, seed, follow=tr["center_cand"],
                                    tol=O.fp32_band(d))
     assert nb == 0
+
+
+def test_c3_fp8_lloyd_direct_full_size(K):
+    # Lloyd steps at the C3 shape (n = 50M rows of 256 e4m3 codes, k = 2000)
+    # on the direct form, the form every FP8 assignment pass takes: sampled
+    # assignments against the oracle (outside the FP32 band), the cost of the
+    # input centers (equal to kmpar_cost's), the centroid update of sampled
+    # clusters following the GPU's assignment, then two more iterations in
+    # one kmpar_lloyd call with a non-increasing cost.
+    n, d, k, ell, rounds, seed = C3
+    Q, S = synth.gauss_mixture_sigma_fp8_torch(n, d, 2000, seed=seed, device="cuda:0")
+    ctx = K.Context(0, K.MODE_REFINED)
+    r = ctx.init(Q, k=k, ell=ell, rounds=rounds, seed=seed, row_scale=S)
+    C0 = r.centers.clone()
+    C = r.centers.clone()
+    a, phi = ctx.lloyd_step(Q, C, row_scale=S, want_assign=True)
+    phi_c = ctx.cost(Q, C0, row_scale=S)
+    torch.cuda.synchronize()
+    assert phi.item() == phi_c.item()
+    a = a.cpu().numpy()
+    C0h = C0.cpu().numpy().astype(np.float64)
+    Ch = C.cpu().numpy()
+
+    def rows(idx):
+        i = torch.from_numpy(np.asarray(idx)).to("cuda:0")
+        return decoded_fp64(Q[i].cpu().numpy(), "fp8", S[i].cpu().numpy())
+
+    rng = np.random.default_rng(5)
+    sample = np.sort(rng.choice(n, 3000, replace=False))
+    oa, od2, osnd = O.nearest(rows(sample), C0h)
+    diff = a[sample] != oa
+    gap = (osnd - od2) / np.maximum(od2, 1e-300)
+    assert np.all(gap[diff] <= O.fp32_band(d)), "argmin differs outside the band"
+    counts = np.bincount(a, minlength=k)
+    assert counts.sum() == n
+    for c in rng.choice(k, 10, replace=False):
+        members = np.nonzero(a == c)[0]
+        if members.size == 0:
+            np.testing.assert_array_equal(Ch[c], C0h[c].astype(np.float32))
+            continue
+        mean = rows(members).mean(axis=0)
+        np.testing.assert_allclose(Ch[c], mean.astype(np.float32), rtol=1e-6, atol=1e-6)
+    _, phis = ctx.lloyd(Q, C, 2, row_scale=S)
+    torch.cuda.synchronize()
+    p = [phi.item()] + phis.cpu().tolist()
+    assert p[1] <= p[0] * (1 + 1e-6) and p[2] <= p[1] * (1 + 1e-6)
 
 
 @pytest.mark.skip(reason="ten REFINED Lloyd steps at this size stopped with an illegal-address "

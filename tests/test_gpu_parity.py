@@ -82,6 +82,30 @@ def test_init_wide_rows_low_precision(ctx, dtype, d):
         compare_init(decoded_fp64(q, "fp8", s), r, tr, 25, 50.0, 3, 4)
 
 
+def test_init_fp8_against_exact_products(ctx):
+    # The oracle fed the exact stored values q * s (in FP64) instead of the
+    # FP32 values the kernels decode, fl32(q * s): the replay band then also
+    # covers that input rounding.  Each decoded element is within u = 2^-24
+    # of q * s, so a distance moves by at most 2 u sum_j |x_j - c_j| (|x_j| +
+    # |c_j|), relative to D^2 a factor 2 u rho of the data (computed here
+    # against each point's nearest candidate); a comparison of two distances
+    # (an argmin, or p = ell D^2 / phi against u) carries twice that, and a
+    # half again covers the runner-up candidate's own rho.
+    X = synth.gauss_mixture_sigma(4000, 64, 40, seed=17)
+    q, s = to_e4m3(X)
+    r, tr = gpu_init(ctx, _dev(q), 30, 60.0, 4, 21, row_scale=_dev(s))
+    Xe = decoded_fp64(q, "fp8", s, exact=True)
+    cand = Xe[tr["cand_point"]]
+    a, d2, _ = O.nearest(Xe, cand)
+    pos = d2 > 0
+    c = cand[a[pos]]
+    rho = (np.abs(Xe[pos] - c) * (np.abs(Xe[pos]) + np.abs(c))).sum(axis=1) / d2[pos]
+    band = O.fp32_band(64) + 6.0 * 2.0 ** -24 * rho.max()
+    o = compare_init(Xe, r, tr, 30, 60.0, 4, 21, band=band, d2_rtol=max(D2_RTOL, band),
+                     rows_out=decoded_fp64(q, "fp8", s))
+    assert band < 1e-3 and sum(o.bad.values()) == 0
+
+
 def test_init_bf16_and_fp8_inputs(ctx):
     X = synth.gauss_mixture_sigma(3000, 64, 40, seed=5)
     Xb = to_bf16_bits(X)
@@ -98,7 +122,7 @@ def test_init_degenerate_inputs(ctx, K):
     r, tr = gpu_init(ctx, _dev(X), 1, 10.0, 3, 0)
     assert r.stats["status"] == 0 and r.stats["n_candidates"] == 1
     assert r.stats["phi"] == [0.0] * 4 and tr["cand_weight"].tolist() == [1000]
-    r = ctx.init(_dev(X), k=3, ell=10.0, rounds=3, seed=0)
+    r = ctx.init(_dev(X), k=3, ell=10.0, rounds=3, seed=0, allow_toofew=True)
     assert r.stats["status"] == K.E_TOOFEW and r.stats["n_centers"] == 1
     # Duplicated points: a duplicate sampled in the same round gets weight 0
     # (ties go to the lowest id) and is never picked by the recluster.
@@ -278,7 +302,7 @@ def test_lloyd_iterations_equal_single_steps(K, mode, dtype):
     assert phi0.numel() == 0 and torch.equal(C1, Cm)
 
 
-@pytest.mark.parametrize("dtype,d", [("f32", 200), ("bf16", 256), ("fp8", 160)])
+@pytest.mark.parametrize("dtype,d", [("f32", 200), ("bf16", 256), ("fp8", 160), ("fp8", 256)])
 def test_lloyd_wide_rows_split_fold(ctx, dtype, d):
     # Rows of 129 to 256 padded elements go through the fold that splits each
     # row over three or four waves; one Lloyd step against the oracle: the
