@@ -205,6 +205,27 @@ int kmpar_cost(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
                int64_t n, int32_t d, const float* C, int32_t m, double* phi, void* ws,
                size_t ws_bytes, void* stream);
 
+/* Size of the fixed device scratch that kmpar_cost_noalloc works in. */
+#define KMPAR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* kmpar_cost without a workspace, for callers that cannot allocate device
+ * memory (code under hipGraph capture that may not call hipMalloc, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments, same
+ * launches and bit-identical result as kmpar_cost, but its scratch is a
+ * fixed KMPAR_NOALLOC_SCRATCH_BYTES (64 MiB) array that the library holds on
+ * every GPU it runs on until the process ends; nothing is allocated or
+ * freed, and no event is created (profiling is skipped for this call).
+ * Returns KMPAR_E_WORKSPACE, before any HIP call, when the call needs more
+ * scratch than that: kmpar_workspace_size(ctx, KMPAR_OP_COST, ...) must not
+ * exceed it (about 8 n + 4 m d bytes for a PLAIN_FP32 context, n up to
+ * about eight million; REFINED contexts also need the screen's operands,
+ * up to 272 bytes per point).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other contexts,
+ * other threads) race and must be serialised by the caller. */
+int kmpar_cost_noalloc(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                       int64_t n, int32_t d, const float* C, int32_t m, double* phi,
+                       void* stream);
+
 /* Nearest center of every point (Section 3.1; ties to the lowest index):
  * assign [n] int32, d2 [n] FP32 squared distance (nullable). */
 int kmpar_assign(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,7 @@ struct ProfRec {
 
 struct kmpar_ctx {
   int device = -1;
+  void* scratch = nullptr;  // this device's copy of the fixed scratch (kmpar_cost_noalloc)
   int num_cu = 1;
   kmpar_mode mode = KMPAR_MODE_PLAIN_FP32;
   std::string err;
@@ -358,6 +360,40 @@ int device_ready(kmpar_ctx* ctx) {
   return KMPAR_OK;
 }
 
+// Fixed device scratch of kmpar_cost_noalloc, for callers that cannot
+// allocate: one copy on every GPU the library runs on, held until the
+// process ends.  In host code `scratch` only names the symbol; the device
+// address of each GPU's copy comes from hipGetSymbolAddress, taken once per
+// device when the first context on it is created, and only that address is
+// passed to kernels.
+constexpr size_t kNoallocBytes = KMPAR_NOALLOC_SCRATCH_BYTES;
+
+}  // namespace
+
+static __device__ __attribute__((aligned(256))) char scratch[KMPAR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The address of `scratch` on device dev (made current here), looked up once.
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    DeviceGuard g(dev);
+    if (!g.ok) return g.e;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 // kmpar_cost's launch sequence on the workspace ws (validated by the caller).
 int cost_run(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype, int64_t n,
              int32_t d, const float* C, int32_t m, double* phi, void* ws, size_t ws_bytes,
@@ -380,10 +416,13 @@ int kmpar_create(int hip_device, kmpar_mode mode, kmpar_ctx** out) {
   if (hip_device >= 0 &&
       hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess)
     return KMPAR_E_HIP;
+  void* scr = nullptr;
+  if (hip_device >= 0 && scratch_address(hip_device, &scr) != hipSuccess) return KMPAR_E_HIP;
   kmpar_ctx* c = new kmpar_ctx;
   c->num_cu = cu;
   c->device = hip_device;
   c->mode = mode;
+  c->scratch = scr;
   *out = c;
   return KMPAR_OK;
 }
@@ -707,6 +746,32 @@ int kmpar_cost(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   return cost_run(ctx, X, row_scale, dtype, n, d, C, m, phi, ws, ws_bytes, stream);
 }
 
+int kmpar_cost_noalloc(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                       int64_t n, int32_t d, const float* C, int32_t m, double* phi,
+                       void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  if (!phi || ((uintptr_t)phi & 7u)) return set_err(ctx, KMPAR_E_INVAL, "phi NULL/misaligned");
+  int rc = check_common(ctx, X, row_scale, dtype, n, d);
+  if (rc) return rc;
+  if (m < 1 || m > kMaxK) return set_err(ctx, KMPAR_E_INVAL, "number of centers %d out of range", m);
+  size_t need = 0;
+  rc = kmpar_workspace_size(ctx, KMPAR_OP_COST, n, d, m, 1.0, 0, dtype, &need);
+  if (rc) return rc;
+  if (need > kNoallocBytes)
+    return set_err(ctx, KMPAR_E_WORKSPACE,
+                   "kmpar_cost_noalloc needs %zu bytes of scratch here, more than its fixed %zu "
+                   "(call kmpar_cost with a workspace, or a PLAIN_FP32 context)",
+                   need, kNoallocBytes);
+  if ((rc = device_ready(ctx))) return rc;
+  if (!ctx->scratch) return set_err(ctx, KMPAR_E_HIP, "no scratch address for device %d", ctx->device);
+  // The same launches as kmpar_cost on the fixed scratch; no event timing
+  // (events are created on demand), so nothing here allocates.
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  rc = cost_run(ctx, X, row_scale, dtype, n, d, C, m, phi, ctx->scratch, kNoallocBytes, stream);
+  ctx->prof = prof;
+  return rc;
+}
 
 }  // extern "C"
 

@@ -62,6 +62,7 @@ _lib.kmpar_workspace_size.argtypes = [_vp, ctypes.c_int, _i64, _i32, _i32, _dbl,
 _lib.kmpar_init.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _i32, _dbl, _i32, _u64,
                             _vp, _vp, _sz, _vp, ctypes.POINTER(Trace), _vp]
 _lib.kmpar_cost.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _vp, _vp, _sz, _vp]
+_lib.kmpar_cost_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _vp, _vp]
 _lib.kmpar_assign.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _vp, _vp, _vp,
                               _sz, _vp]
 _lib.lloyd_step.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _vp, _vp, _vp,
@@ -81,7 +82,8 @@ EXPORTED = ["kmpar_create", "kmpar_destroy", "kmpar_strerror", "kmpar_last_error
             "kmpar_sizeof_stats", "kmpar_max_candidates", "kmpar_workspace_size", "kmpar_init",
             "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_lloyd", "kmpar_profile_enable",
             "kmpar_profile_read", "kmpar_workspace_size_batched", "kmpar_init_batched",
-            "kmpar_set_option", "kmpar_batch_tiles"]
+            "kmpar_set_option", "kmpar_batch_tiles", "kmpar_cost_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 OPT_RECLUSTER_PATH = 0
 OPT_BATCH_AUTOTUNE = 1
 
@@ -272,6 +274,20 @@ class Context:
         self._check(_lib.kmpar_cost(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d,
                                     C.data_ptr(), C.shape[0], phi.data_ptr(), ws.data_ptr(),
                                     ws.numel(), _stream(stream)), "kmpar_cost")
+        return phi
+
+    @_on_stream
+    def cost_noalloc(self, X, C, row_scale=None, stream=None) -> torch.Tensor:
+        """kmpar_cost_noalloc: the cost in the library's fixed scratch (no
+        workspace).  C must already be contiguous float32 on the device."""
+        dt = self._x(X, row_scale)
+        n, d = X.shape
+        if C.dtype != torch.float32 or not C.is_contiguous():
+            raise ValueError("C must be contiguous float32")
+        phi = torch.empty(1, dtype=torch.float64, device=X.device)
+        self._check(_lib.kmpar_cost_noalloc(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d,
+                                            C.data_ptr(), C.shape[0], phi.data_ptr(),
+                                            _stream(stream)), "kmpar_cost_noalloc")
         return phi
 
     @_on_stream

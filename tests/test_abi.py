@@ -177,3 +177,20 @@ def test_init_rejects_candidate_capacity_overflow(K):
     # device work, so a host-only context reports it)
     ctx = K.Context(None)
     assert _call_init(K, ctx, n=2**30, d=8, k=10, ell=1e12, rounds=64, wsb=1 << 62) == K.E_INVAL
+
+
+def test_noalloc_cost_validation(K):
+    # kmpar_cost_noalloc validates and sizes before any HIP call: a call that
+    # needs more than the fixed scratch is refused, a fitting one reaches the
+    # device check of a host-only context.
+    L, ctx = K._lib, K.Context(None)
+    h = ctx._h
+    assert L.kmpar_cost_noalloc(h, 16, None, K.F32, 1000, 8, 32, 5, 64, None) == K.E_NODEVICE
+    assert L.kmpar_cost_noalloc(h, 16, None, K.F32, 9_000_000, 8, 32, 5, 64, None) == K.E_WORKSPACE
+    assert "fixed" in L.kmpar_last_error(h).decode()
+    assert L.kmpar_cost_noalloc(h, 16, None, K.F32, 1000, 8, 32, 0, 64, None) == K.E_INVAL
+    assert L.kmpar_cost_noalloc(h, 16, None, K.F32, 1000, 8, 32, 5, 68, None) == K.E_INVAL
+    assert L.kmpar_cost_noalloc(h, 17, None, K.F32, 1000, 8, 32, 5, 64, None) == K.E_INVAL
+    refined = K.Context(None, K.MODE_REFINED)     # REFINED also sizes the screen's operands
+    assert L.kmpar_cost_noalloc(refined._h, 16, None, K.F32, 400_000, 42, 32, 500, 64,
+                                None) == K.E_WORKSPACE
