@@ -98,8 +98,10 @@ typedef struct kmpar_stats {
   int32_t flagged_draws;                     /* round draws with |u - p| <= band p,
                                                 summed over rounds (step 4)       */
   int32_t flagged_picks;                     /* recluster picks whose u T lies
-                                                within band T of an end of the
-                                                picked interval (step 8)          */
+                                                within (band / 2)(P + u T) of an
+                                                end P of the picked interval: the
+                                                masses' FP32 distances could have
+                                                moved it across (step 8)          */
   int32_t reserved[2];
 } kmpar_stats;
 

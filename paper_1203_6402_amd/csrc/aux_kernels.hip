@@ -416,7 +416,7 @@ struct ReclArgs {
   int* picks;          // [k] output: candidate ids
   float* centers;      // [k][d] output rows
   kmpar_stats* st;
-  double band;         // picks with u*T within band*T of an interval end are flagged
+  double band;         // FP32 band of the distances (see pick_near_end)
 };
 
 // The recluster's draws, one thread each, ahead of the sequential picks.
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
   float* lds = reinterpret_cast<float*>(lds4);
   __shared__ double wtot[kReclBlock / kWave];
   __shared__ double gpart[kReclMaxBlocks];
-  __shared__ double sh_u, sh_base, sh_top, sh_T, sh_plo, sh_phi;
+  __shared__ double sh_u, sh_base, sh_top, sh_plo, sh_phi;
   __shared__ int sh_pick, sh_owner, sh_failed, sh_stop, sh_pflag;
   constexpr int NW = kReclBlock / kWave;
   const int b = blockIdx.x, tid = threadIdx.x, DP = a.DP, d = a.d;
@@ -580,7 +580,6 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
         sh_base = lo_b;
         sh_top = hi_b;
         sh_u = thr;
-        sh_T = T;
         sh_pick = 0x7fffffff;
         sh_pflag = 0;
       }
@@ -663,10 +662,8 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
         }
         __syncthreads();
       }
-      if (tid == 0) {
-        const double bt = a.band * sh_T;
-        if (sh_pflag || thr - sh_plo <= bt || sh_phi - thr <= bt) atomicAdd(&a.st->flagged_picks, 1);
-      }
+      if (tid == 0 && (sh_pflag || pick_near_end(thr, sh_plo, sh_phi, a.band)))
+        atomicAdd(&a.st->flagged_picks, 1);
       const int jl = sh_pick;
       // hop 2 of round s: publish the row, then the outputs
       const float* pr = LROWS ? rows + (size_t)jl * DL : grows + (size_t)jl * DP;

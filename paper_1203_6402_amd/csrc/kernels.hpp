@@ -158,6 +158,15 @@ hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, ui
 // Relative error band of an FP32 direct-form squared distance over d
 // coordinates, doubled: 2 (d + 2) 2^-24.
 __host__ __device__ inline double fp32_flag_band(int d) { return 2.0 * (d + 2) * 0x1.0p-24; }
+// Whether a recluster pick could have fallen into the neighbouring interval:
+// every mass w_j E_j carries the relative error of its FP32 distance, at most
+// band / 2, so a running sum P and the threshold u T move by at most band / 2
+// times themselves, and their difference by (band / 2)(P + u T) (the FP64
+// roundings add a relative 2^-50 margin).  [lo, hi) is the picked interval.
+__host__ __device__ inline bool pick_near_end(double thr, double lo, double hi, double band) {
+  const double b = 0.5 * band + 0x1.0p-50;
+  return thr - lo <= b * (thr + lo) || hi - thr <= b * (hi + thr);
+}
 hipError_t launch_finish_rounds(const int* rs, int rounds, kmpar_stats* st, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s);
 // Step-7 weights w[0 .. nbins) of the assignment A (an LDS histogram per

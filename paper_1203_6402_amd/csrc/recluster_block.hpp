@@ -89,9 +89,9 @@ __device__ void recluster_block(const float* __restrict__ CallT, int ldT, int d,
     if (!(T > 0.0)) break;
     const double thr = u * T;
     // The picked interval [lo, hi) of the running sums, recorded by the
-    // thread that found the pick, decides whether u*T lay within band*T of
-    // one of its ends (counted in flagged_picks); a pick made by a rounding
-    // fallback always does.
+    // thread that found the pick, decides whether u*T lay near enough to one
+    // of its ends to have been decided the other way (pick_near_end; counted
+    // in flagged_picks); a pick made by a rounding fallback always is.
     int my_pick = -1;
     double my_lo = 0.0, my_hi = 0.0;
     if (tid == 0) flag_sh = 0;
@@ -142,8 +142,7 @@ __device__ void recluster_block(const float* __restrict__ CallT, int ldT, int d,
     }
     const int pick = pick_sh;
     if (pick < 0) break;
-    if (tid == 0 && (flag_sh || thr - plo_sh <= band * T || phi_sh - thr <= band * T))
-      st->flagged_picks += 1;
+    if (tid == 0 && (flag_sh || pick_near_end(thr, plo_sh, phi_sh, band))) st->flagged_picks += 1;
     for (int e = tid; e < d; e += BS) {
       const float x = CallT[(int64_t)e * ldT + pick];
       cp[e] = x;
