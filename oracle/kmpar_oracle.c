@@ -18,6 +18,9 @@
  *   orc_kpp_weighted   -- exact enumeration of the pick distribution on tiny
  *                         inputs; w == 1 and C == X gives Algorithm 1.
  *   orc_lloyd_update   -- sklearn's Lloyd iteration (no empty clusters).
+ *   orc_exact_keys     -- the law of the smallest key (D^2 sampling) and of the
+ *                         l smallest (successive draws without replacement)
+ *                         by chi-square against exact enumeration.
  */
 #include <math.h>
 #include <stdint.h>
@@ -38,6 +41,8 @@
 #define ORC_TAG_FIRST 1u /* Algorithm 2 step 1: the uniform first center     */
 #define ORC_TAG_ROUND 2u /* Algorithm 2 step 4: per-point Bernoulli draws      */
 #define ORC_TAG_RECL 3u  /* step 8: weighted k-means++ picks (Algorithm 1)    */
+#define ORC_TAG_EXACT 4u /* D^2 sampling by exponential race: the exact-ell
+                            rounds of Section 5.3 and k-means++ on all of X  */
 
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
   uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
@@ -80,6 +85,30 @@ double orc_uniform(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, uint64_t
 int64_t orc_index(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, uint64_t inst, int64_t n) {
   unsigned __int128 p = (unsigned __int128)orc_word(seed, tag, a, b, inst) * (uint64_t)n;
   return (int64_t)(p >> 64);
+}
+
+/* Uniform on (0, 1]: (top 53 bits of the word + 1) * 2^-53, never 0. */
+double orc_uniform_open(uint64_t seed, uint64_t tag, uint64_t a, uint64_t b, uint64_t inst) {
+  return (double)((orc_word(seed, tag, a, b, inst) >> 11) + 1) * 0x1.0p-53;
+}
+
+/* D^2 sampling as an exponential race (Efraimidis & Spirakis, "Weighted
+ * random sampling with a reservoir", IPL 2006): point i gets the clock
+ * key_i = -ln(V_i) / D2_i, V_i uniform on (0, 1] from tag EXACT at counter
+ * (i, t, inst); key_i is exponential with rate D2_i, so the smallest key is
+ * point i with probability D2_i / sum_j D2_j (one draw of Algorithm 1's
+ * step), and the l smallest keys are l draws without replacement, each in
+ * proportion to D^2 among the points not yet drawn.  D2_i = 0 gives +inf:
+ * such a point is never drawn. */
+void orc_exact_keys(const double* D2, int64_t n, uint64_t seed, int64_t t, uint64_t inst,
+                    double* key) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    if (D2[i] > 0.0)
+      key[i] = -log(orc_uniform_open(seed, ORC_TAG_EXACT, (uint64_t)i, (uint64_t)t, inst)) / D2[i];
+    else
+      key[i] = INFINITY;
+  }
 }
 
 /* Squared Euclidean distance ||x - c||^2, coordinates in order (Section 3.1). */

@@ -11,7 +11,13 @@ composes Algorithm 2 of the paper (Section 3.3) from its steps:
 7. weights w_c = |{x : c nearest to x}|                  -- ``orc_weights``
 8. recluster the weighted candidates with k-means++      -- ``orc_kpp_weighted``
 
-plus Lloyd's iteration (Section 1, Section 3.1) -- ``lloyd_step``.
+plus Lloyd's iteration (Section 1, Section 3.1) -- ``lloyd_step``, Lloyd
+until the assignment is stable -- ``lloyd_until_stable``, the exact-ell
+rounds of Section 5.3 (exactly ell points per round, drawn in proportion to
+D^2 without replacement) -- ``select_exact`` / ``sampling="exact"``, and
+k-means++ on all of X (Algorithm 1) -- ``kmeanspp``.  Both draw D^2 samples
+as an exponential race (``orc_exact_keys``), so with ell = 1 and r = k - 1
+the exact-ell variant makes exactly the draws of k-means++.
 
 Replay ("follow").  Another implementation that computes in lower precision
 may legitimately take a different discrete decision where the oracle's margin
@@ -36,7 +42,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libkmpar_oracle.so")
 _SRC_PATH = os.path.join(_HERE, "kmpar_oracle.c")
 
-TAG_FIRST, TAG_ROUND, TAG_RECL = 1, 2, 3
+TAG_FIRST, TAG_ROUND, TAG_RECL, TAG_EXACT = 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
@@ -81,6 +87,9 @@ def lib():
         L.orc_kpp_weighted.argtypes = [vp, i64, i32, vp, i64, u64, u64, vp, dbl, vp, vp, vp]
         L.orc_kpp_weighted.restype = i64
         L.orc_lloyd_update.argtypes = [vp, i64, i32, vp, i64, vp, vp]
+        L.orc_uniform_open.argtypes = [u64, u64, u64, u64, u64]
+        L.orc_uniform_open.restype = dbl
+        L.orc_exact_keys.argtypes = [vp, i64, u64, i64, u64, vp]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -113,6 +122,10 @@ def uniform(seed, tag, a, b, inst=0) -> float:
 
 def index(seed, tag, a, b, inst, n) -> int:
     return int(lib().orc_index(seed, tag, a, b, inst, n))
+
+
+def uniform_open(seed, tag, a, b, inst=0) -> float:
+    return float(lib().orc_uniform_open(seed, tag, a, b, inst))
 
 
 def first_center(n: int, seed: int, inst: int = 0) -> int:
@@ -150,6 +163,27 @@ def select(D2, phi, ell, seed, t, inst=0):
     u = np.empty(n, np.float64)
     lib().orc_select(_p(D2), n, float(phi), float(ell), seed, t, inst, _p(sel), _p(p), _p(u))
     return sel.astype(bool), p, u
+
+
+def exact_keys(D2, seed, t, inst=0) -> np.ndarray:
+    """Exponential-race keys -ln(V_i) / D2_i (+inf where D2_i = 0)."""
+    D2 = _f64(D2)
+    key = np.empty(D2.size, np.float64)
+    lib().orc_exact_keys(_p(D2), D2.size, seed, t, inst, _p(key))
+    return key
+
+
+def select_exact(D2, ell, seed, t, inst=0):
+    """Exact-ell round (Section 5.3): the min(ell, #{D2 > 0}) points with the
+    smallest keys (ties to the lower index).  Returns (selected mask, keys,
+    tau = the largest selected key, or +inf when nothing is selected)."""
+    key = exact_keys(D2, seed, t, inst)
+    take = int(min(int(ell), int(np.count_nonzero(np.isfinite(key)))))
+    order = np.argsort(key, kind="stable")[:take]
+    sel = np.zeros(key.size, bool)
+    sel[order] = True
+    tau = float(key[order[-1]]) if take else np.inf
+    return sel, key, tau
 
 
 def fold(X, Cnew, first_id, D2, A, S=None):
@@ -204,6 +238,48 @@ def lloyd_step(X, C):
     return Cn, a, total(d2)
 
 
+def lloyd_until_stable(X, C, max_iters, follow=None, band=None):
+    """Lloyd's iteration repeated until the set of centers is stable
+    (Section 1): each iteration assigns every point to its nearest center;
+    when the assignment equals the previous iteration's, the centers would
+    not move and the iteration stops; otherwise the centers move to the
+    centroids (an empty cluster keeps its center).  ``follow`` (optional):
+    another implementation's assignment per iteration, accepted where it
+    differs inside the relative ``band`` (counted as flagged) and then used.
+    Returns (centers, number of center updates made, cost of the input
+    centers of every assignment, n_flagged, n_bad)."""
+    X = _f64(X)
+    d = X.shape[1]
+    band = fp32_band(d) if band is None else band
+    C = _f64(C).copy()
+    prev = None
+    phis = []
+    nf = nb = 0
+    it = 0
+    for it in range(max_iters + 1):
+        a, d2, _ = nearest(X, C)
+        phis.append(total(d2))
+        if follow is not None and it < len(follow):
+            g = np.asarray(follow[it], dtype=np.int64)
+            diff = np.nonzero(g != a)[0]
+            if diff.size:
+                ok = (g[diff] >= 0) & (g[diff] < C.shape[0])
+                dg = np.full(diff.size, np.inf)
+                dg[ok] = ((X[diff[ok]] - C[g[diff[ok]]]) ** 2).sum(axis=1)
+                within = ok & (dg - d2[diff] <= band * d2[diff])
+                nf += int(within.sum())
+                nb += int((~within).sum())
+                a = a.copy()
+                a[diff[ok]] = g[diff[ok]]
+        if prev is not None and np.array_equal(a, prev):
+            return C, it, phis, nf, nb
+        if it == max_iters:
+            break
+        C, _ = lloyd_update(X, a, C)
+        prev = a
+    return C, max_iters, phis, nf, nb
+
+
 # ---------------------------------------------------------------- k-means||
 def fp32_band(d: int) -> float:
     """Relative error bound of a squared distance computed in FP32 in direct
@@ -252,22 +328,33 @@ def first_round_state(X, seed, inst=0) -> RoundState:
 
 
 def run_rounds(X, state: RoundState, t_end, ell, seed, inst=0, follow=None, band=None,
-               flags=None, bad=None) -> RoundState:
+               flags=None, bad=None, sampling="bernoulli") -> RoundState:
     """Algorithm 2 steps 3-6 for rounds state.rounds_done+1 .. t_end, updating
     ``state`` in place (a checkpoint taken after any round resumes to the
     same result).  ``follow``/``band``/``flags``/``bad`` as in
-    ``kmeans_parallel_init``."""
+    ``kmeans_parallel_init``; ``sampling="exact"`` keeps exactly ell points
+    per round (Section 5.3) instead of independent draws."""
     X = _f64(X)
     n, d = X.shape
     band = fp32_band(d) if band is None else band
     for t in range(state.rounds_done + 1, t_end + 1):
-        sel, p, u = select(state.D2, state.phi[-1], ell, seed, t, inst)
+        if sampling == "exact":
+            sel, key, tau = select_exact(state.D2, ell, seed, t, inst)
+        else:
+            sel, p, u = select(state.D2, state.phi[-1], ell, seed, t, inst)
         if follow is not None and "rounds" in follow:
             other = np.zeros(n, bool)
             other[np.asarray(follow["rounds"][t - 1], dtype=np.int64)] = True
             diff = np.nonzero(other != sel)[0]
             if diff.size:
-                within = np.abs(u[diff] - p[diff]) <= band * p[diff] + 1e-300
+                if sampling == "exact":
+                    # a key within the band of the round's threshold could
+                    # have landed on the other side of it (each key carries
+                    # the relative error of its D^2)
+                    kd = key[diff]
+                    within = np.isfinite(kd) & (kd <= tau * (1 + band)) & (kd * (1 + band) >= tau)
+                else:
+                    within = np.abs(u[diff] - p[diff]) <= band * p[diff] + 1e-300
                 flags["draw"] += int(within.sum())
                 bad["draw"] += int((~within).sum())
                 sel = other
@@ -280,7 +367,8 @@ def run_rounds(X, state: RoundState, t_end, ell, seed, inst=0, follow=None, band
     return state
 
 
-def kmeans_parallel_init(X, k, ell, rounds, seed, inst=0, follow=None, band=None, state=None):
+def kmeans_parallel_init(X, k, ell, rounds, seed, inst=0, follow=None, band=None, state=None,
+                         sampling="bernoulli"):
     """Algorithm 2 (Section 3.3) with k-means++ as the Step-8 recluster.
 
     ``follow`` (optional) is a dict with any of
@@ -290,6 +378,8 @@ def kmeans_parallel_init(X, k, ell, rounds, seed, inst=0, follow=None, band=None
     and ``band`` the relative error band of the other side's distances
     (default: ``fp32_band(d)``).  ``state`` (optional) is a ``RoundState``
     checkpoint to resume from instead of starting at step 1.
+    ``sampling="exact"``: every round keeps exactly ell points, drawn in
+    proportion to D^2 without replacement (Section 5.3).
     """
     X = _f64(X)
     n, d = X.shape
@@ -298,7 +388,7 @@ def kmeans_parallel_init(X, k, ell, rounds, seed, inst=0, follow=None, band=None
     bad = {"draw": 0, "argmin": 0, "pick": 0}
 
     st = first_round_state(X, seed, inst) if state is None else state
-    run_rounds(X, st, rounds, ell, seed, inst, follow, band, flags, bad)
+    run_rounds(X, st, rounds, ell, seed, inst, follow, band, flags, bad, sampling)
     D2, A, phi, counts = st.D2, st.A, st.phi, st.counts
 
     cand = np.asarray(st.cand, dtype=np.int64)
@@ -325,3 +415,39 @@ def kmeans_parallel_init(X, k, ell, rounds, seed, inst=0, follow=None, band=None
     bad["pick"] += nb
     return InitResult(cand_point=cand, round_count=counts, phi=phi, assign=A, d2=D2,
                       weights=w, picks=picks, centers=X[cand[picks]], flags=flags, bad=bad)
+
+
+def kmeanspp(X, k, seed, inst=0, follow=None, band=None):
+    """k-means++ on all of X (Algorithm 1): the first center uniformly at
+    random (the FIRST draw of Algorithm 2), then k - 1 centers each drawn in
+    proportion to D^2 by the exponential race of draw s = 1 .. k - 1 (tag
+    EXACT, counter (i, s, inst)).  ``follow``: another implementation's
+    picks; a differing pick is accepted (flagged) when its key lies within
+    the relative ``band`` of the smallest key.  Returns (picks, phi after
+    each pick, n_flagged, n_bad); fewer than k picks when every point
+    coincides with a center."""
+    X = _f64(X)
+    n, d = X.shape
+    band = fp32_band(d) if band is None else band
+    picks = [first_center(n, seed, inst)]
+    D2 = np.full(n, np.inf)
+    A = np.zeros(n, np.int64)
+    fold(X, X[picks[0]:picks[0] + 1], 0, D2, A)
+    phi = [total(D2)]
+    nf = nb = 0
+    for s in range(1, k):
+        key = exact_keys(D2, seed, s, inst)
+        j = int(np.argmin(key))               # first occurrence: the lower index on ties
+        if not np.isfinite(key[j]):
+            break
+        if follow is not None and s < len(follow) and int(follow[s]) != j:
+            g = int(follow[s])
+            if 0 <= g < n and np.isfinite(key[g]) and key[g] <= key[j] * (1 + band):
+                nf += 1
+            else:
+                nb += 1
+            j = g if 0 <= g < n else j
+        picks.append(j)
+        fold(X, X[j:j + 1], s, D2, A)
+        phi.append(total(D2))
+    return np.asarray(picks, np.int64), phi, nf, nb
