@@ -73,7 +73,8 @@ typedef enum kmpar_op {
   KMPAR_OP_INIT = 0,
   KMPAR_OP_COST = 1,
   KMPAR_OP_ASSIGN = 2,
-  KMPAR_OP_LLOYD = 3
+  KMPAR_OP_LLOYD = 3,    /* lloyd_step, kmpar_lloyd, kmpar_lloyd_until_stable */
+  KMPAR_OP_KMEANSPP = 4  /* kmpar_kmeanspp                                   */
 } kmpar_op;
 
 typedef struct kmpar_ctx kmpar_ctx;
@@ -130,7 +131,18 @@ typedef enum kmpar_option {
    * the context keeps the fastest for later batches; 0 = fixed defaults.
    * Tuning synchronises the stream once per new shape and is skipped while
    * the stream is being captured into a graph. */
-  KMPAR_OPT_BATCH_AUTOTUNE = 1
+  KMPAR_OPT_BATCH_AUTOTUNE = 1,
+  /* Round draws of kmpar_init: 0 (default) = Algorithm 2, every point kept
+   * independently with probability min(1, ell d^2(x) / phi); 1 = the
+   * exact-ell variant of Section 5.3, exactly min(ell, #{d^2 > 0}) points
+   * per round, drawn in proportion to d^2 without replacement (ell must then
+   * be an integer).  Those draws are an exponential race: point i gets the
+   * key -ln(V) / d^2(x_i) with V = ((w >> 11) + 1) 2^-53, w from Philox tag 4
+   * at counter (i, t, 0), and the ell smallest keys are kept (ties: lower
+   * index); with ell = 1 and rounds = k - 1 the candidates are exactly the
+   * picks of kmpar_kmeanspp with the same seed.  stats->flagged_draws then
+   * counts keys within the FP32 band of the round's threshold key. */
+  KMPAR_OPT_SAMPLING = 2
 } kmpar_option;
 int kmpar_set_option(kmpar_ctx* ctx, kmpar_option opt, int64_t value);
 
@@ -255,6 +267,38 @@ int lloyd_step(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
 int kmpar_lloyd(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
                 int64_t n, int32_t d, float* C, int32_t k, int32_t iters, int32_t* assign,
                 double* phi, void* ws, size_t ws_bytes, void* stream);
+
+/* k-means++ on all of X (Algorithm 1, the initialisation k-means|| is
+ * measured against in Section 4.2): the first center is point Index(n) of
+ * Philox tag 1 (as kmpar_init's), then center s = 1 .. k-1 is drawn in
+ * proportion to d^2(x, {centers so far}) by the exponential race of
+ * KMPAR_OPT_SAMPLING (tag 4, counter (i, s, 0)); each step is one pass over
+ * X (FP32 direct-form distances to the newest center, folded into d^2).
+ * Output: centers [k x d] FP32 in pick order; picks [k] (device, nullable)
+ * their point indices; phi [k] (device, nullable) the cost after each pick,
+ * phi[s] = phi_X(first s + 1 centers); stats (device, nullable): phi[0] =
+ * psi, n_centers.  If every point lies on a center before k picks, the run
+ * stops there with stats->status = KMPAR_E_TOOFEW.  Workspace:
+ * kmpar_workspace_size(KMPAR_OP_KMEANSPP, ...). */
+int kmpar_kmeanspp(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                   int64_t n, int32_t d, int32_t k, uint64_t seed, float* centers, int32_t* picks,
+                   double* phi, void* ws, size_t ws_bytes, kmpar_stats* stats, void* stream);
+
+/* Lloyd's iteration until the centers are stable (Section 1): every
+ * iteration assigns each point to its nearest center (as lloyd_step); when
+ * the assignment equals the previous iteration's the centers would not move
+ * and the call stops, otherwise the centers move to the centroids.  At most
+ * max_iters center updates.  *iters (HOST int) receives the number of
+ * updates made (max_iters if the assignment never settled); phi [max_iters
+ * + 1] (device, nullable) the cost of each assignment's centers, phi[*iters]
+ * that of the final ones; assign [n] (device, nullable) the final
+ * assignment.  Unlike every other call this one reads a count back to the
+ * host once per iteration (it synchronises the stream and cannot be
+ * captured in a graph).  Workspace: kmpar_workspace_size(KMPAR_OP_LLOYD). */
+int kmpar_lloyd_until_stable(kmpar_ctx* ctx, const void* X, const float* row_scale,
+                             kmpar_dtype dtype, int64_t n, int32_t d, float* C, int32_t k,
+                             int32_t max_iters, int32_t* iters, int32_t* assign, double* phi,
+                             void* ws, size_t ws_bytes, void* stream);
 
 /* One independent clustering instance of kmpar_init_batched (64 bytes). */
 typedef struct kmpar_instance {

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkmpar.so")
-SOURCES = ["fold_direct.hip", "screen_mfma.hip", "aux_kernels.hip", "batched.hip", "api.hip"]
+SOURCES = ["fold_direct.hip", "screen_mfma.hip", "aux_kernels.hip", "batched.hip", "exact.hip",
+           "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions anywhere in device code

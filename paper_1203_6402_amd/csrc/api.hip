@@ -33,6 +33,7 @@ struct kmpar_ctx {
   std::string err;
   bool prof = false;
   int recl_path = 0;  // KMPAR_OPT_RECLUSTER_PATH
+  int sampling = 0;   // KMPAR_OPT_SAMPLING
   kmpar::BatchTuner tuner;  // KMPAR_OPT_BATCH_AUTOTUNE and its choices
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
@@ -106,6 +107,7 @@ struct InitLayout {
   float* ncg;
   float* scg;
   void* Apre;
+  ExactWs ex;     // exact-ell rounds only
   size_t bytes;
 };
 
@@ -122,7 +124,8 @@ size_t a_bytes(kmpar_dtype dt, bool rows, int64_t n, int d) {
   return screen_a_bytes((int)n, screen_ksteps(sp, d));
 }
 
-InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds, kmpar_dtype dt) {
+InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds, kmpar_dtype dt,
+                       bool exact) {
   const int DP = padded_dim(d);
   const int64_t capT = 1 + (int64_t)rounds * cap_round_of(n, ell);
   Carver c(ws);
@@ -156,6 +159,40 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.ncg = c.take<float>((size_t)tiles * 16);
   L.scg = c.take<float>((size_t)tiles * 16);
   L.Apre = c.take<char>(a_bytes(dt, true, n, d));
+  L.ex = ExactWs{};
+  if (exact) {
+    L.ex.keys = c.take<unsigned long long>(n);
+    L.ex.hist = c.take<int>(exact_hist_bins());
+    L.ex.state = c.take<ExactState>(1);
+  }
+  L.bytes = c.off;
+  return L;
+}
+
+// The exact-ell rounds of a context (sized in its workspace); a null
+// context sizes for them.
+bool ctx_exact(const kmpar_ctx* ctx) { return !ctx || ctx->sampling == 1; }
+
+// Workspace of kmpar_kmeanspp.
+struct KppLayout {
+  KppWs w;
+  int* picks;
+  kmpar_stats* st;
+  size_t bytes;
+};
+
+KppLayout kpp_layout(void* ws, int64_t n, int d, int k) {
+  Carver c(ws);
+  KppLayout L{};
+  const int64_t nb = (n + 63) / 64;
+  L.w.D2 = c.take<float>(n);
+  L.w.pkey = c.take<unsigned long long>(nb);
+  L.w.pidx = c.take<int>(nb);
+  L.w.pphi = c.take<double>(nb);
+  L.w.crow = c.take<float>(d);
+  L.w.stop = c.take<int>(4);
+  L.picks = c.take<int>(k);
+  L.st = c.take<kmpar_stats>(1);
   L.bytes = c.off;
   return L;
 }
@@ -167,6 +204,8 @@ struct AssignLayout {
   double* phi_tmp;
   float* Cpad;
   LloydWs lw;
+  int* A2;       // Lloyd until stable: the previous iteration's assignment
+  int* changed;  // and the count of points whose assignment changed
   float* norms;
   int* list;
   int* list_len;
@@ -199,6 +238,8 @@ AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op, kmpar
     L.lw.cstart = c.take<int>(k + 1);
     L.lw.coff = c.take<int>(k + 1);
     L.lw.part = c.take<double>(((n + kSegChunk - 1) / kSegChunk + k) * (int64_t)d);
+    L.A2 = c.take<int>(n);
+    L.changed = c.take<int>(4);
   }
   if (refined && screen_supported(dt, false, d)) {
     const int tiles = (k + 15) / 16;
@@ -444,6 +485,10 @@ int kmpar_set_option(kmpar_ctx* ctx, kmpar_option opt, int64_t value) {
       if (value < 0 || value > 3) return set_err(ctx, KMPAR_E_INVAL, "recluster path %lld", (long long)value);
       ctx->recl_path = (int)value;
       return KMPAR_OK;
+    case KMPAR_OPT_SAMPLING:
+      if (value < 0 || value > 1) return set_err(ctx, KMPAR_E_INVAL, "sampling %lld", (long long)value);
+      ctx->sampling = (int)value;
+      return KMPAR_OK;
     case KMPAR_OPT_BATCH_AUTOTUNE:
       if (value < 0 || value > 1) return set_err(ctx, KMPAR_E_INVAL, "batch autotune %lld", (long long)value);
       ctx->tuner.enabled = value != 0;
@@ -553,9 +598,15 @@ int kmpar_workspace_size(const kmpar_ctx* cctx, kmpar_op op, int64_t n, int32_t 
         return set_err(ctx, KMPAR_E_INVAL, "k, ell or rounds out of range");
       const int64_t capT = 1 + (int64_t)rounds * cap_round_of(n, ell);
       if (capT >= (int64_t)1 << 31) return set_err(ctx, KMPAR_E_INVAL, "candidate capacity too large");
-      *bytes_out = init_layout(nullptr, n, d, k, ell, rounds, dtype).bytes;
+      if (ctx && ctx->sampling == 1 && (ell != floor(ell) || ell > INT32_MAX))
+        return set_err(ctx, KMPAR_E_INVAL, "exact-ell rounds need an integer ell");
+      *bytes_out = init_layout(nullptr, n, d, k, ell, rounds, dtype, ctx_exact(ctx)).bytes;
       return KMPAR_OK;
     }
+    case KMPAR_OP_KMEANSPP:
+      if (k > n) return set_err(ctx, KMPAR_E_INVAL, "k=%d > n", k);
+      *bytes_out = kpp_layout(nullptr, n, d, k).bytes;
+      return KMPAR_OK;
     case KMPAR_OP_COST:
     case KMPAR_OP_ASSIGN:
     case KMPAR_OP_LLOYD:
@@ -605,7 +656,8 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   const int N = (int)n, DP = padded_dim(d);
   const int cap_round = (int)cap_round_of(n, ell);
   const int capT = (int)capT64;
-  InitLayout L = init_layout(ws, n, d, k, ell, rounds, dtype);
+  InitLayout L = init_layout(ws, n, d, k, ell, rounds, dtype, ctx_exact(ctx));
+  const bool exact = ctx->sampling == 1;
   kmpar_stats* st = stats ? stats : L.st;
   const uint64_t inst = 0;
 
@@ -639,11 +691,16 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   }));
   KMPAR_HIP(launch_phi(L.D2, N, L.phi_part, &st->phi[0], s));
   if (refined) KMPAR_HIP(launch_fill_i32(L.list_len, 0, 1, s));
+  if (exact) KMPAR_HIP(launch_fill_i32(L.ex.hist, 0, exact_hist_bins(), s));
   // Steps 3-6: rounds.
   fa.first = 0;
   for (int t = 1; t <= rounds; ++t) {
-    KMPAR_HIP(launch_draw(L.D2, N, &st->phi[t - 1], ell, seed, t, inst, fp32_flag_band(d), L.cnt,
-                          L.keep, L.scan_total, L.rs, cap_round, L.cand_point, st, s));
+    if (exact)
+      KMPAR_HIP(launch_exact_round(L.D2, N, (int)ell, seed, t, inst, fp32_flag_band(d), L.ex, L.cnt,
+                                   L.keep, L.scan_total, L.rs, cap_round, L.cand_point, st, s));
+    else
+      KMPAR_HIP(launch_draw(L.D2, N, &st->phi[t - 1], ell, seed, t, inst, fp32_flag_band(d), L.cnt,
+                            L.keep, L.scan_total, L.rs, cap_round, L.cand_point, st, s));
     KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, t, cap_round, L.Call,
                             L.CallT, capT, s));
     fa.rs = L.rs + t;
@@ -862,6 +919,80 @@ int kmpar_lloyd(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dty
     if (phi) KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi + it, s));
     KMPAR_HIP(launch_lloyd_update(dtype, X, row_scale, (int)n, d, fi.A, k, C, L.lw, s));
   }
+  return KMPAR_OK;
+}
+
+int kmpar_kmeanspp(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                   int64_t n, int32_t d, int32_t k, uint64_t seed, float* centers, int32_t* picks,
+                   double* phi, void* ws, size_t ws_bytes, kmpar_stats* stats, void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  int rc = check_common(ctx, X, row_scale, dtype, n, d);
+  if (rc) return rc;
+  if (k < 1 || k > n || k > kMaxK) return set_err(ctx, KMPAR_E_INVAL, "k=%d out of range", k);
+  if (!centers || !aligned16(centers)) return set_err(ctx, KMPAR_E_INVAL, "centers NULL/misaligned");
+  if (picks && !aligned16(picks)) return set_err(ctx, KMPAR_E_INVAL, "picks misaligned");
+  if (phi && ((uintptr_t)phi & 7u)) return set_err(ctx, KMPAR_E_INVAL, "phi misaligned");
+  if (stats && ((uintptr_t)stats & 7u)) return set_err(ctx, KMPAR_E_INVAL, "stats misaligned");
+  if (!ws) return set_err(ctx, KMPAR_E_INVAL, "workspace is NULL");
+  size_t need = 0;
+  rc = kmpar_workspace_size(ctx, KMPAR_OP_KMEANSPP, n, d, k, 1.0, 0, dtype, &need);
+  if (rc) return rc;
+  if (ws_bytes < need)
+    return set_err(ctx, KMPAR_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  if ((rc = device_ready(ctx))) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  KppLayout L = kpp_layout(ws, n, d, k);
+  KMPAR_HIP(launch_kmeanspp(dtype, X, row_scale, (int)n, d, k, seed, 0, L.w, picks ? picks : L.picks,
+                            centers, phi, stats ? stats : L.st, s));
+  return KMPAR_OK;
+}
+
+int kmpar_lloyd_until_stable(kmpar_ctx* ctx, const void* X, const float* row_scale,
+                             kmpar_dtype dtype, int64_t n, int32_t d, float* C, int32_t k,
+                             int32_t max_iters, int32_t* iters, int32_t* assign, double* phi,
+                             void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  if (max_iters < 0) return set_err(ctx, KMPAR_E_INVAL, "max_iters=%d < 0", max_iters);
+  if (!iters) return set_err(ctx, KMPAR_E_INVAL, "iters is NULL");
+  if (assign && !aligned16(assign)) return set_err(ctx, KMPAR_E_INVAL, "assign misaligned");
+  if (phi && ((uintptr_t)phi & 7u)) return set_err(ctx, KMPAR_E_INVAL, "phi misaligned");
+  if (k > n) return set_err(ctx, KMPAR_E_INVAL, "k=%d > n", k);
+  AssignLayout L;
+  FoldArgs fa;
+  int rc = assign_common(ctx, KMPAR_OP_LLOYD, X, row_scale, dtype, n, d, C, k, ws, ws_bytes, &L, &fa);
+  if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  int* cur = L.A;
+  int* prev = L.A2;
+  *iters = max_iters;
+  for (int it = 0; it <= max_iters; ++it) {
+    FoldArgs fi = fa;
+    fi.A = cur;
+    KMPAR_HIP(launch_pad_rows(C, k, d, padded_dim(d), L.Cpad, s));
+    if ((rc = assign_pass(ctx, dtype, L, fi, k, s, it > 0))) return rc;
+    if (phi) KMPAR_HIP(launch_phi(L.D2, (int)n, L.phi_part, phi + it, s));
+    if (it > 0) {
+      // one host read per iteration: the call cannot be captured in a graph
+      KMPAR_HIP(launch_count_changed(cur, prev, (int)n, L.changed, s));
+      int changed = -1;
+      KMPAR_HIP(hipMemcpyAsync(&changed, L.changed, sizeof(int), hipMemcpyDeviceToHost, s));
+      KMPAR_HIP(hipStreamSynchronize(s));
+      if (changed == 0) {
+        *iters = it;
+        break;
+      }
+    }
+    if (it == max_iters) break;
+    KMPAR_HIP(launch_lloyd_update(dtype, X, row_scale, (int)n, d, cur, k, C, L.lw, s));
+    int* t = cur;
+    cur = prev;
+    prev = t;
+  }
+  if (assign) KMPAR_HIP(launch_copy_i32(cur, assign, n, s));
   return KMPAR_OK;
 }
 

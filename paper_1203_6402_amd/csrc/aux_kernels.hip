@@ -244,6 +244,13 @@ hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, ui
   const int nb = (n + kDrawChunk - 1) / kDrawChunk;
   hipLaunchKernelGGL(k_draw_count, dim3(nb), dim3(256), 0, s, D2, n, phi, ell, seed, t, inst, band,
                      cnt, keep, st);
+  return launch_round_compact(n, cnt, keep, scan_total, rs, t, cap_round, cand_point, st, s);
+}
+
+hipError_t launch_round_compact(int n, int* cnt, const uint64_t* keep, int* scan_total, int* rs,
+                                int t, int cap_round, int* cand_point, kmpar_stats* st,
+                                hipStream_t s) {
+  const int nb = (n + kDrawChunk - 1) / kDrawChunk;
   hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, cnt, nb, scan_total);
   hipLaunchKernelGGL(k_round_commit, dim3(1), dim3(64), 0, s, scan_total, rs, t, cap_round, st);
   hipLaunchKernelGGL(k_draw_write, dim3(nb), dim3(256), 0, s, keep, cnt, rs, t, cap_round,

@@ -18,7 +18,7 @@ constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ULL;
 constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ULL;
 constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73BULL;
 
-enum : uint64_t { kTagFirst = 1, kTagRound = 2, kTagRecluster = 3 };
+enum : uint64_t { kTagFirst = 1, kTagRound = 2, kTagRecluster = 3, kTagExact = 4 };
 
 __device__ __forceinline__ uint64_t philox_word0(uint64_t seed, uint64_t tag, uint64_t a,
                                                  uint64_t b, uint64_t inst) {

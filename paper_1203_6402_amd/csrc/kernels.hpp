@@ -155,6 +155,13 @@ hipError_t launch_phi(const float* D2, int n, double* part, double* out, hipStre
 hipError_t launch_draw(const float* D2, int n, const double* phi, double ell, uint64_t seed, int t,
                        uint64_t inst, double band, int* cnt, uint64_t* keep, int* scan_total,
                        int* rs, int cap_round, int* cand_point, kmpar_stats* st, hipStream_t s);
+// The ordered compaction of round t from per-block kept counts cnt[] and
+// keep masks (one bit per point, kDrawChunk points per block): exclusive
+// scan of the counts, commit of the round (rs[t+1] = rs[t] + m_t, capped at
+// cap_round, stats), then the kept point indices in increasing order.
+hipError_t launch_round_compact(int n, int* cnt, const uint64_t* keep, int* scan_total, int* rs,
+                                int t, int cap_round, int* cand_point, kmpar_stats* st,
+                                hipStream_t s);
 // Relative error band of an FP32 direct-form squared distance over d
 // coordinates, doubled: 2 (d + 2) 2^-24.
 __host__ __device__ inline double fp32_flag_band(int d) { return 2.0 * (d + 2) * 0x1.0p-24; }
@@ -211,6 +218,48 @@ struct LloydWs {
 constexpr int kScanTile = 4096;
 hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
                                const int* A, int k, float* C, const LloydWs& w, hipStream_t s);
+
+// Exact-ell rounds and k-means++ by an exponential race (exact.hip).
+// State of one round's radix select of the ell-th smallest key.
+struct ExactState {
+  unsigned long long prefix;  // the key bits fixed so far (after the last level: tau)
+  int need;                   // 1-based rank of the wanted key within the current bucket
+  int m;                      // points the round takes: min(ell, points with D^2 > 0)
+  int tie_need;               // keys equal to tau that are taken
+  int tie_count;              // keys equal to tau
+  int tie_last;               // index of the last key equal to tau taken (INT_MAX: all)
+  int pad;
+};
+struct ExactWs {
+  unsigned long long* keys;  // [n] key bits of the round
+  int* hist;                 // [exact_hist_bins()] zero between rounds
+  ExactState* state;
+};
+size_t exact_keys_bytes(int64_t n);
+int exact_hist_bins();
+// Round t of the exact-ell variant (Section 5.3): the min(ell, #{D^2 > 0})
+// points with the smallest race keys, appended in index order (counts, masks
+// and compaction as launch_draw); keys within `band` of tau are counted in
+// st->flagged_draws.
+hipError_t launch_exact_round(const float* D2, int n, int ell, uint64_t seed, int t, uint64_t inst,
+                              double band, const ExactWs& w, int* cnt, uint64_t* keep,
+                              int* scan_total, int* rs, int cap_round, int* cand_point,
+                              kmpar_stats* st, hipStream_t s);
+struct KppWs {
+  float* D2;                // [n]
+  unsigned long long* pkey; // [ceil(n / 64)] per-block smallest key
+  int* pidx;                // [ceil(n / 64)] its point
+  double* pphi;             // [ceil(n / 64)] per-block FP64 sum of D^2
+  float* crow;              // [d] the latest center
+  int* stop;                // 1 once every point lies on a center
+};
+// k-means++ on all of X (Algorithm 1) with race-key draws: k - 1 steps of
+// one fold + key pass over X and one pick.
+hipError_t launch_kmeanspp(kmpar_dtype dt, const void* X, const float* rsc, int n, int d, int k,
+                           uint64_t seed, uint64_t inst, const KppWs& w, int* picks,
+                           float* centers, double* phi_steps, kmpar_stats* st, hipStream_t s);
+// *out = number of i < n with a[i] != b[i].
+hipError_t launch_count_changed(const int* a, const int* b, int n, int* out, hipStream_t s);
 
 // Batched k-means|| (batched.hip).
 constexpr int kBatchMaxGroups = 24;

@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 MAX_ROUNDS = 64
 F32, BF16, FP8_E4M3 = 0, 1, 2
 MODE_PLAIN_FP32, MODE_REFINED = 0, 1
-OP_INIT, OP_COST, OP_ASSIGN, OP_LLOYD = 0, 1, 2, 3
+OP_INIT, OP_COST, OP_ASSIGN, OP_LLOYD, OP_KMEANSPP = 0, 1, 2, 3, 4
 OK, E_INVAL, E_WORKSPACE, E_HIP, E_TOOFEW, E_OVERFLOW, E_NODEVICE = 0, -1, -2, -3, -4, -5, -6
 
 
@@ -69,6 +69,10 @@ _lib.lloyd_step.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, 
                             _sz, _vp]
 _lib.kmpar_lloyd.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _i32, _vp, _vp,
                              _vp, _sz, _vp]
+_lib.kmpar_kmeanspp.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _i32, _u64, _vp, _vp, _vp,
+                                _vp, _sz, _vp, _vp]
+_lib.kmpar_lloyd_until_stable.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _i32,
+                                          ctypes.POINTER(_i32), _vp, _vp, _vp, _sz, _vp]
 _lib.kmpar_workspace_size_batched.argtypes = [_vp, _vp, _i32, ctypes.c_int, ctypes.POINTER(_sz)]
 _lib.kmpar_init_batched.argtypes = [_vp, _vp, _vp, _i32, ctypes.c_int, _u64, _vp, _sz, _vp, _vp]
 _lib.kmpar_set_option.argtypes = [_vp, ctypes.c_int, _i64]
@@ -82,10 +86,13 @@ EXPORTED = ["kmpar_create", "kmpar_destroy", "kmpar_strerror", "kmpar_last_error
             "kmpar_sizeof_stats", "kmpar_max_candidates", "kmpar_workspace_size", "kmpar_init",
             "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_lloyd", "kmpar_profile_enable",
             "kmpar_profile_read", "kmpar_workspace_size_batched", "kmpar_init_batched",
-            "kmpar_set_option", "kmpar_batch_tiles", "kmpar_cost_noalloc"]
+            "kmpar_set_option", "kmpar_batch_tiles", "kmpar_cost_noalloc", "kmpar_kmeanspp",
+            "kmpar_lloyd_until_stable"]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 OPT_RECLUSTER_PATH = 0
 OPT_BATCH_AUTOTUNE = 1
+OPT_SAMPLING = 2
+SAMPLING_BERNOULLI, SAMPLING_EXACT = 0, 1
 
 # kmpar_instance (include/kmpar.h), 64 bytes.
 INSTANCE_DTYPE = np.dtype([("X", "<u8"), ("row_scale", "<u8"), ("centers", "<u8"), ("stats", "<u8"),
@@ -343,6 +350,52 @@ class Context:
                                     C.data_ptr(), k, _ptr(a), phi.data_ptr(), ws.data_ptr(),
                                     ws.numel(), _stream(stream)), "lloyd_step")
         return a, phi
+
+    @_on_stream
+    def kmeanspp(self, X, k: int, seed: int = 0, row_scale=None, stream=None, check: bool = True,
+                 allow_toofew: bool = False):
+        """kmpar_kmeanspp: k-means++ on all of X.  Returns (centers k x d,
+        picks [k] int32, phi [k]: cost after each pick, stats) -- with check
+        the call synchronises and the outputs are cut to the centers made."""
+        dt = self._x(X, row_scale)
+        n, d = X.shape
+        ws = self._workspace(self.workspace_size(OP_KMEANSPP, n, d, k, dtype=dt), X.device)
+        centers = torch.empty(k, d, dtype=torch.float32, device=X.device)
+        picks = torch.full((k,), -1, dtype=torch.int32, device=X.device)
+        phi = torch.zeros(k, dtype=torch.float64, device=X.device)
+        st = torch.zeros(ctypes.sizeof(Stats), dtype=torch.uint8, device=X.device)
+        self._check(_lib.kmpar_kmeanspp(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d, k, seed,
+                                        centers.data_ptr(), picks.data_ptr(), phi.data_ptr(),
+                                        ws.data_ptr(), ws.numel(), st.data_ptr(),
+                                        _stream(stream)), "kmpar_kmeanspp")
+        if not check:
+            return centers, picks, phi, {"_raw": st}
+        stats = parse_stats(st, 0)
+        check_status(stats["status"], allow_toofew, "kmpar_kmeanspp")
+        m = stats["n_centers"]
+        return centers[:m], picks[:m], phi[:m], stats
+
+    @_on_stream
+    def lloyd_until_stable(self, X, C, max_iters: int, row_scale=None, want_assign=False,
+                           stream=None):
+        """kmpar_lloyd_until_stable: Lloyd until the assignment no longer
+        changes (at most max_iters updates).  Updates C in place; returns
+        (updates made, final assignment|None, phi[updates + 1]).  The call
+        synchronises the stream once per iteration."""
+        dt = self._x(X, row_scale)
+        n, d = X.shape
+        if C.dtype != torch.float32 or not C.is_contiguous():
+            raise ValueError("C must be contiguous float32")
+        k = C.shape[0]
+        ws = self._workspace(self.workspace_size(OP_LLOYD, n, d, k, dtype=dt), X.device)
+        a = torch.empty(n, dtype=torch.int32, device=X.device) if want_assign else None
+        phi = torch.empty(int(max_iters) + 1, dtype=torch.float64, device=X.device)
+        it = _i32(-1)
+        self._check(_lib.kmpar_lloyd_until_stable(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d,
+                                                  C.data_ptr(), k, int(max_iters), ctypes.byref(it),
+                                                  _ptr(a), phi.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                  _stream(stream)), "kmpar_lloyd_until_stable")
+        return int(it.value), a, phi[:int(it.value) + 1]
 
     @_on_stream
     def lloyd(self, X, C, iters: int, row_scale=None, want_assign=False, stream=None):

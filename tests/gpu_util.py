@@ -65,7 +65,7 @@ def gpu_init(ctx, Xdev, k, ell, rounds, seed, row_scale=None):
 
 
 def compare_init(X64, r, tr, k, ell, rounds, seed, inst=0, band=None, d2_rtol=D2_RTOL,
-                 rows_out=None):
+                 rows_out=None, sampling="bernoulli"):
     """Oracle replay of the GPU run; returns the oracle result after checking
     every part of the run against it.  band: the replay's relative error band
     (default: the FP32 direct-form band of the oracle); rows_out: the values
@@ -75,11 +75,12 @@ def compare_init(X64, r, tr, k, ell, rounds, seed, inst=0, band=None, d2_rtol=D2
     st = r.stats
     follow = {"rounds": split_rounds(tr["cand_point"], st["round_count"]),
               "assign": tr["assign"], "picks": tr["center_cand"]}
-    o = O.kmeans_parallel_init(X64, k, ell, rounds, seed, inst=inst, follow=follow, band=band)
+    o = O.kmeans_parallel_init(X64, k, ell, rounds, seed, inst=inst, follow=follow, band=band,
+                               sampling=sampling)
     assert sum(o.bad.values()) == 0, (o.bad, o.flags)
     # A decision that differs from the oracle's lies inside the band, where
     # the GPU counts its own near-ties: it cannot report fewer.
-    if "flagged_draws" in st:
+    if "flagged_draws" in st and sampling == "bernoulli":
         assert st["flagged_draws"] >= o.flags["draw"], (st["flagged_draws"], o.flags)
         assert st["flagged_picks"] >= o.flags["pick"], (st["flagged_picks"], o.flags)
     assert o.round_count == st["round_count"]
