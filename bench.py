@@ -34,7 +34,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 NSTREAMS = 3   # concurrent inits of the extra three-stream measurement
-LEGS = ("c1", "c1lloyd", "c0", "c2", "c3", "c4")
+LEGS = ("c1", "c1lloyd", "c0", "quality", "c2", "c3", "c4")
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_screen_c1.json")
 SCREEN_SRC = os.path.join(ROOT, "paper_1203_6402_amd", "csrc", "screen_mfma.hip")
@@ -205,6 +205,18 @@ def c1_leg(kmpar, synth, torch, args, X):
                          "flagged_draws": rh.stats["flagged_draws"],
                          "flagged_picks": rh.stats["flagged_picks"]}
     log(f"C1 ell=k/2: {msh:.3f} ms/init, |C|={rh.stats['n_candidates']}")
+
+    # The baseline the paper measures k-means|| against (Section 4.2):
+    # k-means++ on all of X, k passes over the data, on the same GPU.
+    kctx = kmpar.Context(0)
+    kctx.kmeanspp(Xd, k, seed=seed)
+    torch.cuda.synchronize()
+    holder = {}
+    mspp = timed_ms(torch, lambda: holder.__setitem__("r", kctx.kmeanspp(Xd, k, seed=seed,
+                                                                         check=False)), 2)
+    out["kmeanspp"] = {"ms": mspp, "passes_over_X": k, "speedup_of_kmeans_par": mspp / ms,
+                       "GBps_X_read": float(n) * d * 4 * k / (mspp / 1e3) / 1e9}
+    log(f"C1 k-means++ (all of X): {mspp:.1f} ms, {mspp / ms:.1f}x the k-means|| init")
     return out
 
 
@@ -272,6 +284,76 @@ def c0_leg(kmpar, synth, torch, seed, iters=20, reps=5):
         log(f"C0 {name}: init {out[f'{name}_init_ms']:.3f} ms, Lloyd "
             f"{out[f'{name}_lloyd_ms_per_iter']:.3f} ms/iter, phi {out[f'{name}_final_phi']:.6g}")
     return out
+
+
+# ------------------------------------------------------------------ quality
+def gauss_runs(kmpar, torch, X, k, method, ell, rounds, seeds, max_iters=500):
+    """Per seed: the seed cost (after the initialisation) and the final cost
+    and number of Lloyd updates after Lloyd's iteration until stable, on the
+    GPU.  method: "kmeanspp" (Algorithm 1 on all of X) or "par" (k-means||,
+    independent draws, ell and rounds as given) or "exact" (exactly ell per
+    round)."""
+    out = []
+    ctx = kmpar.Context(0, kmpar.MODE_REFINED)
+    if method == "exact":
+        ctx.set_option(kmpar.OPT_SAMPLING, kmpar.SAMPLING_EXACT)
+    lctx = kmpar.Context(0, kmpar.MODE_REFINED)
+    for s in seeds:
+        if method == "kmeanspp":
+            C, _, _, st = ctx.kmeanspp(X, k, seed=s)
+        else:
+            C = ctx.init(X, k=k, ell=float(ell), rounds=rounds, seed=s, allow_toofew=True).centers
+        C = C.contiguous().clone()
+        seed_cost = float(lctx.cost(X, C).item())
+        it, _, phi = lctx.lloyd_until_stable(X, C, max_iters)
+        out.append({"seed": s, "centers": int(C.shape[0]), "seed_cost": seed_cost,
+                    "final_cost": float(phi[-1].item()), "lloyd_updates": it})
+    return out
+
+
+def quality_leg(kmpar, synth, torch, seeds=range(11)):
+    """Quality on GaussMixture (n = 10,000, d = 15, k = 50; Section 4.1) by
+    the paper's protocols, every run on the GPU: the Table 1 protocol (median
+    seed and final cost over 11 runs, R in {1, 10, 100}, k-means++ and
+    k-means|| with ell = k/2 and 2k, r = 5), the Figure 5.2 protocol (median
+    final cost against the number of rounds, ell in {k/10, k/2, k, 2k}, R =
+    10) and the Table 6 protocol (mean Lloyd updates to convergence, k in
+    {20, 50, 100}, R = 10, 10 runs)."""
+    import numpy as np
+    n, d, k = 10_000, 15, 50
+    med = lambda runs, key: float(np.median([r[key] for r in runs]))
+    t1 = {}
+    for R in (1.0, 10.0, 100.0):
+        X = torch.from_numpy(synth.gauss_mixture(n, d, k, R, seed=0)).to("cuda:0")
+        row = {}
+        for name, method, ell in (("kmeans++", "kmeanspp", 0), ("kmeans|| l=k/2 r=5", "par", k // 2),
+                                  ("kmeans|| l=2k r=5", "par", 2 * k)):
+            runs = gauss_runs(kmpar, torch, X, k, method, ell, 5, seeds)
+            row[name] = {"seed_median_1e4": med(runs, "seed_cost") / 1e4,
+                         "final_median_1e4": med(runs, "final_cost") / 1e4,
+                         "lloyd_updates_mean": float(np.mean([r["lloyd_updates"] for r in runs]))}
+        t1[f"R={R:g}"] = row
+        log(f"quality Table 1 R={R:g}: " + ", ".join(
+            f"{m} {v['seed_median_1e4']:.1f}/{v['final_median_1e4']:.1f}" for m, v in row.items()))
+    X = torch.from_numpy(synth.gauss_mixture(n, d, k, 10.0, seed=0)).to("cuda:0")
+    f52 = {"kmeans++ final_median_1e4": med(gauss_runs(kmpar, torch, X, k, "kmeanspp", 0, 0, seeds),
+                                             "final_cost") / 1e4}
+    for ell in (k // 10, k // 2, k, 2 * k):
+        f52[f"l={ell}"] = {str(r): med(gauss_runs(kmpar, torch, X, k, "par", ell, r, seeds),
+                                       "final_cost") / 1e4 for r in (1, 2, 3, 5, 8, 12)}
+    log(f"quality Figure 5.2: {f52}")
+    t6 = {}
+    for kk in (20, 50, 100):
+        Xk = torch.from_numpy(synth.gauss_mixture(n, d, kk, 10.0, seed=1)).to("cuda:0")
+        t6[f"k={kk}"] = {
+            name: float(np.mean([r["lloyd_updates"] for r in
+                                 gauss_runs(kmpar, torch, Xk, kk, method, ell, 5, range(10))]))
+            for name, method, ell in (("kmeans++", "kmeanspp", 0),
+                                      ("kmeans|| l=k/2 r=5", "par", kk // 2),
+                                      ("kmeans|| l=2k r=5", "par", 2 * kk))}
+    log(f"quality Table 6: {t6}")
+    return {"workload": "GaussMixture n = 10,000, d = 15 (synthetic), medians over 11 seeds",
+            "table1": t1, "figure5_2_final_median_1e4": f52, "table6_lloyd_updates_mean": t6}
 
 
 # ----------------------------------------------------------------------- C2
@@ -576,6 +658,7 @@ def main():
         c1 = c1_leg(kmpar, synth, torch, args, X)
     c1_lloyd = c1_lloyd_leg(kmpar, torch, c1) if "c1lloyd" in legs else None
     c0 = c0_leg(kmpar, synth, torch, args.seed) if "c0" in legs else None
+    quality = quality_leg(kmpar, synth, torch) if "quality" in legs else None
     c0_trace = c0.pop("_trace") if c0 else None
     if c1 is not None:
         del c1["Xd"], c1["ctx"], c1["r"]
@@ -606,12 +689,14 @@ def main():
                          "flagged_draws": st["flagged_draws"], "flagged_picks": st["flagged_picks"],
                          "graph_replay_ms_per_step": c1["graph_replay_ms"],
                          "three_streams": c1["three_streams"], "ell_half_k": c1["ell_half_k"],
+                         "kmeanspp_same_input": c1["kmeanspp"],
                          "parallelism": "single GPU"}
         out["roofline"] = c1["roofline"]
     out["cpu_baseline"] = cpu
     out["oracle_replay_c0"] = replay
     out["c1_lloyd"] = c1_lloyd
     out["c0_lloyd"] = c0
+    out["quality"] = quality
     out["precision"] = c2
     out["fp8"] = c3
     out["batched"] = c4
