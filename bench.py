@@ -34,7 +34,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 NSTREAMS = 3   # concurrent inits of the extra three-stream measurement
-LEGS = ("c1", "c1lloyd", "c0", "quality", "c2", "c3", "c4")
+LEGS = ("c1", "c1lloyd", "c0", "quality", "largec", "c2", "c3", "c4")
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_screen_c1.json")
 SCREEN_SRC = os.path.join(ROOT, "paper_1203_6402_amd", "csrc", "screen_mfma.hip")
@@ -356,6 +356,37 @@ def quality_leg(kmpar, synth, torch, seeds=range(11)):
             "table1": t1, "figure5_2_final_median_1e4": f52, "table6_lloyd_updates_mean": t6}
 
 
+# ------------------------------------------------------------ large C
+def largec_leg(kmpar, synth, torch, seed):
+    """The candidate-sharded assignment of Section 3.5 on a large center set
+    and few points (KDDCup1999-shaped rows, n = 20,000, d = 42): against
+    m = 16,384 centers (kmpar_assign's limit) one slice per point block and
+    the sharded form, and against m = 1,000,000 centers sharded."""
+    n, d = 20_000, 42
+    X = torch.from_numpy(synth.heavy_tailed(n, d, seed=seed)).to("cuda:0")
+    ctx = kmpar.Context(0)
+    out = {"workload": f"KDDCup1999-shaped rows (synthetic), n = {n}, d = {d}"}
+    for m, shards_list in ((16_384, (1, 8, 64)), (1_000_000, (64, 256))):
+        C = torch.from_numpy(synth.heavy_tailed(m, d, seed=seed + 1)).to("cuda:0")
+        ref = None
+        for sh in shards_list:
+            a, _, _ = ctx.assign_sharded(X, C, sh)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = a
+            assert torch.equal(a, ref)
+            ms = timed_ms(torch, lambda: ctx.assign_sharded(X, C, sh), 3)
+            e = 2.0 * d * n * m / (ms / 1e3) / 1e12
+            out[f"m={m} shards={sh}"] = {"ms": ms, "tflops": e, "frac_fp32": e / PEAK_FP32_VECTOR_TFLOPS}
+            log(f"large C: m={m} shards={sh}: {ms:.2f} ms, {e:.1f} TFLOP/s")
+        if m <= 16_384:
+            a0, _ = ctx.assign(X, C)
+            torch.cuda.synchronize()
+            assert torch.equal(a0, ref)
+            out[f"m={m} kmpar_assign_ms"] = timed_ms(torch, lambda: ctx.assign(X, C), 3)
+    return out
+
+
 # ----------------------------------------------------------------------- C2
 def c2_leg(kmpar, synth, torch, seed, steps=2):
     """BF16-refined vs plain FP32 on the precision workload: n = 16M, d = 128,
@@ -659,6 +690,7 @@ def main():
     c1_lloyd = c1_lloyd_leg(kmpar, torch, c1) if "c1lloyd" in legs else None
     c0 = c0_leg(kmpar, synth, torch, args.seed) if "c0" in legs else None
     quality = quality_leg(kmpar, synth, torch) if "quality" in legs else None
+    largec = largec_leg(kmpar, synth, torch, args.seed) if "largec" in legs else None
     c0_trace = c0.pop("_trace") if c0 else None
     if c1 is not None:
         del c1["Xd"], c1["ctx"], c1["r"]
@@ -697,6 +729,7 @@ def main():
     out["c1_lloyd"] = c1_lloyd
     out["c0_lloyd"] = c0
     out["quality"] = quality
+    out["large_candidate_set"] = largec
     out["precision"] = c2
     out["fp8"] = c3
     out["batched"] = c4

@@ -74,7 +74,8 @@ typedef enum kmpar_op {
   KMPAR_OP_COST = 1,
   KMPAR_OP_ASSIGN = 2,
   KMPAR_OP_LLOYD = 3,    /* lloyd_step, kmpar_lloyd, kmpar_lloyd_until_stable */
-  KMPAR_OP_KMEANSPP = 4  /* kmpar_kmeanspp                                   */
+  KMPAR_OP_KMEANSPP = 4, /* kmpar_kmeanspp                                   */
+  KMPAR_OP_ASSIGN_SHARDED = 5 /* kmpar_assign_sharded (k = m, up to 2^24)     */
 } kmpar_op;
 
 typedef struct kmpar_ctx kmpar_ctx;
@@ -245,6 +246,25 @@ int kmpar_cost_noalloc(kmpar_ctx* ctx, const void* X, const float* row_scale, km
 int kmpar_assign(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
                  int64_t n, int32_t d, const float* C, int32_t m, int32_t* assign, float* d2,
                  void* ws, size_t ws_bytes, void* stream);
+
+/* The nearest of m centers for every point when the center set is large
+ * (Section 3.5, last paragraph: each mapper holds a slice C' of the centers
+ * and emits <x; argmin over C'>, and the reducer takes the minimum): the m
+ * centers [m x d FP32] are cut into `shards` consecutive slices, every
+ * slice is folded over all points concurrently in FP32 direct form, and
+ * each point's (distance, id) minimum over a slice is merged into one
+ * packed 64-bit word per point (distance bits, then id) with an integer
+ * atomic minimum, which keeps the smallest distance and, among equal ones,
+ * the lowest id -- the result of kmpar_assign bit for bit, for m up to
+ * 2^24 (kmpar_assign takes up to 16384).  1 <= shards <= min(m, 256); more
+ * shards put more workgroups on few points.  Outputs: assign [n], d2 [n]
+ * (nullable), phi (device double, nullable) = the cost, summed in FP64 in a
+ * fixed order.  Workspace: kmpar_workspace_size(KMPAR_OP_ASSIGN_SHARDED,
+ * n, d, m, ...). */
+int kmpar_assign_sharded(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                         int64_t n, int32_t d, const float* C, int32_t m, int32_t shards,
+                         int32_t* assign, float* d2, double* phi, void* ws, size_t ws_bytes,
+                         void* stream);
 
 /* One Lloyd iteration (Section 1; Section 3.1): assign every point to its
  * nearest center, then replace each center by the centroid of its points; a

@@ -150,6 +150,26 @@ def nearest(X, C):
     return arg, d2, snd
 
 
+def nearest_sharded(X, C, shards):
+    """Section 3.5, last paragraph: each mapper holds a slice C' of the
+    centers and emits, per point, the nearest center of its slice; the
+    reducer keeps the nearest of those (ties to the lower index, the slices
+    being consecutive).  Returns (argmin, d^2) like ``nearest``."""
+    X, C = _f64(X), _f64(C)
+    m = C.shape[0]
+    best_a = np.full(X.shape[0], -1, np.int64)
+    best_d = np.full(X.shape[0], np.inf)
+    for sh in range(shards):
+        lo, hi = sh * m // shards, (sh + 1) * m // shards
+        if lo == hi:
+            continue
+        a, d2, _ = nearest(X, C[lo:hi])
+        better = d2 < best_d            # a later slice wins only when strictly closer
+        best_a[better] = a[better] + lo
+        best_d[better] = d2[better]
+    return best_a, best_d
+
+
 def cost(X, C) -> float:
     """phi_X(C) (Section 3.1)."""
     return total(nearest(X, C)[1])

@@ -169,6 +169,29 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   return L;
 }
 
+// Workspace of kmpar_assign_sharded.
+struct ShardLayout {
+  float* Cpad;
+  unsigned long long* packed;
+  float* D2;
+  double* phi_part;
+  size_t bytes;
+};
+
+ShardLayout shard_layout(void* ws, int64_t n, int d, int64_t m) {
+  Carver c(ws);
+  ShardLayout L{};
+  L.Cpad = c.take<float>((size_t)m * padded_dim(d));
+  L.packed = c.take<unsigned long long>(n);
+  L.D2 = c.take<float>(n);
+  L.phi_part = c.take<double>((n + kPhiChunk - 1) / kPhiChunk);
+  L.bytes = c.off;
+  return L;
+}
+
+constexpr int64_t kMaxShardedM = (int64_t)1 << 24;
+constexpr int kMaxShards = 256;
+
 // The exact-ell rounds of a context (sized in its workspace); a null
 // context sizes for them.
 bool ctx_exact(const kmpar_ctx* ctx) { return !ctx || ctx->sampling == 1; }
@@ -590,7 +613,8 @@ int kmpar_workspace_size(const kmpar_ctx* cctx, kmpar_op op, int64_t n, int32_t 
   if (!bytes_out) return set_err(ctx, KMPAR_E_INVAL, "bytes_out is NULL");
   if (dtype != KMPAR_F32 && dtype != KMPAR_BF16 && dtype != KMPAR_FP8_E4M3)
     return set_err(ctx, KMPAR_E_INVAL, "unknown dtype");
-  if (n < 1 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 || k > kMaxK)
+  if (n < 1 || n >= (int64_t)1 << 31 || d < 1 || d > kMaxD || k < 1 ||
+      k > (op == KMPAR_OP_ASSIGN_SHARDED ? kMaxShardedM : kMaxK))
     return set_err(ctx, KMPAR_E_INVAL, "size out of range");
   switch (op) {
     case KMPAR_OP_INIT: {
@@ -603,6 +627,9 @@ int kmpar_workspace_size(const kmpar_ctx* cctx, kmpar_op op, int64_t n, int32_t 
       *bytes_out = init_layout(nullptr, n, d, k, ell, rounds, dtype, ctx_exact(ctx)).bytes;
       return KMPAR_OK;
     }
+    case KMPAR_OP_ASSIGN_SHARDED:
+      *bytes_out = shard_layout(nullptr, n, d, k).bytes;
+      return KMPAR_OK;
     case KMPAR_OP_KMEANSPP:
       if (k > n) return set_err(ctx, KMPAR_E_INVAL, "k=%d > n", k);
       *bytes_out = kpp_layout(nullptr, n, d, k).bytes;
@@ -946,6 +973,54 @@ int kmpar_kmeanspp(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_
   KppLayout L = kpp_layout(ws, n, d, k);
   KMPAR_HIP(launch_kmeanspp(dtype, X, row_scale, (int)n, d, k, seed, 0, L.w, picks ? picks : L.picks,
                             centers, phi, stats ? stats : L.st, s));
+  return KMPAR_OK;
+}
+
+int kmpar_assign_sharded(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtype dtype,
+                         int64_t n, int32_t d, const float* C, int32_t m, int32_t shards,
+                         int32_t* assign, float* d2, double* phi, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (!ctx) return KMPAR_E_INVAL;
+  int rc = check_common(ctx, X, row_scale, dtype, n, d);
+  if (rc) return rc;
+  if (m < 1 || m > kMaxShardedM)
+    return set_err(ctx, KMPAR_E_INVAL, "number of centers %d out of range [1, 2^24]", m);
+  if (shards < 1 || shards > kMaxShards || shards > m)
+    return set_err(ctx, KMPAR_E_INVAL, "shards=%d out of range [1, min(m, %d)]", shards, kMaxShards);
+  if (!C || !aligned16(C)) return set_err(ctx, KMPAR_E_INVAL, "C NULL/misaligned");
+  if (!assign || !aligned16(assign)) return set_err(ctx, KMPAR_E_INVAL, "assign NULL/misaligned");
+  if (d2 && !aligned16(d2)) return set_err(ctx, KMPAR_E_INVAL, "d2 misaligned");
+  if (phi && ((uintptr_t)phi & 7u)) return set_err(ctx, KMPAR_E_INVAL, "phi misaligned");
+  if (!ws) return set_err(ctx, KMPAR_E_INVAL, "workspace is NULL");
+  size_t need = 0;
+  rc = kmpar_workspace_size(ctx, KMPAR_OP_ASSIGN_SHARDED, n, d, m, 1.0, 0, dtype, &need);
+  if (rc) return rc;
+  if (ws_bytes < need)
+    return set_err(ctx, KMPAR_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+  if ((rc = device_ready(ctx))) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return hip_fail(ctx, g.e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int DP = padded_dim(d);
+  ShardLayout L = shard_layout(ws, n, d, m);
+  float* D2 = d2 ? d2 : L.D2;
+  KMPAR_HIP(launch_pad_rows(C, m, d, DP, L.Cpad, s));
+  // every packed minimum starts at all-ones (above any distance and id)
+  KMPAR_HIP(launch_fill_i32(reinterpret_cast<int*>(L.packed), -1, 2 * n, s));
+  FoldArgs fa{};
+  fa.X = X;
+  fa.row_scale = row_scale;
+  fa.n = (int)n;
+  fa.d = d;
+  fa.C = L.Cpad;
+  fa.m_host = m;
+  fa.id0_host = 0;
+  fa.first = 1;
+  fa.packed = L.packed;
+  fa.shards = shards;
+  KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
+  KMPAR_HIP(launch_unpack_min(L.packed, (int)n, assign, D2, s));
+  if (phi) KMPAR_HIP(launch_phi(D2, (int)n, L.phi_part, phi, s));
   return KMPAR_OK;
 }
 

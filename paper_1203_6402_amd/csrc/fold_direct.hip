@@ -38,6 +38,12 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
     id0 = a.id0_host;
     m = a.m_host;
   }
+  // candidates [c_lo, c_hi) of this block row's shard (all m unsharded)
+  int c_lo = 0, c_hi = m;
+  if (a.packed) {
+    c_lo = (int)((int64_t)blockIdx.y * m / a.shards);
+    c_hi = (int)((int64_t)(blockIdx.y + 1) * m / a.shards);
+  }
   const float* __restrict__ C = a.C + (int64_t)id0 * DP;
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const float sc = row_scale_of<T>(a.row_scale, i);
@@ -55,7 +61,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
 #pragma unroll
       for (int j = 0; j < DP; ++j) nx = fmaf(x[j], x[j], nx);
     }
-    for (int c = 0; c < m; ++c) {
+    for (int c = c_lo; c < c_hi; ++c) {
       const float* __restrict__ cr = C + (int64_t)c * DP;
       float acc = 0.0f;
 #pragma unroll
@@ -76,7 +82,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
       }
     }
     constexpr int CB = 8;
-    for (int c0 = 0; c0 < m; c0 += CB) {
+    for (int c0 = c_lo; c0 < c_hi; c0 += CB) {
       float acc[CB];
 #pragma unroll
       for (int q = 0; q < CB; ++q) acc[q] = 0.0f;
@@ -90,7 +96,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
         }
 #pragma unroll
         for (int q = 0; q < CB; ++q) {
-          if (c0 + q < m) {
+          if (c0 + q < c_hi) {
             const float* __restrict__ cr = C + (int64_t)(c0 + q) * DP + h * DCH;
 #pragma unroll
             for (int j = 0; j < DCH; ++j) {
@@ -102,7 +108,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
       }
 #pragma unroll
       for (int q = 0; q < CB; ++q) {
-        if (c0 + q < m && acc[q] < best) {
+        if (c0 + q < c_hi && acc[q] < best) {
           best = acc[q];
           bj = c0 + q;
         }
@@ -112,6 +118,14 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
   // All global stores come after the candidate loop: a store before it could
   // alias the candidate rows and force them onto vector loads.
   if (a.norms) a.norms[i] = nx;
+  if (a.packed) {
+    // The reducer's minimum over the shards: distances are non-negative, so
+    // their FP32 bits order as integers, and equal distances keep the lower id.
+    if (bj >= 0)
+      atomicMin(&a.packed[i], ((unsigned long long)__float_as_uint(best) << 32) |
+                                  (unsigned long long)(unsigned)(id0 + bj));
+    return;
+  }
   if (a.first) {
     a.D2[i] = best;
     a.A[i] = bj >= 0 ? id0 + bj : -1;
@@ -482,7 +496,21 @@ template <typename T>
 static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
   const int work = a.list ? a.list_cap : a.n;
   if (work <= 0) return hipSuccess;
-  const dim3 grid((work + kFoldBlock - 1) / kFoldBlock), block(kFoldBlock);
+  if (a.packed && (a.list || a.norms || a.shards < 1)) return hipErrorInvalidValue;
+  const dim3 grid((work + kFoldBlock - 1) / kFoldBlock, a.packed ? a.shards : 1), block(kFoldBlock);
+  if (a.packed) {  // every row length through the one-thread-per-point fold
+    switch (DP) {
+#define KMPAR_SHARD(V) \
+  case V: hipLaunchKernelGGL((k_fold_direct<V, T>), grid, block, 0, s, a); return hipGetLastError();
+      KMPAR_SHARD(4) KMPAR_SHARD(8) KMPAR_SHARD(12) KMPAR_SHARD(16) KMPAR_SHARD(20)
+      KMPAR_SHARD(24) KMPAR_SHARD(28) KMPAR_SHARD(32) KMPAR_SHARD(36) KMPAR_SHARD(40)
+      KMPAR_SHARD(44) KMPAR_SHARD(48) KMPAR_SHARD(52) KMPAR_SHARD(56) KMPAR_SHARD(60)
+      KMPAR_SHARD(64) KMPAR_SHARD(80) KMPAR_SHARD(96) KMPAR_SHARD(112) KMPAR_SHARD(128)
+      KMPAR_SHARD(160) KMPAR_SHARD(192) KMPAR_SHARD(224) KMPAR_SHARD(256)
+#undef KMPAR_SHARD
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (!a.list && !a.norms && DP > 64 && DP <= 128) {
     switch (DP) {
 #define KMPAR_PAIR(V)                                                             \
@@ -519,6 +547,22 @@ static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_unpack_min(const unsigned long long* packed, int n, int* A,
+                                                    float* D2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long v = packed[i];
+  A[i] = (int)(unsigned)(v & 0xFFFFFFFFull);
+  if (D2) D2[i] = __uint_as_float((unsigned)(v >> 32));
+}
+
+hipError_t launch_unpack_min(const unsigned long long* packed, int n, int* A, float* D2,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack_min, dim3((n + 255) / 256), dim3(256), 0, s, packed, n, A, D2);
   return hipGetLastError();
 }
 

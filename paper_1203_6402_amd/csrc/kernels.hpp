@@ -65,12 +65,22 @@ struct FoldArgs {
   int list_cap;          // upper bound of *list_len
   float* norms;          // nullable: also write ||x||^2 (FP32) of every point
   int2* rpart;           // nullable: kRescanMaxItems * kRescanPts slice winners of a split rescan
+  // Candidate-sharded fold (nullable): the m candidates are cut into
+  // `shards` consecutive slices, block row blockIdx.y takes slice
+  // blockIdx.y, and each point's (distance, id) minimum over the slice is
+  // merged into packed[i] = (FP32 bits of the distance) << 32 | id with an
+  // integer atomic minimum instead of being written to D2 / A.
+  unsigned long long* packed;
+  int shards;
 };
 
 constexpr int kRescanPts = 32;        // listed points per rescan block step
 constexpr int kRescanMaxItems = 1024; // rescan grid limit (and slice-winner slots / 32)
 
 hipError_t launch_fold_direct(kmpar_dtype dt, int DP, const FoldArgs& a, hipStream_t s);
+// packed[i] -> A[i] (the id) and, when D2 != nullptr, D2[i] (the distance).
+hipError_t launch_unpack_min(const unsigned long long* packed, int n, int* A, float* D2,
+                             hipStream_t s);
 // Listed points only (a.list, a.list_len, a.list_cap), one wave per point.
 hipError_t launch_rescan(kmpar_dtype dt, int DP, const FoldArgs& a, hipStream_t s);
 

@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 MAX_ROUNDS = 64
 F32, BF16, FP8_E4M3 = 0, 1, 2
 MODE_PLAIN_FP32, MODE_REFINED = 0, 1
-OP_INIT, OP_COST, OP_ASSIGN, OP_LLOYD, OP_KMEANSPP = 0, 1, 2, 3, 4
+OP_INIT, OP_COST, OP_ASSIGN, OP_LLOYD, OP_KMEANSPP, OP_ASSIGN_SHARDED = 0, 1, 2, 3, 4, 5
 OK, E_INVAL, E_WORKSPACE, E_HIP, E_TOOFEW, E_OVERFLOW, E_NODEVICE = 0, -1, -2, -3, -4, -5, -6
 
 
@@ -73,6 +73,8 @@ _lib.kmpar_kmeanspp.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _i32, _
                                 _vp, _sz, _vp, _vp]
 _lib.kmpar_lloyd_until_stable.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _i32,
                                           ctypes.POINTER(_i32), _vp, _vp, _vp, _sz, _vp]
+_lib.kmpar_assign_sharded.argtypes = [_vp, _vp, _vp, ctypes.c_int, _i64, _i32, _vp, _i32, _i32, _vp,
+                                     _vp, _vp, _vp, _sz, _vp]
 _lib.kmpar_workspace_size_batched.argtypes = [_vp, _vp, _i32, ctypes.c_int, ctypes.POINTER(_sz)]
 _lib.kmpar_init_batched.argtypes = [_vp, _vp, _vp, _i32, ctypes.c_int, _u64, _vp, _sz, _vp, _vp]
 _lib.kmpar_set_option.argtypes = [_vp, ctypes.c_int, _i64]
@@ -87,7 +89,7 @@ EXPORTED = ["kmpar_create", "kmpar_destroy", "kmpar_strerror", "kmpar_last_error
             "kmpar_cost", "kmpar_assign", "lloyd_step", "kmpar_lloyd", "kmpar_profile_enable",
             "kmpar_profile_read", "kmpar_workspace_size_batched", "kmpar_init_batched",
             "kmpar_set_option", "kmpar_batch_tiles", "kmpar_cost_noalloc", "kmpar_kmeanspp",
-            "kmpar_lloyd_until_stable"]
+            "kmpar_lloyd_until_stable", "kmpar_assign_sharded"]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 OPT_RECLUSTER_PATH = 0
 OPT_BATCH_AUTOTUNE = 1
@@ -296,6 +298,25 @@ class Context:
                                             C.data_ptr(), C.shape[0], phi.data_ptr(),
                                             _stream(stream)), "kmpar_cost_noalloc")
         return phi
+
+    @_on_stream
+    def assign_sharded(self, X, C, shards: int, row_scale=None, stream=None):
+        """kmpar_assign_sharded: nearest of m (up to 2^24) centers with the
+        centers cut into `shards` slices merged by a packed minimum.
+        Returns (assign, d2, phi)."""
+        dt = self._x(X, row_scale)
+        n, d = X.shape
+        C = C.contiguous().float()
+        m = C.shape[0]
+        ws = self._workspace(self.workspace_size(OP_ASSIGN_SHARDED, n, d, m, dtype=dt), X.device)
+        a = torch.empty(n, dtype=torch.int32, device=X.device)
+        d2 = torch.empty(n, dtype=torch.float32, device=X.device)
+        phi = torch.empty(1, dtype=torch.float64, device=X.device)
+        self._check(_lib.kmpar_assign_sharded(self._h, X.data_ptr(), _ptr(row_scale), dt, n, d,
+                                              C.data_ptr(), m, int(shards), a.data_ptr(),
+                                              d2.data_ptr(), phi.data_ptr(), ws.data_ptr(),
+                                              ws.numel(), _stream(stream)), "kmpar_assign_sharded")
+        return a, d2, phi
 
     @_on_stream
     def assign(self, X, C, row_scale=None, stream=None):

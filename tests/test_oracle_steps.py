@@ -129,3 +129,18 @@ def test_expected_round_size(orc):
         r = orc.kmeans_parallel_init(X, 10, 20.0, 3, seed=100 + s)
         counts.extend(r.round_count[1:])
     assert abs(np.mean(counts) - 20.0) < 4 * np.sqrt(20.0 / len(counts)) + 0.5
+
+
+@pytest.mark.parametrize("shards", [1, 2, 7, 40])
+def test_sharded_nearest_is_the_nearest(orc, shards):
+    # Section 3.5: per-slice argmins reduced by the minimum give the nearest
+    # center over all of them, ties (duplicated centers here) to the lowest id.
+    rng = np.random.default_rng(shards)
+    X = rng.normal(size=(700, 9))
+    C = rng.normal(size=(40, 9))
+    C[25] = C[3]
+    C[31] = C[30]
+    a, d2 = orc.nearest_sharded(X, C, shards)
+    ba, bd, _ = _brute_nearest(X, C)
+    assert np.array_equal(a, ba)
+    np.testing.assert_array_equal(d2, orc.nearest(X, C)[1])
