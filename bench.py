@@ -203,7 +203,8 @@ def c1_leg(kmpar, synth, torch, args, X):
     out["ell_half_k"] = {"ell": ell_h, "ms_per_init": msh, "n_candidates": rh.stats["n_candidates"],
                          "evals_per_s": float(n) * rh.stats["n_candidates"] / (msh / 1e3),
                          "flagged_draws": rh.stats["flagged_draws"],
-                         "flagged_picks": rh.stats["flagged_picks"]}
+                         "flagged_picks": rh.stats["flagged_picks"],
+                         "flagged_argmins": rh.stats["flagged_argmins"]}
     log(f"C1 ell=k/2: {msh:.3f} ms/init, |C|={rh.stats['n_candidates']}")
 
     # The baseline the paper measures k-means|| against (Section 4.2):
@@ -418,6 +419,7 @@ def c2_leg(kmpar, synth, torch, seed, steps=2):
             ctx.profile(False)
             out["flagged_draws"] = rp.stats["flagged_draws"]
             out["flagged_picks"] = rp.stats["flagged_picks"]
+            out["flagged_argmins"] = rp.stats["flagged_argmins"]
             log(f"C2 screen: {out['roofline']['achieved']:.1f} TFLOP/s "
                 f"({100 * out['roofline']['frac']:.1f}% of the bf16 peak)")
         del ctx
@@ -463,6 +465,7 @@ def c3_leg(kmpar, synth, torch, seed, steps=2, with_plain=True, lloyd_iters=10):
     out["rescanned_points"] = rp.stats["n_rescanned"]
     out["flagged_draws"] = rp.stats["flagged_draws"]
     out["flagged_picks"] = rp.stats["flagged_picks"]
+    out["flagged_argmins"] = rp.stats["flagged_argmins"]
     log(f"C3 screen: {out['roofline']['achieved']:.1f} TFLOP/s "
         f"({100 * out['roofline']['frac']:.1f}% of the bf16 peak)")
     if lloyd_iters > 0:
@@ -591,6 +594,7 @@ def cpu_baseline_leg(X, k, ell, rounds, seed, rows, c0):
         replay = {"workload": "GaussMixture n = 10,000, d = 15, k = 50, ell = 2k, r = 5 (REFINED)",
                   "oracle_flagged": o.flags, "oracle_bad": o.bad,
                   "gpu_flagged_draws": st["flagged_draws"], "gpu_flagged_picks": st["flagged_picks"],
+                  "gpu_flagged_argmins": st["flagged_argmins"],
                   "phi_rel_diff": abs(st["phi"][-1] - o.phi[-1]) / o.phi[-1]}
     return base, replay
 
@@ -719,6 +723,7 @@ def main():
                          "n_candidates": st["n_candidates"], "evals_per_step": c1["evals"],
                          "rescanned_points": c1["rescanned_points"],
                          "flagged_draws": st["flagged_draws"], "flagged_picks": st["flagged_picks"],
+                         "flagged_argmins": st["flagged_argmins"],
                          "graph_replay_ms_per_step": c1["graph_replay_ms"],
                          "three_streams": c1["three_streams"], "ell_half_k": c1["ell_half_k"],
                          "kmeanspp_same_input": c1["kmeanspp"],

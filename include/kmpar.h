@@ -104,7 +104,11 @@ typedef struct kmpar_stats {
                                                 end P of the picked interval: the
                                                 masses' FP32 distances could have
                                                 moved it across (step 8)          */
-  int32_t reserved[2];
+  int32_t flagged_argmins;                   /* kmpar_init: points whose second-
+                                                nearest candidate lies within
+                                                (1 + band) D^2 of the nearest
+                                                (step 7; 0 in batched calls)     */
+  int32_t reserved;
 } kmpar_stats;
 
 /* Optional device outputs of kmpar_init for inspection (each may be NULL). */

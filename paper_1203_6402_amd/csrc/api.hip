@@ -85,6 +85,7 @@ struct Carver {
 struct InitLayout {
   float* D2;
   int* A;
+  float* S;  // second-smallest distance per point (flagged argmins)
   double* phi_part;
   int* cnt;
   uint64_t* keep;  // per-round masks of kept points, one bit per point
@@ -102,7 +103,7 @@ struct InitLayout {
   float* norms;
   int* list;
   int* list_len;
-  int2* rescan_part;  // slice winners of a split rescan
+  int4* rescan_part;  // slice winners of a split rescan
   void* B;
   float* ncg;
   float* scg;
@@ -132,6 +133,7 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   InitLayout L;
   L.D2 = c.take<float>(n);
   L.A = c.take<int>(n);
+  L.S = c.take<float>(n);
   L.phi_part = c.take<double>((n + kPhiChunk - 1) / kPhiChunk);
   L.cnt = c.take<int>((n + kDrawChunk - 1) / kDrawChunk + 1);
   L.keep = c.take<uint64_t>((n + kDrawChunk - 1) / kDrawChunk * (kDrawChunk / 64));
@@ -154,7 +156,7 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.norms = c.take<float>(n);
   L.list = c.take<int>(n);
   L.list_len = c.take<int>(4);
-  L.rescan_part = c.take<int2>((size_t)kRescanMaxItems * kRescanPts);
+  L.rescan_part = c.take<int4>((size_t)kRescanMaxItems * kRescanPts);
   L.B = c.take<char>(screen_b_bytes(tiles, d));
   L.ncg = c.take<float>((size_t)tiles * 16);
   L.scg = c.take<float>((size_t)tiles * 16);
@@ -232,7 +234,7 @@ struct AssignLayout {
   float* norms;
   int* list;
   int* list_len;
-  int2* rescan_part;  // slice winners of a split rescan
+  int4* rescan_part;  // slice winners of a split rescan
   void* B;
   float* ncg;
   float* scg;
@@ -269,7 +271,7 @@ AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op, kmpar
     L.norms = c.take<float>(n);
     L.list = c.take<int>(n);
     L.list_len = c.take<int>(4);
-    L.rescan_part = c.take<int2>((size_t)kRescanMaxItems * kRescanPts);
+    L.rescan_part = c.take<int4>((size_t)kRescanMaxItems * kRescanPts);
     L.B = c.take<char>(screen_b_bytes(tiles, d));
     L.ncg = c.take<float>((size_t)tiles * 16);
     L.scg = c.take<float>((size_t)tiles * 16);
@@ -375,7 +377,7 @@ hipError_t timed_fold(kmpar_ctx* ctx, int slot, kmpar_dtype dt, int DP, const Fo
 // B operands, and their scales (scg).
 hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const FoldArgs& fa,
                         int max_tiles, const float* norms, const void* Apre, void* B, float* ncg,
-                        const int* cand, float* scg, int* list, int* list_len, int2* rpart,
+                        const int* cand, float* scg, int* list, int* list_len, int4* rpart,
                         kmpar_stats* st, hipStream_t s) {
   const int KS = screen_ksteps(split, fa.d);
   const float om2g = 1.0f - 2.0f * screen_g(dt, split, fa.d);
@@ -402,6 +404,7 @@ hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const
   sa.oneminus2g = om2g;
   sa.D2 = fa.D2;
   sa.A = fa.A;
+  sa.S = fa.S;
   sa.first = fa.first;
   sa.list = list;
   sa.list_len = list_len;
@@ -690,6 +693,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
 
   // Steps 1-2: first center, D2 against it, psi.
   KMPAR_HIP(launch_first(N, seed, inst, L.cand_point, L.rs, st, s));
+  KMPAR_HIP(launch_fill_i32(reinterpret_cast<int*>(L.S), 0x7F800000, N, s));  // +inf
   KMPAR_HIP(launch_gather(dtype, X, row_scale, d, DP, L.cand_point, L.rs, 0, 1, L.Call, L.CallT,
                           capT, s));
   FoldArgs fa{};
@@ -700,6 +704,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   fa.C = L.Call;
   fa.D2 = L.D2;
   fa.A = L.A;
+  fa.S = L.S;
   fa.rs = L.rs;
   fa.first = 1;
   // The REFINED screen runs on the rounds (m_t ~ ell candidates); the first
@@ -741,6 +746,7 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
   }
   if (refined) KMPAR_HIP(launch_list_reset(L.list_len, st, s));
   KMPAR_HIP(launch_finish_rounds(L.rs, rounds, st, s));
+  KMPAR_HIP(launch_flag_argmins(L.D2, L.S, N, fp32_flag_band(d), st, s));
   // Step 7: weights.
   KMPAR_HIP(launch_hist(L.A, N, L.w, capT, ctx->num_cu, s));
   // Step 8: weighted k-means++.

@@ -29,6 +29,7 @@ __global__ void k_first(int n, uint64_t seed, uint64_t inst, int* cand_point, in
   st->n_rescanned = 0;
   st->flagged_draws = 0;
   st->flagged_picks = 0;
+  st->flagged_argmins = 0;
 }
 
 hipError_t launch_first(int n, uint64_t seed, uint64_t inst, int* cand_point, int* rs,
@@ -255,6 +256,25 @@ hipError_t launch_round_compact(int n, int* cnt, const uint64_t* keep, int* scan
   hipLaunchKernelGGL(k_round_commit, dim3(1), dim3(64), 0, s, scan_total, rs, t, cap_round, st);
   hipLaunchKernelGGL(k_draw_write, dim3(nb), dim3(256), 0, s, keep, cnt, rs, t, cap_round,
                      cand_point);
+  KMPAR_RET_LAST();
+}
+
+// Points whose nearest candidate has a runner-up within the FP32 band:
+// S <= (1 + band) D2 (a tie at zero included).
+__global__ __launch_bounds__(256) void k_flag_argmins(const float* D2, const float* S, int n,
+                                                      double band, kmpar_stats* st) {
+  __shared__ int sh[8];
+  int c = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    c += ((double)S[i] <= (1.0 + band) * (double)D2[i]) ? 1 : 0;
+  const int tot = block_sum<int, 256>(c, sh);
+  if (threadIdx.x == 0 && tot) atomicAdd(&st->flagged_argmins, tot);
+}
+
+hipError_t launch_flag_argmins(const float* D2, const float* S, int n, double band,
+                               kmpar_stats* st, hipStream_t s) {
+  const int grid = std::min((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_flag_argmins, dim3(grid), dim3(256), 0, s, D2, S, n, band, st);
   KMPAR_RET_LAST();
 }
 

@@ -194,6 +194,7 @@ __global__ void kb_first(const kmpar_instance* inst, int count, int rounds, Plan
   st->n_rescanned = 0;
   st->flagged_draws = 0;
   st->flagged_picks = 0;
+  st->flagged_argmins = 0;
 }
 
 // ------------------------------------------------------------------ gather

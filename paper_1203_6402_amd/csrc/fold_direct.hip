@@ -13,6 +13,36 @@
 
 namespace kmpar {
 
+// The fold of one pass into point i's state: (D2, A) move to the pass's
+// best only when strictly closer (ties keep the lower id), and S, when kept,
+// is the second-smallest distance over every candidate met so far.
+__device__ __forceinline__ void fold_apply(const FoldArgs& a, int i, int id0, float best, int bj,
+                                           float second) {
+  if (a.first) {
+    a.D2[i] = best;
+    a.A[i] = bj >= 0 ? id0 + bj : -1;
+    if (a.S) a.S[i] = second;
+  } else if (bj >= 0 && best < a.D2[i]) {
+    if (a.S) a.S[i] = fminf(a.D2[i], second);
+    a.D2[i] = best;
+    a.A[i] = id0 + bj;
+  } else if (bj >= 0 && a.S) {
+    a.S[i] = fminf(a.S[i], best);
+  }
+}
+
+// A candidate at distance acc met in id order: the strictly smaller becomes
+// the best (ties keep the earlier), the other bounds the second smallest.
+__device__ __forceinline__ void keep_two(float acc, int c, float& best, int& bj, float& second) {
+  if (acc < best) {
+    second = best;
+    best = acc;
+    bj = c;
+  } else {
+    second = fminf(second, acc);
+  }
+}
+
 // Rows longer than 128 are processed in two halves so a point never needs
 // more than 128 registers; the sum order over coordinates is the same.
 // One thread per point (or per listed point).  The early exits keep the
@@ -50,7 +80,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
   const int d = a.d;
   const int64_t row = (int64_t)i * d;
 
-  float best = INFINITY;
+  float best = INFINITY, second = INFINITY;
   int bj = -1;
   float nx = 0.0f;  // ||x||^2 when requested; stored after the candidate loop
   if constexpr (NCH == 1) {
@@ -69,10 +99,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
         const float t = x[j] - cr[j];
         acc = fmaf(t, t, acc);
       }
-      if (acc < best) {
-        best = acc;
-        bj = c;
-      }
+      keep_two(acc, c, best, bj, second);
     }
   } else {
     if (a.norms) {
@@ -107,12 +134,8 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
         }
       }
 #pragma unroll
-      for (int q = 0; q < CB; ++q) {
-        if (c0 + q < c_hi && acc[q] < best) {
-          best = acc[q];
-          bj = c0 + q;
-        }
-      }
+      for (int q = 0; q < CB; ++q)
+        if (c0 + q < c_hi) keep_two(acc[q], c0 + q, best, bj, second);
     }
   }
   // All global stores come after the candidate loop: a store before it could
@@ -126,13 +149,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
                                   (unsigned long long)(unsigned)(id0 + bj));
     return;
   }
-  if (a.first) {
-    a.D2[i] = best;
-    a.A[i] = bj >= 0 ? id0 + bj : -1;
-  } else if (bj >= 0 && best < a.D2[i]) {
-    a.D2[i] = best;
-    a.A[i] = id0 + bj;
-  }
+  fold_apply(a, i, id0, best, bj, second);
 }
 
 // Direct-form rescan of the points a screen pass listed.  A block takes 32
@@ -162,23 +179,17 @@ __device__ __forceinline__ int rescan_split(int groups, int grid, bool can_split
   return S;
 }
 
-// Keeps (b, j) as the better of itself and (ob, oj): smaller distance, then
-// lower id (j = -1, no candidate, compares above every id).
-__device__ __forceinline__ void rescan_better(float ob, int oj, float& b, int& j) {
+// Keeps (b, j, s) as the better of itself and (ob, oj, os): smaller
+// distance, then lower id (j = -1, no candidate, compares above every id);
+// s, the second smallest, is the smallest of the rest.
+__device__ __forceinline__ void rescan_better(float ob, int oj, float os, float& b, int& j,
+                                              float& s) {
   if (ob < b || (ob == b && (unsigned)oj < (unsigned)j)) {
+    s = fminf(fminf(s, b), os);
     b = ob;
     j = oj;
-  }
-}
-
-// The fold's update of point p by its best listed-pass candidate.
-__device__ __forceinline__ void rescan_apply(const FoldArgs& a, int p, int id0, float best, int bj) {
-  if (a.first) {
-    a.D2[p] = best;
-    a.A[p] = bj >= 0 ? id0 + bj : -1;
-  } else if (bj >= 0 && best < a.D2[p]) {
-    a.D2[p] = best;
-    a.A[p] = id0 + bj;
+  } else {
+    s = fminf(s, fminf(ob, os));
   }
 }
 
@@ -203,6 +214,7 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
   __shared__ __attribute__((aligned(16))) float cs[CC * CSTR];
   __shared__ float rb[NS][P];
   __shared__ int rj[NS][P];
+  __shared__ float rs2[NS][P];
   const int r = threadIdx.x % P, slot = threadIdx.x / P;
   const int nlist = *a.list_len;
   const int groups = (nlist + P - 1) / P;
@@ -233,7 +245,7 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
       }
       xs[q * XS + e] = v;
     }
-    float best = INFINITY;
+    float best = INFINITY, second = INFINITY;
     int bj = -1;
     const float* xr = xs + r * XS;
     // Candidate chunks go global -> registers -> LDS; the next chunk's loads
@@ -275,19 +287,20 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
         const int j = slot + NS * i;
-        if (j < nc && acc[i] < best) {
-          best = acc[i];
-          bj = c0 + j;
-        }
+        if (j < nc) keep_two(acc[i], c0 + j, best, bj, second);
       }
     }
     rb[slot][r] = best;
     rj[slot][r] = bj;
+    rs2[slot][r] = second;
     __syncthreads();
     if (slot == 0 && r < np) {
-      for (int q = 1; q < NS; ++q) rescan_better(rb[q][r], rj[q][r], best, bj);
-      if (S == 1) rescan_apply(a, a.list[g * P + r], id0, best, bj);
-      else a.rpart[(int64_t)it * P + r] = make_int2(__float_as_int(best), bj);
+      for (int q = 1; q < NS; ++q) rescan_better(rb[q][r], rj[q][r], rs2[q][r], best, bj, second);
+      if (S == 1)
+        fold_apply(a, a.list[g * P + r], id0, best, bj, second);
+      else
+        a.rpart[(int64_t)it * P + r] =
+            make_int4(__float_as_int(best), bj, __float_as_int(second), 0);
     }
   }
 }
@@ -303,13 +316,13 @@ __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
   const int id0 = a.rs ? a.rs[0] : a.id0_host;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < nlist; i += gridDim.x * 256) {
     const int g = i / P, r = i - g * P;
-    float best = INFINITY;
+    float best = INFINITY, second = INFINITY;
     int bj = -1;
     for (int sl = 0; sl < S; ++sl) {
-      const int2 v = a.rpart[(int64_t)(g * S + sl) * P + r];
-      rescan_better(__int_as_float(v.x), v.y, best, bj);
+      const int4 v = a.rpart[(int64_t)(g * S + sl) * P + r];
+      rescan_better(__int_as_float(v.x), v.y, __int_as_float(v.z), best, bj, second);
     }
-    rescan_apply(a, a.list[i], id0, best, bj);
+    fold_apply(a, a.list[i], id0, best, bj, second);
   }
 }
 
@@ -364,6 +377,7 @@ __global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) void k_fold_split(Fol
   for (int j = 0; j < 64; ++j) x[j] = (live && e0 + j < d) ? Elem<T>::get(X, row + e0 + j, sc) : 0.0f;
   float best = INFINITY;
   int bj = -1;
+  float second = INFINITY;
   const int nch = (m + CH - 1) / CH;
   for (int it = 0; it < nch + W - 1; ++it) {
     const int c = it - st;                    // the chunk this stage takes now
@@ -379,10 +393,7 @@ __global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) void k_fold_split(Fol
             const float t = x[e] - cr[e];
             acc = fmaf(t, t, acc);
           }
-          if (acc < best) {
-            best = acc;
-            bj = c0 + jj;
-          }
+          keep_two(acc, c0 + jj, best, bj, second);
         }
       } else {
         for (int jj = 0; jj < nc; ++jj) {
@@ -400,13 +411,7 @@ __global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) void k_fold_split(Fol
     __syncthreads();  // stage outputs of this step visible; inputs of the last step consumed
   }
   if (st != W - 1 || !live) return;
-  if (a.first) {
-    a.D2[i] = best;
-    a.A[i] = bj >= 0 ? id0 + bj : -1;
-  } else if (bj >= 0 && best < a.D2[i]) {
-    a.D2[i] = best;
-    a.A[i] = id0 + bj;
-  }
+  fold_apply(a, i, id0, best, bj, second);
 }
 
 // The fold for rows of 65 to 128 padded elements (no list, no norms), each
@@ -444,7 +449,7 @@ __global__ __launch_bounds__(2 * kFoldBlock) void k_fold_pair(FoldArgs a) {
   float x[64];
 #pragma unroll
   for (int j = 0; j < 64; ++j) x[j] = (live && e0 + j < d) ? Elem<T>::get(X, row + e0 + j, sc) : 0.0f;
-  float best = INFINITY;
+  float best = INFINITY, second = INFINITY;
   int bj = -1;
   const int nch = (m + CH - 1) / CH;
   for (int it = 0; it <= nch; ++it) {
@@ -474,22 +479,13 @@ __global__ __launch_bounds__(2 * kFoldBlock) void k_fold_pair(FoldArgs a) {
           const float t = x[e] - cr[e];
           acc = fmaf(t, t, acc);
         }
-        if (acc < best) {
-          best = acc;
-          bj = c0 + jj;
-        }
+        keep_two(acc, c0 + jj, best, bj, second);
       }
     }
     __syncthreads();  // chunk it written, chunk it - 1 consumed
   }
   if (half == 0 || !live) return;
-  if (a.first) {
-    a.D2[i] = best;
-    a.A[i] = bj >= 0 ? id0 + bj : -1;
-  } else if (bj >= 0 && best < a.D2[i]) {
-    a.D2[i] = best;
-    a.A[i] = id0 + bj;
-  }
+  fold_apply(a, i, id0, best, bj, second);
 }
 
 template <typename T>

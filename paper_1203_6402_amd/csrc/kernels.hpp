@@ -64,7 +64,9 @@ struct FoldArgs {
   const int* list_len;
   int list_cap;          // upper bound of *list_len
   float* norms;          // nullable: also write ||x||^2 (FP32) of every point
-  int2* rpart;           // nullable: kRescanMaxItems * kRescanPts slice winners of a split rescan
+  int4* rpart;           // nullable: kRescanMaxItems * kRescanPts slice winners of a split rescan
+                         // (distance bits, id, second distance bits, unused)
+  float* S;              // nullable: each point's second-smallest distance, kept with D2 / A
   // Candidate-sharded fold (nullable): the m candidates are cut into
   // `shards` consecutive slices, block row blockIdx.y takes slice
   // blockIdx.y, and each point's (distance, id) minimum over the slice is
@@ -104,6 +106,7 @@ struct ScreenArgs {
   float oneminus2g;
   float* D2;
   int* A;
+  float* S;              // nullable: second-smallest distance per point (see screen_body)
   int first;
   int* list;             // points the screen could not settle
   int* list_len;
@@ -185,6 +188,9 @@ __host__ __device__ inline bool pick_near_end(double thr, double lo, double hi, 
   return thr - lo <= b * (thr + lo) || hi - thr <= b * (hi + thr);
 }
 hipError_t launch_finish_rounds(const int* rs, int rounds, kmpar_stats* st, hipStream_t s);
+// st->flagged_argmins += #{i : S[i] <= (1 + band) D2[i]}.
+hipError_t launch_flag_argmins(const float* D2, const float* S, int n, double band,
+                               kmpar_stats* st, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s);
 // Step-7 weights w[0 .. nbins) of the assignment A (an LDS histogram per
 // block while nbins fits a CU's LDS, else global atomics).

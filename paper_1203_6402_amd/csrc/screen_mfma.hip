@@ -670,9 +670,16 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     r1 = refine_dist<T, false>(X + (int64_t)p * d, crow, d, sp);
   }
   if (!valid) return;
+  // S (when kept), the second-smallest distance, is exact wherever it is at
+  // most (1 + band) D2 with band = 2 (d + 2) 2^-24: a bound lb of a
+  // candidate sits at least G S_c below its distance, G >= 2 band, so a
+  // candidate certified by lb >= D (or lb2 > r1) lies beyond that and leaves
+  // S's near-tie status as it was.
   bool listed = false;
   if (!in_range) {
-    listed = D > 0.0f;  // outside the bound's range: the direct form decides
+    // outside the bound's range: the direct form decides (points already at
+    // zero distance too when S is kept, for a tie at zero)
+    listed = D > 0.0f || a.S != nullptr;
   } else if (!refine) {
     if (a.first) {  // m == 0 (never on the paths that call the screen)
       a.D2[p] = INFINITY;
@@ -681,6 +688,7 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     return;
   } else if (r1 < D) {
     if (lb2 > r1) {
+      if (a.S) a.S[p] = D;
       a.D2[p] = r1;
       a.A[p] = id0 + j1;
     } else {
@@ -688,6 +696,8 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     }
   } else if (!(lb2 >= D)) {
     listed = true;
+  } else if (a.S) {
+    a.S[p] = fminf(a.S[p], r1);
   }
   if (listed) {
     const int pos = atomicAdd(a.list_len, 1);

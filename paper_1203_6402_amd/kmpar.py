@@ -38,7 +38,8 @@ class Stats(ctypes.Structure):
                 ("n_rescanned", ctypes.c_int32),
                 ("flagged_draws", ctypes.c_int32),
                 ("flagged_picks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("flagged_argmins", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Trace(ctypes.Structure):
@@ -571,4 +572,4 @@ def parse_stats(st: torch.Tensor, rounds: int) -> dict:
             "round_count": [s.round_count[i] for i in range(rounds + 1)],
             "n_candidates": s.n_candidates, "n_centers": s.n_centers, "status": s.status,
             "n_rescanned": s.n_rescanned, "flagged_draws": s.flagged_draws,
-            "flagged_picks": s.flagged_picks}
+            "flagged_picks": s.flagged_picks, "flagged_argmins": s.flagged_argmins}

@@ -65,12 +65,13 @@ def gpu_init(ctx, Xdev, k, ell, rounds, seed, row_scale=None):
 
 
 def compare_init(X64, r, tr, k, ell, rounds, seed, inst=0, band=None, d2_rtol=D2_RTOL,
-                 rows_out=None, sampling="bernoulli"):
+                 rows_out=None, sampling="bernoulli", argmins=True):
     """Oracle replay of the GPU run; returns the oracle result after checking
     every part of the run against it.  band: the replay's relative error band
     (default: the FP32 direct-form band of the oracle); rows_out: the values
     the library returns as center rows when they differ from the oracle's
-    input X64 (FP8 rows fed to the oracle as exact products)."""
+    input X64 (FP8 rows fed to the oracle as exact products); argmins: the
+    run counts its near-tied argmins (single-instance calls)."""
     d = X64.shape[1]
     st = r.stats
     follow = {"rounds": split_rounds(tr["cand_point"], st["round_count"]),
@@ -83,6 +84,15 @@ def compare_init(X64, r, tr, k, ell, rounds, seed, inst=0, band=None, d2_rtol=D2
     if "flagged_draws" in st and sampling == "bernoulli":
         assert st["flagged_draws"] >= o.flags["draw"], (st["flagged_draws"], o.flags)
         assert st["flagged_picks"] >= o.flags["pick"], (st["flagged_picks"], o.flags)
+    if argmins:
+        assert st["flagged_argmins"] >= o.flags["argmin"], (st["flagged_argmins"], o.flags)
+        n, m = X64.shape[0], o.cand_point.size
+        if n * m * d <= 2e9:
+            # A runner-up more than twice the band away is never flagged: the
+            # FP32 direct form moves each distance by less than band / 2
+            # (2.01: the second-order terms).
+            _, d2, snd = O.nearest(X64, X64[o.cand_point])
+            assert st["flagged_argmins"] <= int(np.sum(snd - d2 <= 2.01 * O.fp32_band(d) * d2))
     assert o.round_count == st["round_count"]
     assert np.array_equal(o.cand_point, tr["cand_point"])
     assert np.array_equal(o.weights, tr["cand_weight"])

@@ -29,7 +29,7 @@ def _replay_all(Xs64, cs, sts, trs, ks, ells, rounds, seed):
         assert st["status"] == 0, (i, st)
         tr = {key: v.cpu().numpy() for key, v in trs[i].items()}
         r = SimpleNamespace(stats=st, centers=cs[i])
-        compare_init(X64, r, tr, int(ks[i]), float(ells[i]), rounds, seed, inst=i)
+        compare_init(X64, r, tr, int(ks[i]), float(ells[i]), rounds, seed, inst=i, argmins=False)
         assert tr["cand_weight"].sum() == X64.shape[0]
 
 
@@ -61,7 +61,7 @@ def test_batched_c4_draw_sample_matches_oracle(ctx):
         tr = {key: v.cpu().numpy() for key, v in trs[i].items()}
         r = SimpleNamespace(stats=sts[i], centers=cs[i])
         compare_init(Xs[i].cpu().numpy().astype(np.float64), r, tr, int(ks[i]), float(ells[i]), 5, 0,
-                     inst=int(i))
+                     inst=int(i), argmins=False)
 
 
 def test_batched_bf16_and_ragged_dims(ctx):

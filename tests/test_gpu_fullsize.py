@@ -76,6 +76,7 @@ def test_c1_kdd_shaped_full_size(K, ell):
     assert torch.equal(a.centers, b.centers)
     for key in a.trace:
         assert torch.equal(a.trace[key], b.trace[key]), key
+    assert a.stats["flagged_argmins"] == b.stats["flagged_argmins"]
     st = b.stats
     assert st["status"] == 0 and st["n_centers"] == k
     tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
@@ -87,7 +88,7 @@ def test_c1_kdd_shaped_full_size(K, ell):
     print(f"C1 ell={ell:g}: oracle replay of all {n} points", flush=True)
     o = compare_init(X.astype(np.float64), b, tr, k, ell, rounds, seed)
     print(f"C1 ell={ell:g}: flagged {o.flags}, GPU counted draws {st['flagged_draws']} "
-          f"picks {st['flagged_picks']}", flush=True)
+          f"picks {st['flagged_picks']} argmins {st['flagged_argmins']}", flush=True)
 
 
 def test_c2_precision_full_size(K):
@@ -102,6 +103,7 @@ def test_c2_precision_full_size(K):
     assert torch.equal(a.centers, b.centers)
     for key in a.trace:
         assert torch.equal(a.trace[key], b.trace[key]), key
+    assert a.stats["flagged_argmins"] == b.stats["flagged_argmins"]
     st = b.stats
     assert st["status"] == 0 and st["n_centers"] == k
     tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
@@ -135,6 +137,7 @@ def test_c3_fp8_full_size(K):
     assert torch.equal(a.centers, b.centers)
     for key in a.trace:
         assert torch.equal(a.trace[key], b.trace[key]), key
+    assert a.stats["flagged_argmins"] == b.stats["flagged_argmins"]
     st = b.stats
     assert st["status"] == 0 and st["n_centers"] == k
     assert st["n_rescanned"] <= 0.02 * n * rounds

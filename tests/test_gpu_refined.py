@@ -171,3 +171,23 @@ def test_refined_heavy_tailed_large_norm_gap(plain, refined):
     b = refined.init(Xd, k=100, ell=200.0, rounds=5, seed=7, trace=True)
     torch.cuda.synchronize()
     _same_init(a, b)
+
+
+@pytest.mark.parametrize("d,span", [(4, 6), (20, 3)])
+def test_flagged_argmins_on_integer_lattice(plain, refined, d, span):
+    # Integer coordinates make every FP32 distance exact, so a runner-up
+    # within the band is an exact tie: the count of flagged argmins is the
+    # number of points whose two nearest candidates are equally far (a tie
+    # at zero included), in both modes.
+    X = np.random.default_rng(11).integers(-span, span + 1, size=(6000, d)).astype(np.float32)
+    Xd = _dev(X)
+    a = plain.init(Xd, k=20, ell=60.0, rounds=4, seed=3, trace=True)
+    b = refined.init(Xd, k=20, ell=60.0, rounds=4, seed=3, trace=True)
+    torch.cuda.synchronize()
+    _same_init(a, b)
+    tr = {key: v.cpu().numpy() for key, v in b.trace.items()}
+    X64 = X.astype(np.float64)
+    o = compare_init(X64, b, tr, 20, 60.0, 4, 3)
+    _, d2, snd = O.nearest(X64, X64[o.cand_point])
+    ties = int(np.sum(snd == d2))
+    assert ties > 0 and b.stats["flagged_argmins"] == ties
