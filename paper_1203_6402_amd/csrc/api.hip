@@ -112,11 +112,6 @@ struct InitLayout {
   size_t bytes;
 };
 
-// Screen operand buffers for up to `tiles` tiles of 16 candidates.
-size_t screen_b_bytes(int tiles, int d) {
-  return (size_t)tiles * screen_ksteps(3, d) * 64 * 16;  // the widest split
-}
-
 // Bytes of prepared A operands for the screen of this dtype (0 if unused).
 size_t a_bytes(kmpar_dtype dt, bool rows, int64_t n, int d) {
   if (!screen_supported(dt, rows, d)) return 0;
@@ -256,7 +251,7 @@ AssignLayout assign_layout(void* ws, int64_t n, int d, int k, kmpar_op op, kmpar
   L.Cpad = c.take<float>((size_t)k * DP);
   if (op == KMPAR_OP_LLOYD) {
     const int64_t nbs = (n + kSortChunk - 1) / kSortChunk;
-    const int64_t Lt = (int64_t)k * nbs;
+    const int64_t Lt = (int64_t)(k + 1) * nbs;  // keys 0 .. k (k: no valid center)
     L.lw.bcnt = c.take<int>(Lt);
     L.lw.scan_tmp = c.take<int>((Lt + kScanTile - 1) / kScanTile + 1);
     L.lw.sorted = c.take<int>(n);

@@ -800,7 +800,10 @@ hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, cons
 
 // ------------------------------------------------------------- Lloyd update
 // Deterministic centroid update (Section 3.1 centroid; Section 1 Lloyd):
-//  1. per-block cluster counts   bcnt[c * nbs + b]
+//  1. per-block cluster counts   bcnt[c * nbs + b], c = 0 .. k, where key k
+//     collects the points without a valid center (an assignment outside
+//     [0, k), which only a point with no finite distance gets): they are
+//     sorted behind every cluster and summed into none
 //  2. exclusive scan of the flattened table -> each (cluster, block) slot
 //  3. stable scatter of point indices into cluster-sorted order
 //  4. cluster chunks of kSegChunk sorted points, each split into fixed
@@ -810,21 +813,21 @@ hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, cons
 //     chunk order, the slices then in slice order; divided by the count.
 // Every sum runs in an order fixed by (n, d, k, assignment) alone, so the
 // update is reproducible run to run.
+// The sort key of an assignment: the cluster, or k for none.
+__device__ __forceinline__ int sort_key(int a, int k) { return (a >= 0 && a < k) ? a : k; }
+
 __global__ __launch_bounds__(256) void k_sort_count(const int* A, int n, int k, int* bcnt,
                                                     int nbs) {
-  extern __shared__ int h[];
-  for (int c = threadIdx.x; c < k; c += 256) h[c] = 0;
+  extern __shared__ int h[];  // k + 1 keys
+  for (int c = threadIdx.x; c <= k; c += 256) h[c] = 0;
   __syncthreads();
   const int base = blockIdx.x * kSortChunk;
   for (int r = threadIdx.x; r < kSortChunk; r += 256) {
     const int i = base + r;
-    if (i < n) {
-      const int a = A[i];
-      if (a >= 0 && a < k) atomicAdd(&h[a], 1);
-    }
+    if (i < n) atomicAdd(&h[sort_key(A[i], k)], 1);
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < k; c += 256) bcnt[(int64_t)c * nbs + blockIdx.x] = h[c];
+  for (int c = threadIdx.x; c <= k; c += 256) bcnt[(int64_t)c * nbs + blockIdx.x] = h[c];
 }
 
 // Three-phase exclusive scan of a[0..L): tile sums, scan of the tile sums,
@@ -858,16 +861,16 @@ __global__ __launch_bounds__(256) void k_scan_apply(int* a, int64_t L, const int
 // One wave per block scatters its chunk in point order, a 64-point tile at a
 // time; the keys of kSortAhead tiles are loaded before the first of them is
 // placed. The lanes holding the same key are found with one ballot per key bit
-// (nbits = bits of k - 1); a lane's slot is its key's cursor plus the number
-// of lower lanes with that key, and the highest such lane advances the cursor
-// by the group's size once every lane has read it.
-constexpr int kSortAhead = 16;
+// (nbits = bits of k, keys 0 .. k); a lane's slot is its key's cursor plus the
+// number of lower lanes with that key, and the highest such lane advances the
+// cursor by the group's size once every lane has read it.  Every point of
+// the chunk gets a slot, so sorted[0 .. n) is written whole.
 static_assert(kSortChunk % (64 * kSortAhead) == 0, "sort chunk must hold whole key batches");
 
 __global__ __launch_bounds__(64) void k_sort_scatter(const int* A, int n, int k, int nbits,
                                                      const int* bbase, int nbs, int* sorted) {
-  extern __shared__ int cur[];
-  for (int c = threadIdx.x; c < k; c += 64) cur[c] = bbase[(int64_t)c * nbs + blockIdx.x];
+  extern __shared__ int cur[];  // k + 1 keys
+  for (int c = threadIdx.x; c <= k; c += 64) cur[c] = bbase[(int64_t)c * nbs + blockIdx.x];
   __syncthreads();
   const int base = blockIdx.x * kSortChunk;
   for (int t0 = 0; t0 < kSortChunk && base + t0 < n; t0 += 64 * kSortAhead) {
@@ -875,7 +878,7 @@ __global__ __launch_bounds__(64) void k_sort_scatter(const int* A, int n, int k,
 #pragma unroll
     for (int u = 0; u < kSortAhead; ++u) {
       const int i = base + t0 + u * 64 + threadIdx.x;
-      keys[u] = (i < n) ? A[i] : -1;
+      keys[u] = (i < n) ? sort_key(A[i], k) : -1;
     }
 #pragma unroll
     for (int u = 0; u < kSortAhead; ++u) {
@@ -883,7 +886,7 @@ __global__ __launch_bounds__(64) void k_sort_scatter(const int* A, int n, int k,
       if (i0 >= n) break;
       const int i = i0 + threadIdx.x;
       const int key0 = keys[u];
-      const bool valid = key0 >= 0 && key0 < k;
+      const bool valid = key0 >= 0;  // i < n
       const int key = valid ? key0 : 0;
       uint64_t grp = __ballot(valid);
       for (int b = 0; b < nbits; ++b) {
@@ -903,7 +906,8 @@ __global__ __launch_bounds__(64) void k_sort_scatter(const int* A, int n, int k,
 }
 
 // Cluster offsets and the chunk list: cluster c owns sorted positions
-// [coff[c], coff[c+1]) split into chunks cstart[c] .. cstart[c+1]-1.
+// [coff[c], coff[c+1]) split into chunks cstart[c] .. cstart[c+1]-1; coff[k]
+// is where the points without a valid center begin (n when there are none).
 __global__ __launch_bounds__(1024) void k_chunk_list(const int* bbase, int nbs, int k, int n,
                                                      int* coff, int* cstart) {
   __shared__ long long sh[17];
@@ -912,7 +916,7 @@ __global__ __launch_bounds__(1024) void k_chunk_list(const int* bbase, int nbs, 
   long long s = 0;
   for (int c = lo; c < hi; ++c) {
     const int o = bbase[(int64_t)c * nbs];
-    const int o1 = (c + 1 < k) ? bbase[(int64_t)(c + 1) * nbs] : n;
+    const int o1 = bbase[(int64_t)(c + 1) * nbs];
     coff[c] = o;
     s += (o1 - o + kSegChunk - 1) / kSegChunk;
   }
@@ -920,24 +924,16 @@ __global__ __launch_bounds__(1024) void k_chunk_list(const int* bbase, int nbs, 
   long long run = block_excl_scan<long long, 1024>(s, sh, &tot);
   for (int c = lo; c < hi; ++c) {
     const int o = bbase[(int64_t)c * nbs];
-    const int o1 = (c + 1 < k) ? bbase[(int64_t)(c + 1) * nbs] : n;
+    const int o1 = bbase[(int64_t)(c + 1) * nbs];
     cstart[c] = (int)run;
     run += (o1 - o + kSegChunk - 1) / kSegChunk;
   }
   if (threadIdx.x == 0) {
-    coff[k] = n;
+    coff[k] = bbase[(int64_t)k * nbs];
     cstart[k] = (int)tot;
   }
 }
 
-constexpr int kSegAhead = 16;  // rows whose loads a slice issues before adding them
-
-// Lanes per slice row: the power of two covering d, at most 64.
-__host__ __device__ __forceinline__ int seg_width(int d) {
-  int w = 1;
-  while (w < d && w < 64) w <<= 1;
-  return w;
-}
 
 // Block q sums chunk q of its cluster: 256 threads form 256 / DW slices of DW
 // lanes (lane = element), slice s owns the s-th of that many consecutive
@@ -1039,14 +1035,20 @@ __global__ __launch_bounds__(256) void k_centroid(const double* part, const int*
 hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
                                const int* A, int k, float* C, const LloydWs& w, hipStream_t s) {
   const int nbs = (n + kSortChunk - 1) / kSortChunk;
-  const int64_t L = (int64_t)k * nbs;
+  const int64_t L = (int64_t)(k + 1) * nbs;  // keys 0 .. k
   const int ntiles = (int)((L + kScanTile - 1) / kScanTile);
-  const size_t lds = (size_t)k * sizeof(int);
+  const size_t lds = (size_t)(k + 1) * sizeof(int);
+  hipError_t e = hipFuncSetAttribute((const void*)k_sort_count,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_sort_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sort_count, dim3(nbs), dim3(256), lds, s, A, n, k, w.bcnt, nbs);
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, w.bcnt, L, w.scan_tmp);
   hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, w.scan_tmp, ntiles, (int*)nullptr);
   hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(256), 0, s, w.bcnt, L, w.scan_tmp);
-  const int nbits = k > 1 ? 32 - __builtin_clz((unsigned)(k - 1)) : 0;
+  const int nbits = 32 - __builtin_clz((unsigned)k);  // bits of the largest key, k
   hipLaunchKernelGGL(k_sort_scatter, dim3(nbs), dim3(64), lds, s, A, n, k, nbits, w.bcnt, nbs,
                      w.sorted);
   hipLaunchKernelGGL(k_chunk_list, dim3(1), dim3(1024), 0, s, w.bcnt, nbs, k, n, w.coff, w.cstart);

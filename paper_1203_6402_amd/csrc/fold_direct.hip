@@ -169,8 +169,6 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
 // grid), one block per (group, slice); the slices' winners go to a.rpart and
 // k_rescan_merge combines them in slice order by (distance, id), the same
 // decision. Both kernels derive S from the device-side list length alone.
-constexpr int kRescanCands = 32;  // candidate rows per LDS chunk
-constexpr int kRescanMaxSplit = 8;
 
 __device__ __forceinline__ int rescan_split(int groups, int grid, bool can_split) {
   int S = 1;

@@ -1,0 +1,109 @@
+// Launch and buffer geometry of the kernels: block shapes, chunk sizes and
+// buffer extents as plain integer functions.  The kernels, the workspace
+// layouts and the host-side address checker all take them from here, so
+// this header holds no HIP types and compiles as ordinary C++.
+#pragma once
+
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __HIPCC__
+#define KMPAR_HD __host__ __device__
+#else
+#define KMPAR_HD
+#endif
+
+namespace kmpar {
+
+// Padded row length used for candidate / center rows (zeros past d).
+KMPAR_HD inline int padded_dim_hd(int d) {
+  if (d <= 64) return (d + 3) / 4 * 4;
+  if (d <= 128) return (d + 15) / 16 * 16;
+  return (d + 31) / 32 * 32;
+}
+
+// Integer square root (floor), identical on host and device.
+KMPAR_HD inline int64_t isqrt64(int64_t v) {
+  int64_t r = 0;
+  for (int64_t b = (int64_t)1 << 31; b > 0; b >>= 1)
+    if ((r + b) * (r + b) <= v) r += b;
+  return r;
+}
+
+// Per-round candidate capacity min(n, L + 12 isqrt(L) + 76), L = ceil(ell):
+// at least ell + 12 sqrt(ell) + 64, i.e. more than 12 standard deviations
+// above the expected ell kept points (Section 3.3).  Integer arithmetic, so
+// host planning and device kernels agree exactly.
+KMPAR_HD inline int64_t cap_round_hd(int64_t n, double ell) {
+  const double c = ceil(ell);
+  if (!(c < 4.0e18)) return n;
+  const int64_t L = (int64_t)c;
+  const int64_t cap = L + 12 * isqrt64(L) + 76;
+  return cap < n ? cap : n;
+}
+
+// Point tile of the direct-form distance pass and the other chunked passes.
+constexpr int kFoldBlock = 256;
+constexpr int kPhiChunk = 4096;    // points per block of the phi reduction
+constexpr int kDrawChunk = 2048;   // points per block of the draw passes
+constexpr int kSortChunk = 4096;   // points per block of the Lloyd counting sort
+constexpr int kSegChunk = 2048;    // sorted points per block of the centroid sums
+constexpr int kScanTile = 4096;    // elements per tile of the three-phase scan
+constexpr int kSortAhead = 16;     // 64-point key tiles loaded ahead by the scatter
+constexpr int kSegAhead = 16;      // rows whose loads a centroid slice issues ahead
+
+// Lanes per slice row of the centroid sums: the power of two covering d, at
+// most 64.
+KMPAR_HD inline int seg_width(int d) {
+  int w = 1;
+  while (w < d && w < 64) w <<= 1;
+  return w;
+}
+
+// Rescan of listed points: points per block step, grid limit (and slice-
+// winner slots / kRescanPts), candidate rows per LDS chunk, most slices.
+constexpr int kRescanPts = 32;
+constexpr int kRescanMaxItems = 1024;
+constexpr int kRescanCands = 32;
+constexpr int kRescanMaxSplit = 8;
+
+// ------------------------------------------------------------ the screen
+// Largest number of 32-wide k-steps of the screen's operands.
+constexpr int kScreenMaxKS = 16;
+constexpr int kWaves = 4;               // waves per screen block
+constexpr int kStageBytes = 32 * 1024;  // LDS per candidate staging buffer
+// LDS bytes each wave reuses after the pass (a quarter of the two buffers).
+constexpr int kWaveStage = kStageBytes * 2 / kWaves;
+// 16-point row tiles per wave: four while the A operands of KS k-steps fit
+// the registers beside the accumulators and running maxima, two beyond 8.
+// Rows with scales spend more registers per value (row scales, the scaled
+// epilogue): two row tiles from five k-steps on.
+constexpr int screen_krt(int KS, bool scaled) {
+  return scaled ? (KS <= 4 ? 4 : 2) : (KS <= 8 ? 4 : 2);
+}
+constexpr int kBlockPts = kWaves * 4 * 16;  // the largest block (256 points)
+// Candidate tiles per LDS chunk for KS k-steps, chunks per tag group (groups
+// of up to 16 tiles), and the tag bits that number a tile within its group.
+constexpr int screen_chunk_tiles(int KS) { return kStageBytes / (KS * 64 * 16); }
+constexpr int screen_group_chunks(int KS) {
+  return screen_chunk_tiles(KS) >= 16 ? 1 : 16 / screen_chunk_tiles(KS);
+}
+constexpr int screen_tag_bits(int KS) {
+  int b = 0;
+  while ((1 << b) < screen_group_chunks(KS) * screen_chunk_tiles(KS)) ++b;
+  return b;
+}
+// K axis of a split-term operand: SPLIT copies of d, in 32-wide k-steps.
+constexpr int screen_ksteps(int split, int d) { return split ? (split * d + 31) / 32 : 0; }
+// Prepared A operands: every tile of 16 points of whole 256-point blocks.
+inline size_t screen_a_bytes(int n, int KS) {
+  const size_t tiles = (size_t)(n + kBlockPts - 1) / kBlockPts * (kBlockPts / 16);
+  return tiles * KS * 64 * 16;
+}
+// B operands for up to `tiles` tiles of 16 candidates at the widest split.
+inline size_t screen_b_bytes(int tiles, int d) {
+  return (size_t)tiles * screen_ksteps(3, d) * 64 * 16;
+}
+
+}  // namespace kmpar

@@ -8,43 +8,11 @@
 #include <map>
 
 #include "../../include/kmpar.h"
+#include "geometry.hpp"
 
 namespace kmpar {
 
-// Padded row length used for candidate / center rows (zeros past d).
-__host__ __device__ inline int padded_dim_hd(int d) {
-  if (d <= 64) return (d + 3) / 4 * 4;
-  if (d <= 128) return (d + 15) / 16 * 16;
-  return (d + 31) / 32 * 32;
-}
 inline int padded_dim(int d) { return padded_dim_hd(d); }
-
-// Integer square root (floor), identical on host and device.
-__host__ __device__ inline int64_t isqrt64(int64_t v) {
-  int64_t r = 0;
-  for (int64_t b = (int64_t)1 << 31; b > 0; b >>= 1)
-    if ((r + b) * (r + b) <= v) r += b;
-  return r;
-}
-
-// Per-round candidate capacity min(n, L + 12 isqrt(L) + 76), L = ceil(ell):
-// at least ell + 12 sqrt(ell) + 64, i.e. more than 12 standard deviations
-// above the expected ell kept points (Section 3.3).  Integer arithmetic, so
-// host planning and device kernels agree exactly.
-__host__ __device__ inline int64_t cap_round_hd(int64_t n, double ell) {
-  const double c = ceil(ell);
-  if (!(c < 4.0e18)) return n;
-  const int64_t L = (int64_t)c;
-  const int64_t cap = L + 12 * isqrt64(L) + 76;
-  return cap < n ? cap : n;
-}
-
-// Point tile of the direct-form distance pass and the other chunked passes.
-constexpr int kFoldBlock = 256;
-constexpr int kPhiChunk = 4096;    // points per block of the phi reduction
-constexpr int kDrawChunk = 2048;   // points per block of the draw passes
-constexpr int kSortChunk = 4096;   // points per block of the Lloyd counting sort
-constexpr int kSegChunk = 2048;    // sorted points per block of the centroid sums
 
 // Parameters of one distance-fold pass: every listed point meets the m
 // candidate rows C[id0 .. id0+m) (DP-padded FP32) and keeps the nearest.
@@ -75,9 +43,6 @@ struct FoldArgs {
   unsigned long long* packed;
   int shards;
 };
-
-constexpr int kRescanPts = 32;        // listed points per rescan block step
-constexpr int kRescanMaxItems = 1024; // rescan grid limit (and slice-winner slots / 32)
 
 hipError_t launch_fold_direct(kmpar_dtype dt, int DP, const FoldArgs& a, hipStream_t s);
 // packed[i] -> A[i] (the id) and, when D2 != nullptr, D2[i] (the distance).
@@ -114,22 +79,7 @@ struct ScreenArgs {
 };
 
 int screen_split(kmpar_dtype dt, bool centers_are_rows);
-int screen_ksteps(int split, int d);
 bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d);
-// Largest number of 32-wide k-steps of the screen's operands.
-constexpr int kScreenMaxKS = 16;
-// Candidate tiles per LDS chunk of the screen for KS k-steps, chunks per tag
-// group (groups of up to 16 tiles), and the tag bits that number a tile
-// within its group.
-constexpr int screen_chunk_tiles(int KS) { return (32 * 1024) / (KS * 64 * 16); }
-constexpr int screen_group_chunks(int KS) {
-  return screen_chunk_tiles(KS) >= 16 ? 1 : 16 / screen_chunk_tiles(KS);
-}
-constexpr int screen_tag_bits(int KS) {
-  int b = 0;
-  while ((1 << b) < screen_group_chunks(KS) * screen_chunk_tiles(KS)) ++b;
-  return b;
-}
 // Error constant G of the screen's lower bound.
 float screen_g(kmpar_dtype dt, int split, int d);
 // B operands of the candidates C[rs[0] ..) (or C[0 .. m_host)), their biases
@@ -141,7 +91,6 @@ hipError_t launch_prep_b(kmpar_dtype dt, int split, int KS, const float* C, int 
                          hipStream_t s);
 hipError_t launch_screen(kmpar_dtype dt, int split, int KS, const ScreenArgs& a, hipStream_t s);
 bool screen_a_direct(kmpar_dtype dt, int split, int d);
-size_t screen_a_bytes(int n, int KS);
 // The screen's A operands and, when norms != nullptr, ||x||^2, from one read of X.
 hipError_t launch_prep_a(kmpar_dtype dt, int split, int KS, const void* X, const float* rsc, int n,
                          int d, float* norms, void* Apre, hipStream_t s);
@@ -224,14 +173,13 @@ hipError_t launch_copy_i32(const int* src, int* dst, int64_t count, hipStream_t 
 
 // Lloyd centroid update by a deterministic counting sort.
 struct LloydWs {
-  int* bcnt;      // k * nbs
-  int* scan_tmp;  // ceil(k*nbs / kScanTile) + 1
+  int* bcnt;      // (k + 1) * nbs: clusters 0 .. k-1, then points with no valid center
+  int* scan_tmp;  // ceil((k + 1) * nbs / kScanTile) + 1
   int* sorted;    // n
   int* cstart;    // k + 1
   int* coff;      // k + 1
   double* part;   // (ceil(n / kSegChunk) + k) * d
 };
-constexpr int kScanTile = 4096;
 hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_scale, int n, int d,
                                const int* A, int k, float* C, const LloydWs& w, hipStream_t s);
 

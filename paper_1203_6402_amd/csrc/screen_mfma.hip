@@ -271,18 +271,10 @@ __global__ __launch_bounds__(256) void k_first_prep(const T* X, const float* row
 // c+1 are in flight.  Each accumulator starts at -ncg_j/2, so it ends as
 // acc = x.c - ncg_j/2 = -(lb - (1-2G)||x||^2)/2, and the smallest lb is the
 // largest acc.
-constexpr int kWaves = 4;              // waves per block
-constexpr int kStageBytes = 32 * 1024; // LDS per staging buffer
-// 16-point row tiles per wave: four while the A operands of KS k-steps fit
-// the registers beside the accumulators and running maxima, two beyond 8.
-constexpr int screen_krt(int KS) { return KS <= 8 ? 4 : 2; }
-// Rows with scales spend more registers per value (row scales, the scaled
-// epilogue): two row tiles from five k-steps on, so two waves share a SIMD.
 template <int KS, typename T>
 constexpr int screen_krt_t() {
-  return ScaledRows<T>::value ? (KS <= 4 ? 4 : 2) : screen_krt(KS);
+  return screen_krt(KS, ScaledRows<T>::value);
 }
-constexpr int kBlockPts = kWaves * 4 * 16;  // the largest block (256 points)
 
 typedef __attribute__((address_space(3))) void lds_void;
 typedef const __attribute__((address_space(1))) void gbl_void;
@@ -336,8 +328,6 @@ __device__ __forceinline__ void epilogue(const f32x4 (&acc)[KRT], uint32_t keep,
       s1[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], v, FLT_MAX);
     }
 }
-
-constexpr int kWaveStage = kStageBytes * 2 / kWaves;  // LDS bytes per wave after the pass
 
 // Starts the copy of rows [row0, row0 + nr) of X (raw elements, rowb bytes
 // each, nr * rowb a multiple of 16) straight from global memory into dst:
@@ -651,8 +641,9 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   const float nxg = a.oneminus2g * nx;
   const float lbmin = fmaf(b1, -2.0f, nxg);
   const float lb2 = fmaf(b2, -2.0f, nxg);
-  const bool refine = valid && in_range && j1 >= 0 && lbmin < D;
-  const float* crow = a.C + (int64_t)(id0 + max(j1, 0)) * a.DP;
+  const bool jok = j1 >= 0 && j1 < m;  // a candidate of the pass, not a padding column
+  const bool refine = valid && in_range && jok && lbmin < D;
+  const float* crow = a.C + (int64_t)(id0 + (jok ? j1 : 0)) * a.DP;  // read only when refining
   float r1 = 0.0f;
   if (staged) {
     for (int c0 = 0; c0 < WP; c0 += R) {
@@ -681,11 +672,11 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     // zero distance too when S is kept, for a tie at zero)
     listed = D > 0.0f || a.S != nullptr;
   } else if (!refine) {
-    if (a.first) {  // m == 0 (never on the paths that call the screen)
-      a.D2[p] = INFINITY;
-      a.A[p] = -1;
-    }
-    return;
+    // lbmin >= D: no candidate comes closer.  Without a usable winner (only
+    // non-finite values give none) or in a first pass, which writes every
+    // point, the direct form decides.
+    if (!a.first && jok && lbmin >= D) return;
+    listed = true;
   } else if (r1 < D) {
     if (lb2 > r1) {
       if (a.S) a.S[p] = D;
@@ -849,11 +840,6 @@ bool screen_a_direct(kmpar_dtype dt, int split, int d) {
   return dt == KMPAR_BF16 && d % 8 == 0;
 }
 
-size_t screen_a_bytes(int n, int KS) {
-  const size_t tiles = (size_t)(n + kBlockPts - 1) / kBlockPts * (kBlockPts / 16);
-  return tiles * KS * 64 * 16;
-}
-
 hipError_t launch_prep_a(kmpar_dtype dt, int split, int KS, const void* X, const float* rsc, int n,
                          int d, float* norms, void* Apre, hipStream_t s) {
   if (dt == KMPAR_F32 && split == 3)
@@ -905,8 +891,6 @@ int screen_split(kmpar_dtype dt, bool centers_are_rows) {
   if (dt == KMPAR_FP8_E4M3) return centers_are_rows ? 1 : 0;
   return centers_are_rows ? 1 : 2;
 }
-
-int screen_ksteps(int split, int d) { return split ? (split * d + 31) / 32 : 0; }
 
 bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d) {
   const int sp = screen_split(dt, centers_are_rows);

@@ -191,3 +191,33 @@ def test_flagged_argmins_on_integer_lattice(plain, refined, d, span):
     _, d2, snd = O.nearest(X64, X64[o.cand_point])
     ties = int(np.sum(snd == d2))
     assert ties > 0 and b.stats["flagged_argmins"] == ties
+
+
+@pytest.mark.parametrize("mode", ["plain", "refined"])
+def test_lloyd_rows_without_a_finite_distance(plain, refined, mode):
+    # Rows holding NaN or Inf have no finite distance to any center: their
+    # assignment is -1 and no centroid takes them, while every other row is
+    # assigned and averaged as without them.  (Such rows once sent the last
+    # cluster's sums into sorted positions the scatter had not written.)
+    ctx = refined if mode == "refined" else plain
+    X = synth.gauss_mixture(20000, 15, 50, 10.0, seed=5)
+    bad = np.arange(3, 20000, 997)
+    X[bad[::2], 3] = np.nan
+    X[bad[1::2], 7] = np.inf
+    X64 = X.astype(np.float64)
+    ok = np.isfinite(X64).all(axis=1)
+    rng = np.random.default_rng(1)
+    C = torch.from_numpy(X[rng.choice(np.nonzero(ok)[0], 50, replace=False)].copy()).to("cuda:0")
+    Xd = _dev(X)
+    for _ in range(3):
+        Cin = C.cpu().numpy().astype(np.float64)
+        a, _phi = ctx.lloyd_step(Xd, C, want_assign=True)
+        torch.cuda.synchronize()
+        a = a.cpu().numpy()
+        assert np.all(a[~ok] == -1)
+        oa, od2, osnd = O.nearest(X64[ok], Cin)
+        diff = a[ok] != oa
+        gap = (osnd - od2) / np.maximum(od2, 1e-300)
+        assert np.all(gap[diff] <= O.fp32_band(15))
+        Co, _ = O.lloyd_update(X64[ok], a[ok], Cin)
+        np.testing.assert_allclose(C.cpu().numpy(), Co.astype(np.float32), rtol=1e-6, atol=1e-6)
