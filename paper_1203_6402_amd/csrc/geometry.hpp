@@ -84,10 +84,13 @@ constexpr int screen_krt(int KS, bool scaled) {
 }
 constexpr int kBlockPts = kWaves * 4 * 16;  // the largest block (256 points)
 // Candidate tiles per LDS chunk for KS k-steps, chunks per tag group (groups
-// of up to 16 tiles), and the tag bits that number a tile within its group.
+// of up to 64 tiles), and the tag bits that number a tile within its group.
+// A larger group merges its running maxima less often; its tag, in the low
+// mantissa bits, moves each value by up to 2^(TB - 23) of its magnitude.
+constexpr int kScreenGroupTiles = 64;
 constexpr int screen_chunk_tiles(int KS) { return kStageBytes / (KS * 64 * 16); }
 constexpr int screen_group_chunks(int KS) {
-  return screen_chunk_tiles(KS) >= 16 ? 1 : 16 / screen_chunk_tiles(KS);
+  return screen_chunk_tiles(KS) >= kScreenGroupTiles ? 1 : kScreenGroupTiles / screen_chunk_tiles(KS);
 }
 constexpr int screen_tag_bits(int KS) {
   int b = 0;

@@ -18,7 +18,7 @@
 //                                        direct-form pass over the candidates.
 // Every decision is therefore the decision of the FP32 direct-form path.
 //
-// Within a group of up to 16 candidate tiles (one or more LDS chunks), the
+// Within a group of up to 64 candidate tiles (one or more LDS chunks), the
 // running maxima carry the tile's position in the group in the low TB
 // mantissa bits of the value itself (the lane fixes the column within the
 // tile), so the per-value work is one bit insert and two med3; each group's
@@ -395,7 +395,9 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   // per candidate: -ncg/2 (four copies when BCAST), or (-ncg/2, scale) when SC
   __shared__ __attribute__((aligned(16))) float sN[2][CT * 16 * (BCAST ? 4 : (SC ? 2 : 1))];
 
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  // the wave index is uniform across the wave: kept in a scalar register, it
+  // makes the chunk staging loop a scalar loop
+  const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int d = a.d;
   int id0 = a.id0_host, m = a.m_host;
   if (a.rs) {
