@@ -375,7 +375,11 @@ hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const
                         const int* cand, float* scg, int* list, int* list_len, int4* rpart,
                         kmpar_stats* st, hipStream_t s) {
   const int KS = screen_ksteps(split, fa.d);
-  const float om2g = 1.0f - 2.0f * screen_g(dt, split, fa.d);
+  // A pass of at most kScreenOneGroupMaxTiles tiles tags each tile by its
+  // index in the pass (single-group screen); the bound covers the tag.
+  const int tag_bits = max_tiles <= kScreenOneGroupMaxTiles ? screen_pass_tag_bits(max_tiles) : 0;
+  const float om2g =
+      1.0f - 2.0f * screen_g(dt, split, fa.d, tag_bits > 0 ? tag_bits : screen_tag_bits(KS));
   const bool fp8 = dt == KMPAR_FP8_E4M3;
   hipError_t e = launch_prep_b(dt, split, KS, fa.C, DP, fa.d, fa.rs, fa.m_host, max_tiles, om2g, B,
                                ncg, fa.X, fa.row_scale, fp8 ? cand : nullptr,
@@ -404,6 +408,7 @@ hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const
   sa.list = list;
   sa.list_len = list_len;
   sa.stats = st;
+  sa.tag_bits = tag_bits;
   e = timed(ctx, kSlotScreen, fa.n, nullptr, fa.rs, fa.m_host, s,
             [&] { return launch_screen(dt, split, KS, sa, s); });
   if (e != hipSuccess) return e;

@@ -73,8 +73,20 @@ constexpr int kRescanMaxSplit = 8;
 constexpr int kScreenMaxKS = 16;
 constexpr int kWaves = 4;               // waves per screen block
 constexpr int kStageBytes = 32 * 1024;  // LDS per candidate staging buffer
+// The single-group screen (a pass of at most kScreenOneGroupMaxTiles tiles,
+// each value tagged with its tile's index in the pass) keeps no per-group
+// maxima, which frees the registers for three waves per SIMD at up to four
+// k-steps of unscaled rows; there its staging buffers shrink so that three
+// blocks share a CU.
+constexpr int kScreenOneGroupMaxTiles = 128;
+constexpr bool screen_three_waves(int KS, bool oneg, bool scaled) { return oneg && KS <= 4 && !scaled; }
+constexpr int screen_stage_bytes(int KS, bool oneg, bool scaled = false) {
+  return screen_three_waves(KS, oneg, scaled) ? 24 * 1024 : kStageBytes;
+}
 // LDS bytes each wave reuses after the pass (a quarter of the two buffers).
-constexpr int kWaveStage = kStageBytes * 2 / kWaves;
+constexpr int screen_wave_stage(int KS, bool oneg, bool scaled = false) {
+  return screen_stage_bytes(KS, oneg, scaled) * 2 / kWaves;
+}
 // 16-point row tiles per wave: four while the A operands of KS k-steps fit
 // the registers beside the accumulators and running maxima, two beyond 8.
 // Rows with scales spend more registers per value (row scales, the scaled
@@ -88,13 +100,27 @@ constexpr int kBlockPts = kWaves * 4 * 16;  // the largest block (256 points)
 // A larger group merges its running maxima less often; its tag, in the low
 // mantissa bits, moves each value by up to 2^(TB - 23) of its magnitude.
 constexpr int kScreenGroupTiles = 64;
-constexpr int screen_chunk_tiles(int KS) { return kStageBytes / (KS * 64 * 16); }
+constexpr int screen_chunk_tiles(int KS, bool oneg = false, bool scaled = false) {
+  return screen_stage_bytes(KS, oneg, scaled) / (KS * 64 * 16);
+}
 constexpr int screen_group_chunks(int KS) {
   return screen_chunk_tiles(KS) >= kScreenGroupTiles ? 1 : kScreenGroupTiles / screen_chunk_tiles(KS);
 }
 constexpr int screen_tag_bits(int KS) {
   int b = 0;
   while ((1 << b) < screen_group_chunks(KS) * screen_chunk_tiles(KS)) ++b;
+  return b;
+}
+// Whether the biases of a chunk are stored four times over (one LDS read
+// then gives an accumulator's initial value): unscaled rows with chunks of
+// up to 16 tiles, up to 8 in the three-wave screen (its LDS budget).
+constexpr bool screen_bcast(int KS, bool oneg, bool scaled) {
+  return !scaled && screen_chunk_tiles(KS, oneg, scaled) <= (screen_three_waves(KS, oneg, scaled) ? 8 : 16);
+}
+// Tag bits of the single-group screen for a pass of up to max_tiles tiles.
+constexpr int screen_pass_tag_bits(int max_tiles) {
+  int b = 1;
+  while ((1 << b) < max_tiles) ++b;
   return b;
 }
 // K axis of a split-term operand: SPLIT copies of d, in 32-wide k-steps.

@@ -76,12 +76,13 @@ struct ScreenArgs {
   int* list;             // points the screen could not settle
   int* list_len;
   kmpar_stats* stats;    // nullable: receives the listed counts
+  int tag_bits;          // > 0: single-group screen, tiles tagged by their index in the pass
 };
 
 int screen_split(kmpar_dtype dt, bool centers_are_rows);
 bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d);
-// Error constant G of the screen's lower bound.
-float screen_g(kmpar_dtype dt, int split, int d);
+// Error constant G of the screen's lower bound with tag_bits bits of tag.
+float screen_g(kmpar_dtype dt, int split, int d, int tag_bits);
 // B operands of the candidates C[rs[0] ..) (or C[0 .. m_host)), their biases
 // and, for FP8 rows, their scales: FP8 rows (split 1, against rows of X)
 // take the candidates' e4m3 codes from X rows cand[id].

@@ -378,20 +378,30 @@ __device__ __forceinline__ float refine_dist(const T* x, const float* c, int d, 
 }
 
 // The screen of block `blk` of the points of `a` (kWaves * KRT * 16 points).
-template <int SPLIT, int KS, typename T, bool DIRECT>
+// ONEG: the pass has at most kScreenOneGroupMaxTiles tiles and each value
+// carries its tile's index in the pass (a.tag_bits bits), so the running
+// maxima are the pass's maxima and no per-group maxima or ids are kept.
+template <int SPLIT, int KS, typename T, bool DIRECT, bool ONEG>
 __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   constexpr int KRT = screen_krt_t<KS, T>();  // row tiles per wave
   constexpr int WP = KRT * 16;         // points per wave
   constexpr int BP = kWaves * WP;      // points per block
-  constexpr int CT = screen_chunk_tiles(KS);        // candidate tiles per chunk
-  static_assert(CT * KS * 64 * 16 <= kStageBytes, "chunk exceeds its staging buffer");
+  // the single-group screen of up to four k-steps of unscaled rows runs
+  // three waves per SIMD (smaller staging, no software pipeline)
+  constexpr bool THREE = screen_three_waves(KS, ONEG, ScaledRows<T>::value);
+  constexpr bool PIPE = !THREE;
+  constexpr bool SCR = ScaledRows<T>::value;
+  constexpr int STAGE = screen_stage_bytes(KS, ONEG, SCR);  // bytes per staging buffer
+  constexpr int WSTAGE = screen_wave_stage(KS, ONEG, SCR);  // a wave's share after the pass
+  constexpr int CT = screen_chunk_tiles(KS, ONEG, SCR);     // candidate tiles per chunk
+  static_assert(CT >= 1 && CT * KS * 64 * 16 <= STAGE, "chunk exceeds its staging buffer");
   constexpr int CHUNK_V = CT * KS * 64;             // 16-byte vectors per chunk
   // Two full staging buffers whatever the chunk: after the pass each wave
-  // reuses a quarter of the 64 KB (kWaveStage bytes) for its own data.
-  __shared__ u16x8 sB[2][kStageBytes / 16];
-  static_assert(2 * kStageBytes == kWaves * kWaveStage, "wave quarters must tile the buffers");
+  // reuses a quarter of them (WSTAGE bytes) for its own data.
+  __shared__ u16x8 sB[2][STAGE / 16];
+  static_assert(2 * STAGE == kWaves * WSTAGE, "wave quarters must tile the buffers");
   constexpr bool SC = ScaledRows<T>::value;  // codes with row scales
-  constexpr bool BCAST = !SC && CT <= 16;     // LDS for four copies of each bias
+  constexpr bool BCAST = screen_bcast(KS, ONEG, SC);  // LDS for four copies of each bias
   // per candidate: -ncg/2 (four copies when BCAST), or (-ncg/2, scale) when SC
   __shared__ __attribute__((aligned(16))) float sN[2][CT * 16 * (BCAST ? 4 : (SC ? 2 : 1))];
 
@@ -471,14 +481,19 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     }
   }
 
-  // Per chunk, the largest and second largest tagged acc of each (row tile,
-  // row), the tag being the tile's position in the chunk; after each chunk
-  // they are merged into the running largest, second largest and argmax.
-  // The mask lives in a VGPR so that the tag insert is one v_and_or_b32
-  // (VOP3 reads at most one SGPR, and the tile position is one).
-  constexpr int GC = screen_group_chunks(KS);  // chunks per tag group
-  constexpr int TB = screen_tag_bits(KS);
-  static_assert((1 << TB) >= GC * CT, "tag too narrow for a group");
+  // Per tag group, the largest and second largest tagged acc of each (row
+  // tile, row), the tag being the tile's position in the group; after each
+  // group they are merged into the running largest, second largest and
+  // argmax.  ONEG: one group, the whole pass, folded straight into the
+  // running pair.  The mask lives in a VGPR so that the tag insert is one
+  // v_and_or_b32 (VOP3 reads at most one SGPR, and the tile position is one).
+  constexpr int GC = ONEG ? 1 << 20 : screen_group_chunks(KS);  // chunks per tag group
+  constexpr int TBG = screen_tag_bits(KS);
+  static_assert(ONEG || (1 << TBG) >= screen_group_chunks(KS) * CT, "tag too narrow for a group");
+  const int TB = ONEG ? a.tag_bits : TBG;
+  // a pass with more tiles than the tag can number (the host sizes the tag
+  // from the pass's capacity) is left to the direct form
+  const bool tag_ok = !ONEG || (TB >= 1 && TB <= 10 && ntiles <= (1 << TB));
   uint32_t keep;
   asm volatile("v_mov_b32 %0, %1" : "=v"(keep) : "s"(~((1u << TB) - 1u)));
   // SC: the scales of the rows of each value (0 outside the screen's range:
@@ -529,9 +544,9 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     const int nt = min(CT, ntiles - c * CT);
     const u16x8* buf = sB[c & 1];
     const float* ncs = sN[c & 1];
-    const int cg = c % GC;         // position of the chunk in its tag group
-    const uint32_t t0 = cg * CT;   // tag of the chunk's first tile
-    if (cg == 0) {
+    const int cg = ONEG ? c : c % GC;  // position of the chunk in its tag group
+    const uint32_t t0 = cg * CT;       // tag of the chunk's first tile
+    if (!ONEG && cg == 0) {
 #pragma unroll
       for (int r = 0; r < KRT; ++r)
 #pragma unroll
@@ -544,13 +559,28 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     // epilogue of tile q, so matrix and vector units overlap within a wave
     // (two accumulator sets, unrolled by two so no copies are needed).
     f32x4 acc0[KRT], acc1[KRT];
+    // each tile's values go to the group pair (the running pair when ONEG)
+    auto fold = [&](const f32x4 (&acc)[KRT], int q) {
+      if constexpr (ONEG)
+        epilogue<KRT, SC>(acc, keep, t0 + q, s1, s2, srow, ncs, q, lane);
+      else
+        epilogue<KRT, SC>(acc, keep, t0 + q, c1, c2, srow, ncs, q, lane);
+    };
+    if constexpr (!PIPE) {
+      // three waves per SIMD: the other waves' vector work overlaps a
+      // wave's matrix instructions, so one accumulator set suffices
+      for (int q = 0; q < nt; ++q) {
+        mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, q, lane, acc0);
+        fold(acc0, q);
+      }
+    } else {
     mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, 0, lane, acc0);
     int q = 0;
     for (; q + 2 < nt; q += 2) {
       mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, q + 1, lane, acc1);
-      epilogue<KRT, SC>(acc0, keep, t0 + q, c1, c2, srow, ncs, q, lane);
+      fold(acc0, q);
       mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, q + 2, lane, acc0);
-      epilogue<KRT, SC>(acc1, keep, t0 + q + 1, c1, c2, srow, ncs, q + 1, lane);
+      fold(acc1, q + 1);
       // Issue order: the operand reads first, then every MFMA followed by
       // three vector instructions, so that one wave keeps both the matrix
       // and the vector pipes busy.
@@ -563,14 +593,15 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     }
     if (q + 1 < nt) {
       mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, q + 1, lane, acc1);
-      epilogue<KRT, SC>(acc0, keep, t0 + q, c1, c2, srow, ncs, q, lane);
-      epilogue<KRT, SC>(acc1, keep, t0 + q + 1, c1, c2, srow, ncs, q + 1, lane);
+      fold(acc0, q);
+      fold(acc1, q + 1);
     } else {
-      epilogue<KRT, SC>(acc0, keep, t0 + q, c1, c2, srow, ncs, q, lane);
+      fold(acc0, q);
+    }
     }
     // Group merge: candidate id from the tag and the lane's column; a tie
     // with the running maximum keeps the earlier (lower) id.
-    if (cg == GC - 1 || c + 1 == nchunks) {
+    if (!ONEG && (cg == GC - 1 || c + 1 == nchunks)) {
 #pragma unroll
     for (int r = 0; r < KRT; ++r)
 #pragma unroll
@@ -593,44 +624,60 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   const bool valid = lane < WP && p < a.n;  // lanes past the wave's points idle
   const float nx = valid ? a.norms[p] : 0.0f;
   const float D = (a.first || !valid) ? INFINITY : a.D2[p];
-  char* xw = reinterpret_cast<char*>(&sB[0][0]) + wave * kWaveStage;
+  char* xw = reinterpret_cast<char*>(&sB[0][0]) + wave * WSTAGE;
 
   // Merge of the 16 columns of every point through LDS: lane l writes the
   // (largest, second largest, id) of each (row tile, row) at [point][l % 16]
   // (columns XOR-swizzled by the point to spread the banks), then lane p
   // reads the 16 entries of point p and merges them in column order.  Of two
   // equal maxima the earlier column is kept; no decision depends on which,
-  // since then lb2 = lbmin <= r1 and the point is listed.
-  f32x4* M = reinterpret_cast<f32x4*>(xw);  // [WP points][16 columns]
-#pragma unroll
-  for (int r = 0; r < KRT; ++r)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int pl = r * 16 + (lane / 16) * 4 + i;
-      M[pl * 16 + ((lane % 16) ^ (pl & 15))] =
-          f32x4{s1[r][i], s2[r][i], __int_as_float(ix[r][i]), 0.0f};
-    }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // since then lb2 = lbmin <= r1 and the point is listed.  When the wave's
+  // share cannot hold all its points' entries, the points go in two halves.
+  // ONEG: a maximum's id is its tag (tile index in the pass) and the column.
+  constexpr int HALVES = WP * 16 * 16 > WSTAGE ? 2 : 1;
+  constexpr int PH = WP / HALVES;  // points per half
+  static_assert(PH * 16 * 16 <= WSTAGE && PH % 16 == 0, "merge exceeds the wave's share");
+  f32x4* M = reinterpret_cast<f32x4*>(xw);  // [PH points][16 columns]
   float b1 = -INFINITY, b2 = -INFINITY;
   int j1 = -1;
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const f32x4 e = M[lane * 16 + (c ^ (lane & 15))];
-    const bool take = e.x > b1;
-    b2 = __builtin_amdgcn_fmed3f(b1, e.x, __builtin_amdgcn_fmed3f(b2, e.y, FLT_MAX));
-    j1 = take ? __float_as_int(e.z) : j1;
-    b1 = __builtin_amdgcn_fmed3f(b1, e.x, FLT_MAX);
+  for (int h = 0; h < HALVES; ++h) {
+#pragma unroll
+    for (int r = h * (KRT / HALVES); r < (h + 1) * (KRT / HALVES); ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pl = r * 16 + (lane / 16) * 4 + i - h * PH;
+        int id;
+        if constexpr (ONEG)
+          id = (int)(__float_as_uint(s1[r][i]) & ~keep) * 16 + (lane % 16);
+        else
+          id = ix[r][i];
+        M[pl * 16 + ((lane % 16) ^ (pl & 15))] = f32x4{s1[r][i], s2[r][i], __int_as_float(id), 0.0f};
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane / PH == h) {  // this lane's point is in the half
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const f32x4 e = M[(lane - h * PH) * 16 + (c ^ (lane & 15))];
+        const bool take = e.x > b1;
+        b2 = __builtin_amdgcn_fmed3f(b1, e.x, __builtin_amdgcn_fmed3f(b2, e.y, FLT_MAX));
+        j1 = take ? __float_as_int(e.z) : j1;
+        b1 = __builtin_amdgcn_fmed3f(b1, e.x, FLT_MAX);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the share is free again
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  __builtin_amdgcn_wave_barrier();  // the quarter is free again
 
   // This wave's rows (raw elements) go to its quarter: full waves stage them
   // in groups of R (a multiple of 16, so every group is whole 16-byte units);
   // the one partial wave of X reads its rows from global memory instead.
   const int nvalid = max(0, min(WP, a.n - wbase));
   const int rowb = d * (int)sizeof(T);  // <= 1 KB, so R >= 16
-  const int R = min(WP, (kWaveStage / rowb) & ~15);  // rows per staging group
+  const int R = min(WP, (WSTAGE / rowb) & ~15);  // rows per staging group
   const bool staged = nvalid == WP;
   if (staged) stage_rows<T>(xw, X, wbase, R, rowb, lane);
 
@@ -639,7 +686,8 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   // float4.
   float sp = 1.0f;  // the point's row scale (FP8)
   if constexpr (SC) sp = valid ? a.row_scale[p] : 0.0f;
-  const bool in_range = nx >= kNormMin && nx <= kNormMax && (!SC || (sp >= kScaleMin && sp <= kScaleMax));
+  const bool in_range = tag_ok && nx >= kNormMin && nx <= kNormMax &&
+                        (!SC || (sp >= kScaleMin && sp <= kScaleMax));
   const float nxg = a.oneminus2g * nx;
   const float lbmin = fmaf(b1, -2.0f, nxg);
   const float lb2 = fmaf(b2, -2.0f, nxg);
@@ -700,7 +748,18 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
 
 template <int SPLIT, int KS, typename T, bool DIRECT>
 __global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
-  screen_body<SPLIT, KS, T, DIRECT>(a, blockIdx.x);
+  screen_body<SPLIT, KS, T, DIRECT, false>(a, blockIdx.x);
+}
+// The single-group screen; k_screen_one3, held to the registers of three
+// waves per SIMD, where its shape runs three (screen_three_waves).
+template <int SPLIT, int KS, typename T, bool DIRECT>
+__global__ __launch_bounds__(kWaves * 64) void k_screen_one(ScreenArgs a) {
+  screen_body<SPLIT, KS, T, DIRECT, true>(a, blockIdx.x);
+}
+template <int SPLIT, int KS, typename T, bool DIRECT>
+__global__ __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
+void k_screen_one3(ScreenArgs a) {
+  screen_body<SPLIT, KS, T, DIRECT, true>(a, blockIdx.x);
 }
 
 // Adds the previous pass's listed count to the stats and clears it.
@@ -715,10 +774,24 @@ template <int SPLIT, int KS, typename T>
 static void launch_one(const ScreenArgs& a, hipStream_t s) {
   constexpr int BP = kWaves * screen_krt_t<KS, T>() * 16;
   const int blocks = (a.n + BP - 1) / BP;
-  if (a.Apre)
+  constexpr bool THREE = screen_three_waves(KS, true, ScaledRows<T>::value);
+  if (a.tag_bits > 0) {
+    if constexpr (THREE) {
+      if (a.Apre)
+        hipLaunchKernelGGL((k_screen_one3<SPLIT, KS, T, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_screen_one3<SPLIT, KS, T, true>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+    } else {
+      if (a.Apre)
+        hipLaunchKernelGGL((k_screen_one<SPLIT, KS, T, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_screen_one<SPLIT, KS, T, true>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+    }
+  } else if (a.Apre) {
     hipLaunchKernelGGL((k_screen<SPLIT, KS, T, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
-  else
+  } else {
     hipLaunchKernelGGL((k_screen<SPLIT, KS, T, true>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+  }
 }
 
 // KS k-steps, dispatched up to MAXKS (the widest row the dtype and split
@@ -906,7 +979,7 @@ bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d) {
 // in the low mantissa bits; times 2 for margin.  FP8 rows add the roundings
 // of their decoded elements (fl(s q), twice the dot: 2u S) and of the scaled
 // epilogue (s_x s_c, the fma, the bias: 3u, doubled).
-float screen_g(kmpar_dtype dt, int split, int d) {
+float screen_g(kmpar_dtype dt, int split, int d, int tag_bits) {
   const double u = 0x1.0p-24;
   const int K = 32 * screen_ksteps(split, d);
   double split_err = 0.0;
@@ -918,7 +991,7 @@ float screen_g(kmpar_dtype dt, int split, int d) {
   const double misc = (d + 8) * u + 2.0 * (d + 2) * u;
   // |acc| <= |x.c| + ||c||^2 / 2 <= 1.01 S; the tag moves it by less than
   // 2^(TB-23) |acc|, and lb by twice that.
-  const double tag_err = 2.02 * std::ldexp(1.0, screen_tag_bits(screen_ksteps(split, d)) - 23);
+  const double tag_err = 2.02 * std::ldexp(1.0, tag_bits - 23);
   const double scale_err = dt == KMPAR_FP8_E4M3 ? 8.2 * u : 0.0;
   const double safety = 2.0;  // 2G = safety * budget
   return (float)(safety * (split_err + acc_err + misc + tag_err + scale_err) / 2.0);

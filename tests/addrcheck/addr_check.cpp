@@ -141,11 +141,20 @@ void check_screen(Checker& ck, const ScreenShape& s, int sample) {
     return;
   }
   const int KRT = screen_krt(KS, SC), WP = KRT * 16, BP = kWaves * WP;
-  const int CT = screen_chunk_tiles(KS), CHUNK_V = CT * KS * 64;
-  if (CT * KS * 64 * 16 > kStageBytes) ck.fail("chunk exceeds its staging buffer");
-  const bool BCAST = !SC && CT <= 16;
+  // the single-group screen runs passes of at most kScreenOneGroupMaxTiles
+  // tiles (the host's choice from the pass capacity)
+  const bool oneg = s.max_tiles <= kScreenOneGroupMaxTiles;
+  const int STAGE = screen_stage_bytes(KS, oneg, SC), WSTAGE = screen_wave_stage(KS, oneg, SC);
+  const int CT = screen_chunk_tiles(KS, oneg, SC), CHUNK_V = CT * KS * 64;
+  if (CT < 1 || CT * KS * 64 * 16 > STAGE) ck.fail("chunk exceeds its staging buffer");
+  if (2 * STAGE != kWaves * WSTAGE) ck.fail("wave shares do not tile the staging buffers");
+  const bool BCAST = screen_bcast(KS, oneg, SC);
   const int nW = BCAST ? 4 : (SC ? 2 : 1);
-  const int64_t sBsz = 2LL * kStageBytes, sNsz = 2LL * CT * 16 * nW * 4;
+  const int64_t sBsz = 2LL * STAGE, sNsz = 2LL * CT * 16 * nW * 4;
+  if (screen_three_waves(KS, oneg, SC) && 3 * (sBsz + sNsz) > 160 * 1024)
+    ck.fail("three blocks of the three-wave screen exceed a CU's LDS");
+  if (oneg && s.m > 0 && (s.m + 15) / 16 > (1 << screen_pass_tag_bits(s.max_tiles)))
+    ck.fail("tile tags cannot number the pass");
   const int NBT = (CT * 16 + kWaves * 64 - 1) / (kWaves * 64);
   const int ntiles = (s.m + 15) / 16, nchunks = (ntiles + CT - 1) / CT;
   const int64_t n = s.n;
@@ -163,8 +172,8 @@ void check_screen(Checker& ck, const ScreenShape& s, int sample) {
         const int nt = std::min(CT, ntiles - c * CT), nv = nt * KS * 64;
         for (int v0 = wave * 64; v0 < nv; v0 += kWaves * 64) {
           ck.in("B chunk", ((int64_t)c * CHUNK_V + v0 + lane) * 16, 16, Bsz, blk, tid);
-          ck.in("LDS sB", (int64_t)(c & 1) * kStageBytes + (int64_t)(v0 + lane) * 16, 16,
-                (int64_t)(c & 1) * kStageBytes + kStageBytes, blk, tid);
+          ck.in("LDS sB", (int64_t)(c & 1) * STAGE + (int64_t)(v0 + lane) * 16, 16,
+                (int64_t)(c & 1) * STAGE + STAGE, blk, tid);
         }
         // stage_ncg(c)
         for (int i = 0; i < NBT; ++i) {
@@ -180,8 +189,8 @@ void check_screen(Checker& ck, const ScreenShape& s, int sample) {
         // operand and bias reads of the chunk's tiles
         for (int q = 0; q < nt; ++q) {
           for (int st = 0; st < KS; ++st)
-            ck.in("LDS buf", (int64_t)(c & 1) * kStageBytes + ((int64_t)(q * KS + st) * 64 + lane) * 16, 16,
-                  (int64_t)(c & 1) * kStageBytes + kStageBytes, blk, tid);
+            ck.in("LDS buf", (int64_t)(c & 1) * STAGE + ((int64_t)(q * KS + st) * 64 + lane) * 16, 16,
+                  (int64_t)(c & 1) * STAGE + STAGE, blk, tid);
           ck.in("LDS ncs", ((int64_t)(c & 1) * CT * 16 * nW + (int64_t)(q * 16 + lane % 16) * nW) * 4,
                 BCAST ? 16 : (SC ? 8 : 4), sNsz, blk, tid);
         }
@@ -208,16 +217,22 @@ void check_screen(Checker& ck, const ScreenShape& s, int sample) {
             if (p < n) ck.in("row_scale", p * 4, 4, n * 4, blk, tid);
           }
       }
-      // per-wave merge through the wave's quarter of sB
-      const int64_t xw = (int64_t)wave * kWaveStage;
-      for (int r = 0; r < KRT; ++r)
-        for (int i = 0; i < 4; ++i) {
-          const int pl = r * 16 + (lane / 16) * 4 + i;
-          ck.in("LDS M write", xw + (int64_t)(pl * 16 + ((lane % 16) ^ (pl & 15))) * 16, 16,
-                xw + kWaveStage, blk, tid);
-        }
-      for (int c = 0; c < 16; ++c)
-        ck.in("LDS M read", xw + (int64_t)(lane * 16 + (c ^ (lane & 15))) * 16, 16, sBsz, blk, tid);
+      // per-wave merge through the wave's share of sB, in halves when the
+      // share cannot hold every point's entries
+      const int64_t xw = (int64_t)wave * WSTAGE;
+      const int HALVES = WP * 16 * 16 > WSTAGE ? 2 : 1, PH = WP / HALVES;
+      for (int h = 0; h < HALVES; ++h) {
+        for (int r = h * (KRT / HALVES); r < (h + 1) * (KRT / HALVES); ++r)
+          for (int i = 0; i < 4; ++i) {
+            const int pl = r * 16 + (lane / 16) * 4 + i - h * PH;
+            ck.in("LDS M write", xw + (int64_t)(pl * 16 + ((lane % 16) ^ (pl & 15))) * 16, 16,
+                  xw + WSTAGE, blk, tid);
+          }
+        if (lane / PH == h)
+          for (int c = 0; c < 16; ++c)
+            ck.in("LDS M read", xw + (int64_t)((lane - h * PH) * 16 + (c ^ (lane & 15))) * 16, 16,
+                  xw + WSTAGE, blk, tid);
+      }
       const int64_t p = wbase + lane;
       const bool valid = lane < WP && p < n;
       if (valid) {
@@ -227,7 +242,7 @@ void check_screen(Checker& ck, const ScreenShape& s, int sample) {
       // staging of the wave's rows, groups of R
       const int64_t nvalid = std::max<int64_t>(0, std::min<int64_t>(WP, n - wbase));
       const int rowb = d * Sz;
-      const int R = std::min(WP, (kWaveStage / rowb) & ~15);
+      const int R = std::min(WP, (WSTAGE / rowb) & ~15);
       if (R < 16) ck.fail("staging group below 16 rows");
       const bool staged = nvalid == WP;
       // the winner j1: any column of the pass's tiles; refined only when j1 < m
@@ -239,7 +254,7 @@ void check_screen(Checker& ck, const ScreenShape& s, int sample) {
           for (int v0 = 0; v0 < bytes; v0 += 1024)
             if (v0 + 16 * lane < bytes) {
               ck.in("X rows (staged)", (wbase + c0) * rowb + v0 + 16 * lane, 16, Xsz, blk, tid);
-              ck.in("LDS rows", xw + v0 + 16 * lane, 16, xw + kWaveStage, blk, tid);
+              ck.in("LDS rows", xw + v0 + 16 * lane, 16, xw + WSTAGE, blk, tid);
             }
           if (valid && lane >= c0 && lane < c0 + nr) {
             // refine_dist<XLDS>: 32 elements at a time from the staged row
