@@ -16,29 +16,33 @@ namespace kmpar {
 // The fold of one pass into point i's state: (D2, A) move to the pass's
 // best only when strictly closer (ties keep the lower id), and S, when kept,
 // is the second-smallest distance over every candidate met so far.
+// TRACK: the pass keeps S (a.S != nullptr); without it S is left alone.
+template <bool TRACK = true>
 __device__ __forceinline__ void fold_apply(const FoldArgs& a, int i, int id0, float best, int bj,
                                            float second) {
   if (a.first) {
     a.D2[i] = best;
     a.A[i] = bj >= 0 ? id0 + bj : -1;
-    if (a.S) a.S[i] = second;
+    if constexpr (TRACK) a.S[i] = second;
   } else if (bj >= 0 && best < a.D2[i]) {
-    if (a.S) a.S[i] = fminf(a.D2[i], second);
+    if constexpr (TRACK) a.S[i] = fminf(a.D2[i], second);
     a.D2[i] = best;
     a.A[i] = id0 + bj;
-  } else if (bj >= 0 && a.S) {
+  } else if (TRACK && bj >= 0) {
     a.S[i] = fminf(a.S[i], best);
   }
 }
 
 // A candidate at distance acc met in id order: the strictly smaller becomes
-// the best (ties keep the earlier), the other bounds the second smallest.
+// the best (ties keep the earlier), the other bounds the second smallest
+// (TRACK: only passes that keep S track it; the others spare its registers).
+template <bool TRACK = true>
 __device__ __forceinline__ void keep_two(float acc, int c, float& best, int& bj, float& second) {
   if (acc < best) {
-    second = best;
+    if constexpr (TRACK) second = best;
     best = acc;
     bj = c;
-  } else {
+  } else if constexpr (TRACK) {
     second = fminf(second, acc);
   }
 }
@@ -47,7 +51,7 @@ __device__ __forceinline__ void keep_two(float acc, int c, float& best, int& bj,
 // more than 128 registers; the sum order over coordinates is the same.
 // One thread per point (or per listed point).  The early exits keep the
 // candidate-row addresses wave-uniform, so they are read with scalar loads.
-template <int DP, typename T>
+template <int DP, typename T, bool TRACK>
 __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
   constexpr int DCH = DP <= 128 ? DP : DP / 2;
   constexpr int NCH = DP / DCH;
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
         const float t = x[j] - cr[j];
         acc = fmaf(t, t, acc);
       }
-      keep_two(acc, c, best, bj, second);
+      keep_two<TRACK>(acc, c, best, bj, second);
     }
   } else {
     if (a.norms) {
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
       }
 #pragma unroll
       for (int q = 0; q < CB; ++q)
-        if (c0 + q < c_hi) keep_two(acc[q], c0 + q, best, bj, second);
+        if (c0 + q < c_hi) keep_two<TRACK>(acc[q], c0 + q, best, bj, second);
     }
   }
   // All global stores come after the candidate loop: a store before it could
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_fold_direct(FoldArgs a) {
                                   (unsigned long long)(unsigned)(id0 + bj));
     return;
   }
-  fold_apply(a, i, id0, best, bj, second);
+  fold_apply<TRACK>(a, i, id0, best, bj, second);
 }
 
 // Direct-form rescan of the points a screen pass listed.  A block takes 32
@@ -191,7 +195,7 @@ __device__ __forceinline__ void rescan_better(float ob, int oj, float os, float&
   }
 }
 
-template <int DP, typename T>
+template <int DP, typename T, bool TRACK>
 __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
   constexpr int P = kRescanPts, CC = kRescanCands, XS = DP + 1, CSTR = DP + 4;
   constexpr int NS = 256 / P, NI = CC / NS;  // candidate slots, candidates per slot
@@ -285,26 +289,28 @@ __global__ __launch_bounds__(256) void k_rescan(FoldArgs a) {
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
         const int j = slot + NS * i;
-        if (j < nc) keep_two(acc[i], c0 + j, best, bj, second);
+        if (j < nc) keep_two<TRACK>(acc[i], c0 + j, best, bj, second);
       }
     }
     rb[slot][r] = best;
     rj[slot][r] = bj;
-    rs2[slot][r] = second;
+    if constexpr (TRACK) rs2[slot][r] = second;
     __syncthreads();
     if (slot == 0 && r < np) {
-      for (int q = 1; q < NS; ++q) rescan_better(rb[q][r], rj[q][r], rs2[q][r], best, bj, second);
+      for (int q = 1; q < NS; ++q)
+        rescan_better(rb[q][r], rj[q][r], TRACK ? rs2[q][r] : INFINITY, best, bj, second);
       if (S == 1)
-        fold_apply(a, a.list[g * P + r], id0, best, bj, second);
+        fold_apply<TRACK>(a, a.list[g * P + r], id0, best, bj, second);
       else
         a.rpart[(int64_t)it * P + r] =
-            make_int4(__float_as_int(best), bj, __float_as_int(second), 0);
+            make_int4(__float_as_int(best), bj, TRACK ? __float_as_int(second) : 0x7F800000, 0);
     }
   }
 }
 
 // Merges the slices of a split rescan (nothing to do when S = 1). grid is the
 // rescan's launch grid, from which S is derived again.
+template <bool TRACK>
 __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
   constexpr int P = kRescanPts;
   const int nlist = *a.list_len;
@@ -320,7 +326,7 @@ __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
       const int4 v = a.rpart[(int64_t)(g * S + sl) * P + r];
       rescan_better(__int_as_float(v.x), v.y, __int_as_float(v.z), best, bj, second);
     }
-    fold_apply(a, a.list[i], id0, best, bj, second);
+    fold_apply<TRACK>(a, a.list[i], id0, best, bj, second);
   }
 }
 
@@ -341,8 +347,8 @@ __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
 constexpr int kSplitPts = 128;                 // points per block of k_fold_split
 constexpr int kSplitGroups = kSplitPts / 64;   // waves per pipeline stage
 
-template <int DP, typename T>
-__global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) void k_fold_split(FoldArgs a) {
+template <int DP, typename T, bool TRACK>
+__device__ __forceinline__ void fold_split_body(const FoldArgs& a) {
   constexpr int W = (DP + 63) / 64;
   constexpr int CH = 8;
   static_assert(W >= 3 && W <= 4, "rows of 129 to 256 padded elements");
@@ -391,7 +397,7 @@ __global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) void k_fold_split(Fol
             const float t = x[e] - cr[e];
             acc = fmaf(t, t, acc);
           }
-          keep_two(acc, c0 + jj, best, bj, second);
+          keep_two<TRACK>(acc, c0 + jj, best, bj, second);
         }
       } else {
         for (int jj = 0; jj < nc; ++jj) {
@@ -409,7 +415,19 @@ __global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) void k_fold_split(Fol
     __syncthreads();  // stage outputs of this step visible; inputs of the last step consumed
   }
   if (st != W - 1 || !live) return;
-  fold_apply(a, i, id0, best, bj, second);
+  fold_apply<TRACK>(a, i, id0, best, bj, second);
+}
+
+template <int DP, typename T>
+__global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) void k_fold_split(FoldArgs a) {
+  fold_split_body<DP, T, false>(a);
+}
+// Tracking the runner-up costs a register; held to six waves per SIMD (three
+// blocks of eight waves per CU) as the plain variant runs.
+template <int DP, typename T>
+__global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) __attribute__((amdgpu_waves_per_eu(6)))
+void k_fold_split_track(FoldArgs a) {
+  fold_split_body<DP, T, true>(a);
 }
 
 // The fold for rows of 65 to 128 padded elements (no list, no norms), each
@@ -420,8 +438,8 @@ __global__ __launch_bounds__(kSplitPts * ((DP + 63) / 64)) void k_fold_split(Fol
 // leaves each partial sum in LDS; one chunk later the second wave continues
 // the chain over the rest of the row and keeps the best candidate. Same chain
 // and candidate order as k_fold_direct, so the result is bitwise the same.
-template <int DP, typename T>
-__global__ __launch_bounds__(2 * kFoldBlock) void k_fold_pair(FoldArgs a) {
+template <int DP, typename T, bool TRACK>
+__device__ __forceinline__ void fold_pair_body(const FoldArgs& a) {
   static_assert(DP > 64 && DP <= 128, "rows of 65 to 128 padded elements");
   constexpr int H1 = DP - 64, CH = 16;
   __shared__ float part[2][CH][kFoldBlock];  // [buffer][candidate of the chunk][point]
@@ -477,16 +495,27 @@ __global__ __launch_bounds__(2 * kFoldBlock) void k_fold_pair(FoldArgs a) {
           const float t = x[e] - cr[e];
           acc = fmaf(t, t, acc);
         }
-        keep_two(acc, c0 + jj, best, bj, second);
+        keep_two<TRACK>(acc, c0 + jj, best, bj, second);
       }
     }
     __syncthreads();  // chunk it written, chunk it - 1 consumed
   }
   if (half == 0 || !live) return;
-  fold_apply(a, i, id0, best, bj, second);
+  fold_apply<TRACK>(a, i, id0, best, bj, second);
 }
 
-template <typename T>
+template <int DP, typename T>
+__global__ __launch_bounds__(2 * kFoldBlock) void k_fold_pair(FoldArgs a) {
+  fold_pair_body<DP, T, false>(a);
+}
+// Tracking the runner-up: held to seven waves per SIMD as the plain variant.
+template <int DP, typename T>
+__global__ __launch_bounds__(2 * kFoldBlock) __attribute__((amdgpu_waves_per_eu(7)))
+void k_fold_pair_track(FoldArgs a) {
+  fold_pair_body<DP, T, true>(a);
+}
+
+template <typename T, bool TRACK>
 static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
   const int work = a.list ? a.list_cap : a.n;
   if (work <= 0) return hipSuccess;
@@ -495,7 +524,7 @@ static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
   if (a.packed) {  // every row length through the one-thread-per-point fold
     switch (DP) {
 #define KMPAR_SHARD(V) \
-  case V: hipLaunchKernelGGL((k_fold_direct<V, T>), grid, block, 0, s, a); return hipGetLastError();
+  case V: hipLaunchKernelGGL((k_fold_direct<V, T, TRACK>), grid, block, 0, s, a); return hipGetLastError();
       KMPAR_SHARD(4) KMPAR_SHARD(8) KMPAR_SHARD(12) KMPAR_SHARD(16) KMPAR_SHARD(20)
       KMPAR_SHARD(24) KMPAR_SHARD(28) KMPAR_SHARD(32) KMPAR_SHARD(36) KMPAR_SHARD(40)
       KMPAR_SHARD(44) KMPAR_SHARD(48) KMPAR_SHARD(52) KMPAR_SHARD(56) KMPAR_SHARD(60)
@@ -509,7 +538,10 @@ static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
     switch (DP) {
 #define KMPAR_PAIR(V)                                                             \
   case V:                                                                  \
-    hipLaunchKernelGGL((k_fold_pair<V, T>), grid, dim3(2 * kFoldBlock), 0, s, a);      \
+    if constexpr (TRACK)                                                        \
+      hipLaunchKernelGGL((k_fold_pair_track<V, T>), grid, dim3(2 * kFoldBlock), 0, s, a); \
+    else                                                                        \
+      hipLaunchKernelGGL((k_fold_pair<V, T>), grid, dim3(2 * kFoldBlock), 0, s, a); \
     return hipGetLastError();
       KMPAR_PAIR(80) KMPAR_PAIR(96) KMPAR_PAIR(112) KMPAR_PAIR(128)
 #undef KMPAR_PAIR
@@ -520,8 +552,12 @@ static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
     switch (DP) {
 #define KMPAR_SPLIT(V)                                                            \
   case V:                                                                  \
-    hipLaunchKernelGGL((k_fold_split<V, T>), dim3((work + kSplitPts - 1) / kSplitPts),   \
-                       dim3(kSplitPts * ((V + 63) / 64)), 0, s, a);                         \
+    if constexpr (TRACK)                                                        \
+      hipLaunchKernelGGL((k_fold_split_track<V, T>), dim3((work + kSplitPts - 1) / kSplitPts), \
+                         dim3(kSplitPts * ((V + 63) / 64)), 0, s, a);                     \
+    else                                                                        \
+      hipLaunchKernelGGL((k_fold_split<V, T>), dim3((work + kSplitPts - 1) / kSplitPts), \
+                         dim3(kSplitPts * ((V + 63) / 64)), 0, s, a);                     \
     return hipGetLastError();
       KMPAR_SPLIT(160) KMPAR_SPLIT(192) KMPAR_SPLIT(224) KMPAR_SPLIT(256)
 #undef KMPAR_SPLIT
@@ -531,7 +567,7 @@ static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
   switch (DP) {
 #define KMPAR_CASE(V) \
   case V:             \
-    hipLaunchKernelGGL((k_fold_direct<V, T>), grid, block, 0, s, a); break;
+    hipLaunchKernelGGL((k_fold_direct<V, T, TRACK>), grid, block, 0, s, a); break;
     KMPAR_CASE(4) KMPAR_CASE(8) KMPAR_CASE(12) KMPAR_CASE(16) KMPAR_CASE(20) KMPAR_CASE(24)
     KMPAR_CASE(28) KMPAR_CASE(32) KMPAR_CASE(36) KMPAR_CASE(40) KMPAR_CASE(44) KMPAR_CASE(48)
     KMPAR_CASE(52) KMPAR_CASE(56) KMPAR_CASE(60) KMPAR_CASE(64) KMPAR_CASE(80) KMPAR_CASE(96)
@@ -560,16 +596,19 @@ hipError_t launch_unpack_min(const unsigned long long* packed, int n, int* A, fl
   return hipGetLastError();
 }
 
+// Passes that keep each point's runner-up distance (a.S) run the tracking
+// variants; the others (assignment passes) the lighter ones.
 hipError_t launch_fold_direct(kmpar_dtype dt, int DP, const FoldArgs& a, hipStream_t s) {
+  const bool track = a.S != nullptr;
   switch (dt) {
-    case KMPAR_F32: return launch_t<float>(DP, a, s);
-    case KMPAR_BF16: return launch_t<bf16_t>(DP, a, s);
-    case KMPAR_FP8_E4M3: return launch_t<fp8_t>(DP, a, s);
+    case KMPAR_F32: return track ? launch_t<float, true>(DP, a, s) : launch_t<float, false>(DP, a, s);
+    case KMPAR_BF16: return track ? launch_t<bf16_t, true>(DP, a, s) : launch_t<bf16_t, false>(DP, a, s);
+    case KMPAR_FP8_E4M3: return track ? launch_t<fp8_t, true>(DP, a, s) : launch_t<fp8_t, false>(DP, a, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename T>
+template <typename T, bool TRACK>
 static hipError_t launch_rescan_t(int DP, const FoldArgs& a, hipStream_t s) {
   // the listed count is only known on the device: enough blocks for the
   // largest list up to four per CU, each looping over groups of points
@@ -580,7 +619,7 @@ static hipError_t launch_rescan_t(int DP, const FoldArgs& a, hipStream_t s) {
   switch (DP) {
 #define KMPAR_CASE(V) \
   case V:             \
-    hipLaunchKernelGGL((k_rescan<V, T>), grid, block, 0, s, a); break;
+    hipLaunchKernelGGL((k_rescan<V, T, TRACK>), grid, block, 0, s, a); break;
     KMPAR_CASE(4) KMPAR_CASE(8) KMPAR_CASE(12) KMPAR_CASE(16) KMPAR_CASE(20) KMPAR_CASE(24)
     KMPAR_CASE(28) KMPAR_CASE(32) KMPAR_CASE(36) KMPAR_CASE(40) KMPAR_CASE(44) KMPAR_CASE(48)
     KMPAR_CASE(52) KMPAR_CASE(56) KMPAR_CASE(60) KMPAR_CASE(64) KMPAR_CASE(80) KMPAR_CASE(96)
@@ -592,16 +631,19 @@ static hipError_t launch_rescan_t(int DP, const FoldArgs& a, hipStream_t s) {
   }
   if (a.rpart) {
     const int mb = (min(a.list_cap, kRescanMaxItems * kRescanPts) + 255) / 256;
-    hipLaunchKernelGGL(k_rescan_merge, dim3(mb), dim3(256), 0, s, a, blocks);
+    hipLaunchKernelGGL(k_rescan_merge<TRACK>, dim3(mb), dim3(256), 0, s, a, blocks);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_rescan(kmpar_dtype dt, int DP, const FoldArgs& a, hipStream_t s) {
   switch (dt) {
-    case KMPAR_F32: return launch_rescan_t<float>(DP, a, s);
-    case KMPAR_BF16: return launch_rescan_t<bf16_t>(DP, a, s);
-    case KMPAR_FP8_E4M3: return launch_rescan_t<fp8_t>(DP, a, s);
+    case KMPAR_F32:
+      return a.S ? launch_rescan_t<float, true>(DP, a, s) : launch_rescan_t<float, false>(DP, a, s);
+    case KMPAR_BF16:
+      return a.S ? launch_rescan_t<bf16_t, true>(DP, a, s) : launch_rescan_t<bf16_t, false>(DP, a, s);
+    case KMPAR_FP8_E4M3:
+      return a.S ? launch_rescan_t<fp8_t, true>(DP, a, s) : launch_rescan_t<fp8_t, false>(DP, a, s);
   }
   return hipErrorInvalidValue;
 }
