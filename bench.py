@@ -34,7 +34,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 NSTREAMS = 3   # concurrent inits of the extra three-stream measurement
-LEGS = ("c1", "c1lloyd", "c0", "quality", "largec", "c2", "c3", "c4")
+LEGS = ("c1", "c1lloyd", "sweep", "c0", "quality", "largec", "c2", "c3", "c4")
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_screen_c1.json")
 SCREEN_SRC = os.path.join(ROOT, "paper_1203_6402_amd", "csrc", "screen_mfma.hip")
@@ -257,6 +257,34 @@ def c1_lloyd_leg(kmpar, torch, c1, iters=5):
 
 
 # ----------------------------------------------------------------------- C0
+def sweep_leg(kmpar, torch, X, ms=(1, 2, 4, 8, 16, 32, 64), reps=5):
+    """The distance pass where HBM bounds it: kmpar_assign (PLAIN) of the C1
+    rows (n = 4.8M, d = 42 FP32) against m = 1 .. 64 centers.  Per m, the
+    fold's event-timed duration, its rate in bytes -- n (4 d + 8) per launch:
+    the rows read once, the assignment and D^2 written -- against the 8 TB/s
+    HBM peak, and its FLOP rate (2 d n m) beside it."""
+    ctx = kmpar.Context(0, kmpar.MODE_PLAIN_FP32)
+    n, d = X.shape
+    rows = []
+    for m in ms:
+        C = X[:: max(1, n // m)][:m].clone()
+        ctx.assign(X, C)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            ctx.assign(X, C)
+        torch.cuda.synchronize()
+        p = ctx.profile_read(kmpar.SLOT_FOLD_DIRECT)
+        ctx.profile(False)
+        us = p["ms"] / p["launches"] * 1e3
+        gbs = n * (4 * d + 8) / (us * 1e-6) / 1e9
+        rows.append({"m": m, "us_per_launch": us, "GB_per_s": gbs, "frac_hbm": gbs / PEAK_HBM_GBS,
+                     "tflops": 2.0 * d * n * m / (us * 1e-6) / 1e12})
+        log(f"sweep m={m}: {us:.1f} us, {gbs:.0f} GB/s ({100 * gbs / PEAK_HBM_GBS:.1f}% of HBM)")
+    return {"workload": f"kmpar_assign PLAIN, C1 rows n = {n}, d = {d} FP32, m centers",
+            "bytes_per_launch": f"n (4 d + 8) = {n * (4 * d + 8)}", "sweep": rows}
+
+
 def c0_leg(kmpar, synth, torch, seed, iters=20, reps=5):
     """GaussMixture k* = 50 centers ~ N(0, 10 I) in d = 15, n = 10,000,
     k = 50, ell = 2k, r = 5, then 20 Lloyd iterations; per mode, the time of
@@ -692,6 +720,7 @@ def main():
         X = synth.heavy_tailed(n, d, seed=args.seed)
         c1 = c1_leg(kmpar, synth, torch, args, X)
     c1_lloyd = c1_lloyd_leg(kmpar, torch, c1) if "c1lloyd" in legs else None
+    sweep = sweep_leg(kmpar, torch, c1["Xd"]) if "sweep" in legs and c1 is not None else None
     c0 = c0_leg(kmpar, synth, torch, args.seed) if "c0" in legs else None
     quality = quality_leg(kmpar, synth, torch) if "quality" in legs else None
     largec = largec_leg(kmpar, synth, torch, args.seed) if "largec" in legs else None
@@ -732,6 +761,7 @@ def main():
     out["cpu_baseline"] = cpu
     out["oracle_replay_c0"] = replay
     out["c1_lloyd"] = c1_lloyd
+    out["few_centers_sweep"] = sweep
     out["c0_lloyd"] = c0
     out["quality"] = quality
     out["large_candidate_set"] = largec

@@ -10,6 +10,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "rows.hpp"
 
 namespace kmpar {
 
@@ -330,6 +331,120 @@ __global__ __launch_bounds__(256) void k_rescan_merge(FoldArgs a, int grid) {
   }
 }
 
+// Assignment passes against few centers (rows of up to 64 padded elements)
+// read X once and do little arithmetic per byte: they are bound by HBM, where
+// k_fold_direct's one thread per point issues d strided loads per lane and
+// keeps few bytes in flight.  Two forms, each folding every candidate with
+// the FMA chain of k_fold_direct (candidates in id order, ties to the lower
+// id), so the result is k_fold_direct's bit for bit.  No list, no norms, no
+// runner-up.
+//
+// m <= kStreamMaxM: one wave of 64 points per block, whose rows (one
+// contiguous span) are copied into LDS by direct 16-byte global-to-LDS loads
+// that hold no registers while in flight; many small blocks per CU keep the
+// most bytes in flight.  Each lane then reads its row from LDS and folds the
+// candidates.  The one partial wave at the end of X copies its rows lane by
+// lane.
+typedef __attribute__((address_space(3))) void fold_lds_void;
+typedef const __attribute__((address_space(1))) void fold_gbl_void;
+
+template <int DP, typename T>
+__global__ __launch_bounds__(64) void k_fold_stream(FoldArgs a) {
+  constexpr int S = (int)sizeof(T);
+  __shared__ __attribute__((aligned(16))) char rows[64 * DP * S];  // the wave's 64 raw rows
+  const int lane = threadIdx.x, d = a.d, rowb = d * S;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int64_t p = p0 + lane;
+  const bool full = p0 + 64 <= a.n;  // the whole span lies inside X
+  const bool live = p < a.n;
+  if (full) {
+    const int bytes = 64 * rowb;  // a multiple of 16
+    const char* src = static_cast<const char*>(a.X) + p0 * rowb;
+    for (int v0 = 0; v0 < bytes; v0 += 1024)
+      if (v0 + 16 * lane < bytes)
+        __builtin_amdgcn_global_load_lds((fold_gbl_void*)(src + v0 + 16 * lane),
+                                         (fold_lds_void*)(rows + v0), 16, 0, 0);
+  } else if (live) {  // the partial wave: each lane copies its own row
+    const T* X = static_cast<const T*>(a.X);
+    for (int j = 0; j < d; ++j) reinterpret_cast<T*>(rows)[lane * d + j] = X[p * d + j];
+  }
+  const float sc = live ? row_scale_of<T>(a.row_scale, p) : 1.0f;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (!live) return;
+  float x[DP];
+  const T* xr = reinterpret_cast<const T*>(rows + lane * rowb);
+#pragma unroll
+  for (int j = 0; j < DP; ++j) x[j] = j < d ? Elem<T>::get(xr, j, sc) : 0.0f;
+  const int m = a.m_host, id0 = a.id0_host;
+  const float* __restrict__ C = a.C + (int64_t)id0 * DP;
+  float best = INFINITY, second = INFINITY;
+  int bj = -1;
+  for (int c = 0; c < m; ++c) {
+    const float* __restrict__ cr = C + (int64_t)c * DP;
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < DP; ++j) {
+      const float t = x[j] - cr[j];
+      acc = fmaf(t, t, acc);
+    }
+    keep_two<false>(acc, c, best, bj, second);
+  }
+  fold_apply<false>(a, (int)p, id0, best, bj, second);
+}
+
+// kStreamMaxM < m <= kStagedMaxM: blocks of four waves stage their 64 rows
+// through LDS with coalesced 16-byte loads (the first pass's staging), and
+// the waves split the candidates (wave w takes c = w, w + 4, ...), each
+// keeping the nearest of its share; the four are merged in candidate order
+// (smaller distance, then lower id).
+template <int DP, typename T>
+__global__ __launch_bounds__(256) void k_fold_few(FoldArgs a) {
+  __shared__ float xs[64 * (DP + 1)];  // [64][XS], XS = d + 1 when d is a multiple of 32
+  __shared__ float ss[64];             // FP8 row scales
+  __shared__ float rb[4][64];
+  __shared__ int rj[4][64];
+  const int d = a.d, pad = d % 32 == 0 ? 1 : 0, XS = d + pad;
+  const int p0 = blockIdx.x * 64;
+  const int np = max(0, min(64, a.n - p0));
+  stage_rows<T>(static_cast<const T*>(a.X), a.row_scale, p0, np, d, pad, ss, xs);
+  __syncthreads();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), pl = threadIdx.x % 64;
+  float x[DP];
+#pragma unroll
+  for (int j = 0; j < DP; ++j) x[j] = (j < d && pl < np) ? xs[pl * XS + j] : 0.0f;
+  const int m = a.m_host, id0 = a.id0_host;
+  const float* __restrict__ C = a.C + (int64_t)id0 * DP;
+  float best = INFINITY, second = INFINITY;
+  int bj = -1;
+  for (int c = w; c < m; c += 4) {
+    const float* __restrict__ cr = C + (int64_t)c * DP;
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < DP; ++j) {
+      const float t = x[j] - cr[j];
+      acc = fmaf(t, t, acc);
+    }
+    keep_two<false>(acc, c, best, bj, second);
+  }
+  rb[w][pl] = best;
+  rj[w][pl] = bj;
+  __syncthreads();
+  if (w != 0 || pl >= np) return;
+#pragma unroll
+  for (int q = 1; q < 4; ++q) {
+    const float ob = rb[q][pl];
+    const int oj = rj[q][pl];
+    if (ob < best || (ob == best && (unsigned)oj < (unsigned)bj)) {
+      best = ob;
+      bj = oj;
+    }
+  }
+  fold_apply<false>(a, p0 + pl, id0, best, bj, second);
+}
+
 // The fold for rows of more than 128 padded elements (no list, no norms),
 // each row split over W = ceil(DP / 64) waves: a block of 128 W threads holds its
 // kSplitPts = 128 points in two groups of W waves, wave s of a group keeping elements
@@ -545,6 +660,23 @@ static hipError_t launch_t(int DP, const FoldArgs& a, hipStream_t s) {
     return hipGetLastError();
       KMPAR_PAIR(80) KMPAR_PAIR(96) KMPAR_PAIR(112) KMPAR_PAIR(128)
 #undef KMPAR_PAIR
+      default: break;
+    }
+  }
+  if (!a.list && !a.norms && !a.packed && !a.S && !a.rs && a.m_host <= kStagedMaxM && DP <= 64) {
+    switch (DP) {
+#define KMPAR_STAGED(V)                                                                     \
+  case V:                                                                                   \
+    if (a.m_host <= kStreamMaxM)                                                            \
+      hipLaunchKernelGGL((k_fold_stream<V, T>), dim3((a.n + 63) / 64), dim3(64), 0, s, a); \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_fold_few<V, T>), dim3((a.n + 63) / 64), dim3(256), 0, s, a);   \
+    return hipGetLastError();
+      KMPAR_STAGED(4) KMPAR_STAGED(8) KMPAR_STAGED(12) KMPAR_STAGED(16) KMPAR_STAGED(20)
+      KMPAR_STAGED(24) KMPAR_STAGED(28) KMPAR_STAGED(32) KMPAR_STAGED(36) KMPAR_STAGED(40)
+      KMPAR_STAGED(44) KMPAR_STAGED(48) KMPAR_STAGED(52) KMPAR_STAGED(56) KMPAR_STAGED(60)
+      KMPAR_STAGED(64)
+#undef KMPAR_STAGED
       default: break;
     }
   }

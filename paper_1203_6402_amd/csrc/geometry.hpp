@@ -61,6 +61,13 @@ KMPAR_HD inline int seg_width(int d) {
   return w;
 }
 
+// Assignment passes against at most this many centers (rows of up to 64
+// padded elements) stage X through LDS (bound by HBM): one-wave blocks with
+// direct global-to-LDS copies up to kStreamMaxM centers (k_fold_stream),
+// four-wave blocks splitting the centers beyond (k_fold_few).
+constexpr int kStreamMaxM = 4;
+constexpr int kStagedMaxM = 64;
+
 // Rescan of listed points: points per block step, grid limit (and slice-
 // winner slots / kRescanPts), candidate rows per LDS chunk, most slices.
 constexpr int kRescanPts = 32;

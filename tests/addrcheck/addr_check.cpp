@@ -7,6 +7,7 @@
 //     the MFMA operand and bias reads, the per-wave merge, the staging of
 //     the wave's rows, the refinement reads, D2 / A / S and the list;
 //   * the operand preparation (k_prep_a, k_first_prep, k_prep_b);
+//   * the few-center folds (k_fold_stream, k_fold_few);
 //   * the listed-point rescan (k_rescan, k_rescan_merge);
 //   * the Lloyd update (k_sort_count, k_sort_scatter, k_chunk_list,
 //     k_seg_sum, k_centroid), run on a concrete assignment;
@@ -358,6 +359,84 @@ void check_prep_a(Checker& ck, Dtype t, int split, int n, int d, bool first, int
   }
 }
 
+// k_fold_stream: one wave of 64 points per block; full spans copied into
+// LDS by 16-byte direct loads, the partial wave lane by lane.
+void check_fold_stream(Checker& ck, Dtype t, int n, int d, int m, int id0, int64_t crows, int sample) {
+  const int DP = padded_dim_hd(d), Sz = elem_size(t), rowb = d * Sz;
+  const int64_t lds = (int64_t)64 * DP * Sz, Xsz = (int64_t)n * d * Sz, Csz = crows * DP * 4;
+  if (DP > 64 || m > kStreamMaxM) ck.fail("stream fold outside its shape");
+  if ((64 * rowb) % 16) ck.fail("span not whole 16-byte units");
+  const int64_t nblocks = (n + 63) / 64;
+  for (int64_t blk : pick_blocks(nblocks, sample, (uint64_t)n * 11 + d + m)) {
+    const int64_t p0 = blk * 64;
+    const bool full = p0 + 64 <= n;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int64_t p = p0 + lane;
+      const bool live = p < n;
+      if (full) {
+        for (int v0 = 0; v0 < 64 * rowb; v0 += 1024)
+          if (v0 + 16 * lane < 64 * rowb) {
+            ck.in("X span", p0 * rowb + v0 + 16 * lane, 16, Xsz, blk, lane);
+            ck.in("LDS rows", v0 + 16 * lane, 16, lds, blk, lane);
+          }
+      } else if (live) {
+        for (int j = 0; j < d; j += std::max(1, d - 1)) {
+          ck.in("X row", (p * d + j) * Sz, Sz, Xsz, blk, lane);
+          ck.in("LDS row copy", ((int64_t)lane * d + j) * Sz, Sz, lds, blk, lane);
+        }
+      }
+      if (!live) continue;
+      if (t == FP8) ck.in("row_scale", p * 4, 4, (int64_t)n * 4, blk, lane);
+      ck.in("LDS row read", (int64_t)lane * rowb, rowb, lds, blk, lane);
+      for (int c = 0; c < m; ++c) ck.in("C row", ((int64_t)(id0 + c) * DP) * 4, (int64_t)DP * 4, Csz, blk, lane);
+      ck.in("D2/A", p * 4, 4, (int64_t)n * 4, blk, lane);
+    }
+  }
+}
+
+// k_fold_few: 64 rows staged through LDS per block of 256 threads, the
+// four waves splitting up to kStagedMaxM candidates.
+void check_fold_few(Checker& ck, Dtype t, int n, int d, int m, int id0, int64_t crows, int sample) {
+  const int DP = padded_dim_hd(d), Sz = elem_size(t), EPV = 16 / Sz;
+  const int pad = d % 32 == 0 ? 1 : 0, XS = d + pad;
+  const int64_t xs_sz = (int64_t)64 * (DP + 1) * 4, Xsz = (int64_t)n * d * Sz, Csz = crows * DP * 4;
+  if (DP > 64 || m > kStagedMaxM) ck.fail("few-center fold outside its shape");
+  const int64_t nblocks = (n + 63) / 64;
+  for (int64_t blk : pick_blocks(nblocks, sample, (uint64_t)n * 5 + d + m)) {
+    const int64_t p0 = blk * 64;
+    const int np = (int)std::max<int64_t>(0, std::min<int64_t>(64, n - p0));
+    const int cnt = np * d, nvec = cnt * Sz / 16;
+    for (int tid = 0; tid < 256; ++tid) {
+      if (t == FP8 && tid < np) ck.in("row_scale", (p0 + tid) * 4, 4, (int64_t)n * 4, blk, tid);
+      for (int v0 = 0; v0 < nvec; v0 += 4 * 256)
+        for (int u = 0; u < 4; ++u) {
+          const int idx = v0 + u * 256 + tid;
+          if (idx >= nvec) continue;
+          ck.in("X rows", p0 * d * Sz + (int64_t)idx * 16, 16, Xsz, blk, tid);
+          const int e = idx * EPV;
+          int row = e / d, col = e - row * d;
+          for (int k = 0; k < EPV; ++k) {
+            ck.in("LDS xs", ((int64_t)e + k + row * pad) * 4, 4, xs_sz, blk, tid);
+            if (++col == d) {
+              col = 0;
+              ++row;
+            }
+          }
+        }
+      for (int e = nvec * EPV + tid; e < cnt; e += 256) {
+        ck.in("X tail", (p0 * d + e) * Sz, Sz, Xsz, blk, tid);
+        ck.in("LDS xs tail", ((int64_t)e + (e / d) * pad) * 4, 4, xs_sz, blk, tid);
+      }
+      const int w = tid / 64, pl = tid % 64;
+      for (int j = 0; j < d; j += std::max(1, d - 1))
+        if (pl < np) ck.in("LDS row", ((int64_t)pl * XS + j) * 4, 4, xs_sz, blk, tid);
+      for (int c = w; c < m; c += 4)
+        ck.in("C row", ((int64_t)(id0 + c) * DP) * 4, (int64_t)DP * 4, Csz, blk, tid);
+      if (w == 0 && pl < np) ck.in("D2/A", (p0 + pl) * 4, 4, (int64_t)n * 4, blk, tid);
+    }
+  }
+}
+
 // k_rescan + k_rescan_merge for a list of nlist points.
 void check_rescan(Checker& ck, Dtype t, int n, int d, int m, int id0, int64_t crows, int nlist) {
   const int DP = padded_dim_hd(d), Sz = elem_size(t);
@@ -583,6 +662,29 @@ int main(int argc, char** argv) {
         if (nl <= c.n)
           run("rescan " + tag + " list=" + std::to_string(nl),
               [&] { check_rescan(ck, c.t, c.n, c.d, c.k, 0, c.k, nl); });
+    }
+  }
+
+  // ---- assignment passes against few centers (staged rows)
+  if (!legacy) {
+    struct FewCase { const char* name; Dtype t; int n, d, m; };
+    std::vector<FewCase> few = {
+        {"staged C1 4.8M x 42 f32 m=1", F32, 4800000, 42, 1},
+        {"staged C1 4.8M x 42 f32 m=64", F32, 4800000, 42, 64},
+        {"staged 10007 x 64 f32 m=33", F32, 10007, 64, 33},
+        {"staged 10007 x 32 bf16 m=5", BF16, 10007, 32, 5},
+        {"staged 10007 x 3 fp8 m=2", FP8, 10007, 3, 2},
+        {"staged 999 x 61 fp8 m=64", FP8, 999, 61, 64},
+        {"staged 1 x 1 f32 m=1", F32, 1, 1, 1},
+        {"staged 10007 x 64 f32 m=4", F32, 10007, 64, 4},
+        {"staged 129 x 17 fp8 m=3", FP8, 129, 17, 3},
+        {"staged 4.8M+5 x 42 f32 m=5", F32, 4800005, 42, 5},
+    };
+    for (const auto& c : few) {
+      if (c.m <= kStreamMaxM)
+        run(c.name, [&] { check_fold_stream(ck, c.t, c.n, c.d, c.m, 0, c.m, 16); });
+      else
+        run(c.name, [&] { check_fold_few(ck, c.t, c.n, c.d, c.m, 0, c.m, 16); });
     }
   }
 

@@ -166,6 +166,39 @@ def test_assign_and_cost(ctx, n, d, m):
     assert phi.item() == pytest.approx(O.total(od2), rel=D2_RTOL)
 
 
+@pytest.mark.parametrize("dt", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("d,m", [(3, 1), (15, 2), (42, 4), (64, 3), (32, 5), (42, 31), (64, 64), (37, 64),
+                                 (42, 65)])
+def test_assign_few_centers(ctx, dt, d, m):
+    # Passes against at most 64 centers (rows of up to 64 padded elements)
+    # stage X through LDS; the result must be the one-thread fold's bit for
+    # bit (the sharded form with one shard runs that fold) and the oracle's
+    # outside the FP32 band.  m = 65 is past the staged form (the one-thread
+    # fold itself).
+    n = 10007
+    X = synth.gauss_mixture(n, d, 8, 10.0, seed=d + m)
+    C = (X[np.random.default_rng(m).choice(n, m, replace=False)] + 0.1).astype(np.float32)
+    if dt == "f32":
+        Xd, rs, X64 = _dev(X), None, X.astype(np.float64)
+    elif dt == "bf16":
+        Xb = to_bf16_bits(X)
+        Xd, rs, X64 = _dev(Xb).view(torch.bfloat16), None, decoded_fp64(Xb, "bf16")
+    else:
+        q, sc = to_e4m3(X)
+        Xd, rs, X64 = _dev(q), _dev(sc), decoded_fp64(q, "fp8", sc)
+    a, d2 = ctx.assign(Xd, _dev(C), row_scale=rs)
+    a1, d21, phi1 = ctx.assign_sharded(Xd, _dev(C), 1, row_scale=rs)
+    torch.cuda.synchronize()
+    assert torch.equal(a, a1) and torch.equal(d2, d21)
+    a, d2 = a.cpu().numpy(), d2.cpu().numpy().astype(np.float64)
+    oa, od2, osnd = O.nearest(X64, C.astype(np.float64))
+    pos = od2 > 0
+    np.testing.assert_allclose(d2[pos], od2[pos], rtol=D2_RTOL)
+    diff = a != oa
+    gap = (osnd - od2) / np.maximum(od2, 1e-300)
+    assert np.all(gap[diff] <= O.fp32_band(d)), "argmin differs outside the band"
+
+
 def test_lloyd_steps(ctx):
     X = synth.gauss_mixture(20000, 15, 50, 10.0, seed=2)
     X64 = X.astype(np.float64)
