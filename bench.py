@@ -37,7 +37,8 @@ NSTREAMS = 3   # concurrent inits of the extra three-stream measurement
 LEGS = ("c1", "c1lloyd", "sweep", "c0", "quality", "largec", "c2", "c3", "c4")
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_screen_c1.json")
-SCREEN_SRC = os.path.join(ROOT, "paper_1203_6402_amd", "csrc", "screen_mfma.hip")
+SCREEN_SRCS = [os.path.join(ROOT, "paper_1203_6402_amd", "csrc", f)
+               for f in ("screen_mfma.hip", "geometry.hpp")]
 
 
 def log(msg: str):
@@ -82,16 +83,19 @@ def screen_roofline(kmpar, ctx, d, profile=None, traffic=None):
 
 
 def screen_traffic():
-    """HBM bytes per C1 k_screen launch from the committed counter summary,
-    or None when the summary is missing or the kernel source changed since."""
+    """HBM bytes per C1 screen launch from the committed counter summary, or
+    None when the summary is missing or the kernel sources (the screen and
+    its launch geometry) changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        with open(SCREEN_SRC, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in SCREEN_SRCS:
+            with open(src, "rb") as f:
+                h.update(f.read())
     except OSError:
         return None
-    if t.get("source_sha256") != sha:
+    if t.get("source_sha256") != h.hexdigest():
         return None
     return t["hbm_bytes_per_launch"]
 
