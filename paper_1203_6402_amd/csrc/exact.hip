@@ -245,37 +245,52 @@ __global__ __launch_bounds__(256) void k_kpp_first(const T* X, const float* row_
   }
 }
 
-// One step over blocks of 64 rows (staged through LDS with coalesced loads):
-// fold the latest center crow into D^2 (FP32 direct form, coordinates in
-// ascending order, as every fold computes it; first: D^2 is that distance),
-// then, when t > 0, the key of draw t; each block writes its smallest (key,
-// index) and the FP64 sum of its D^2 (fixed order).
+// One step over blocks of one wave and 64 rows: the rows, one contiguous
+// span, are copied into LDS by direct 16-byte global-to-LDS loads (the one
+// partial block at the end of X copies them lane by lane); each lane folds
+// the latest center crow into its point's D^2 (FP32 direct form, coordinates
+// in ascending order, as every fold computes it; first: D^2 is that
+// distance), then, when t > 0, computes the key of draw t; the block writes
+// its smallest (key, index) and the FP64 sum of its D^2 (fixed order).
+typedef __attribute__((address_space(3))) void kpp_lds_void;
+typedef const __attribute__((address_space(1))) void kpp_gbl_void;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_kpp_step(const T* X, const float* row_scale, int n, int d,
-                                                  const float* crow, int first, uint64_t seed,
-                                                  int t, uint64_t inst, const int* stop, float* D2,
-                                                  unsigned long long* pkey, int* pidx,
-                                                  double* pphi) {
-  extern __shared__ float xs[];  // [64][XS] rows, then the center [d]
-  __shared__ float ss[64];
+__global__ __launch_bounds__(64) void k_kpp_step(const T* X, const float* row_scale, int n, int d,
+                                                 const float* crow, int first, uint64_t seed,
+                                                 int t, uint64_t inst, const int* stop, float* D2,
+                                                 unsigned long long* pkey, int* pidx,
+                                                 double* pphi) {
+  extern __shared__ __attribute__((aligned(16))) char rows[];  // [64][d] raw elements
   if (*stop) return;
-  const int pad = d % 32 == 0 ? 1 : 0, XS = d + pad;
-  float* cs = xs + 64 * XS;
-  const int p0 = blockIdx.x * 64;
-  const int np = max(0, min(64, n - p0));
-  for (int e = threadIdx.x; e < d; e += 256) cs[e] = crow[e];
-  stage_rows<T>(X, row_scale, p0, np, d, pad, ss, xs);
-  __syncthreads();
-  if (threadIdx.x >= kWave) return;
+  constexpr int S = (int)sizeof(T);
+  const int lane = threadIdx.x, rowb = d * S;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int64_t i = p0 + lane;
+  const bool live = i < n;
+  if (p0 + 64 <= n) {
+    const int bytes = 64 * rowb;  // a multiple of 16
+    const char* src = reinterpret_cast<const char*>(X) + p0 * rowb;
+    for (int v0 = 0; v0 < bytes; v0 += 1024)
+      if (v0 + 16 * lane < bytes)
+        __builtin_amdgcn_global_load_lds((kpp_gbl_void*)(src + v0 + 16 * lane),
+                                         (kpp_lds_void*)(rows + v0), 16, 0, 0);
+  } else if (live) {
+    for (int e = 0; e < d; ++e) reinterpret_cast<T*>(rows)[lane * d + e] = X[i * d + e];
+  }
+  const float sc = live ? row_scale_of<T>(row_scale, i) : 1.0f;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   unsigned long long kb = ~0ull;
   int ki = INT_MAX;
   double ph = 0.0;
-  if ((int)threadIdx.x < np) {
-    const int i = p0 + threadIdx.x;
-    const float* xr = xs + threadIdx.x * XS;
+  if (live) {
+    const T* xr = reinterpret_cast<const T*>(rows + lane * rowb);
     float acc = 0.0f;
     for (int e = 0; e < d; ++e) {
-      const float tt = xr[e] - cs[e];
+      const float tt = Elem<T>::get(xr, e, sc) - crow[e];
       acc = fmaf(tt, tt, acc);
     }
     float dd = acc;
@@ -287,7 +302,7 @@ __global__ __launch_bounds__(256) void k_kpp_step(const T* X, const float* row_s
     ph = (double)dd;
     if (t > 0) {
       kb = key_bits(race_key(dd, seed, (uint64_t)i, (uint64_t)t, inst));
-      ki = i;
+      ki = (int)i;
     }
   }
 #pragma unroll
@@ -300,7 +315,7 @@ __global__ __launch_bounds__(256) void k_kpp_step(const T* X, const float* row_s
     }
   }
   ph = wave_sum(ph);
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     pkey[blockIdx.x] = kb;
     pidx[blockIdx.x] = ki;
     pphi[blockIdx.x] = ph;
@@ -324,18 +339,30 @@ __global__ __launch_bounds__(1024) void k_kpp_pick(const unsigned long long* pke
   __shared__ double sh[1024 / kWave + 1];
   __shared__ int sp;
   if (*stop) return;
-  const int R = (nb + 1023) / 1024;
-  const int lo = min(nb, (int)threadIdx.x * R), hi = min(nb, lo + R);
   unsigned long long kb = ~0ull;
   int ki = INT_MAX;
   double ph = 0.0;
-  for (int b = lo; b < hi; ++b) {
-    ph += pphi[b];
-    const unsigned long long ob = pkey[b];
-    const int oi = pidx[b];
-    if (ob < kb || (ob == kb && oi < ki)) {
-      kb = ob;
-      ki = oi;
+  // block partials b = tid, tid + 1024, ... (each wave's loads coalesced),
+  // kPickAhead rounds of loads in flight before they are added in that order
+  constexpr int kPickAhead = 8;
+  for (int b0 = threadIdx.x; b0 < nb; b0 += kPickAhead * 1024) {
+    double vp[kPickAhead];
+    unsigned long long vk[kPickAhead];
+    int vi[kPickAhead];
+#pragma unroll
+    for (int u = 0; u < kPickAhead; ++u) {
+      const int b = b0 + u * 1024;
+      vp[u] = b < nb ? pphi[b] : 0.0;
+      vk[u] = b < nb ? pkey[b] : ~0ull;
+      vi[u] = b < nb ? pidx[b] : INT_MAX;
+    }
+#pragma unroll
+    for (int u = 0; u < kPickAhead; ++u) {
+      if (b0 + u * 1024 < nb) ph += vp[u];
+      if (vk[u] < kb || (vk[u] == kb && vi[u] < ki)) {
+        kb = vk[u];
+        ki = vi[u];
+      }
     }
   }
   const double phi = block_sum<double, 1024>(ph, sh);
@@ -393,14 +420,14 @@ static hipError_t run_kmeanspp(const void* Xv, const float* rsc, int n, int d, i
                                float* centers, double* phi_steps, kmpar_stats* st, hipStream_t s) {
   const T* X = static_cast<const T*>(Xv);
   const int nb = (n + 63) / 64;
-  const size_t lds = ((size_t)64 * (d + (d % 32 == 0 ? 1 : 0)) + d) * 4;
+  const size_t lds = (size_t)64 * d * sizeof(T);  // the block's raw rows
   hipError_t e = hipFuncSetAttribute((const void*)k_kpp_step<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_kpp_first<T>, dim3(1), dim3(256), 0, s, X, rsc, n, d, seed, inst, w.stop,
                      picks, centers, w.crow, st);
   for (int step = 1; step <= k; ++step) {
-    hipLaunchKernelGGL(k_kpp_step<T>, dim3(nb), dim3(256), lds, s, X, rsc, n, d, w.crow,
+    hipLaunchKernelGGL(k_kpp_step<T>, dim3(nb), dim3(64), lds, s, X, rsc, n, d, w.crow,
                        step == 1 ? 1 : 0, seed, step < k ? step : 0, inst, w.stop, w.D2, w.pkey,
                        w.pidx, w.pphi);
     hipLaunchKernelGGL(k_kpp_pick<T>, dim3(1), dim3(1024), 0, s, w.pkey, w.pidx, w.pphi, nb, X,

@@ -7,7 +7,7 @@
 //     the MFMA operand and bias reads, the per-wave merge, the staging of
 //     the wave's rows, the refinement reads, D2 / A / S and the list;
 //   * the operand preparation (k_prep_a, k_first_prep, k_prep_b);
-//   * the few-center folds (k_fold_stream, k_fold_few);
+//   * the few-center folds (k_fold_stream, k_fold_few) and the k-means++ step;
 //   * the listed-point rescan (k_rescan, k_rescan_merge);
 //   * the Lloyd update (k_sort_count, k_sort_scatter, k_chunk_list,
 //     k_seg_sum, k_centroid), run on a concrete assignment;
@@ -394,6 +394,39 @@ void check_fold_stream(Checker& ck, Dtype t, int n, int d, int m, int id0, int64
   }
 }
 
+// k_kpp_step (k-means++ on all of X): one wave of 64 rows per block copied
+// into a dynamic LDS buffer of 64 d elements, the latest center read per
+// coordinate, D^2 read and written, one (key, index, sum) per block.
+void check_kpp_step(Checker& ck, Dtype t, int n, int d, int sample) {
+  const int Sz = elem_size(t), rowb = d * Sz;
+  const int64_t lds = (int64_t)64 * d * Sz, Xsz = (int64_t)n * d * Sz;
+  const int64_t nblocks = (n + 63) / 64;
+  if ((64 * rowb) % 16) ck.fail("span not whole 16-byte units");
+  for (int64_t blk : pick_blocks(nblocks, sample, (uint64_t)n * 13 + d)) {
+    const int64_t p0 = blk * 64;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int64_t i = p0 + lane;
+      if (p0 + 64 <= n) {
+        for (int v0 = 0; v0 < 64 * rowb; v0 += 1024)
+          if (v0 + 16 * lane < 64 * rowb) {
+            ck.in("X span", p0 * rowb + v0 + 16 * lane, 16, Xsz, blk, lane);
+            ck.in("LDS rows", v0 + 16 * lane, 16, lds, blk, lane);
+          }
+      } else if (i < n) {
+        ck.in("X row", i * d * Sz, (int64_t)d * Sz, Xsz, blk, lane);
+        ck.in("LDS row copy", (int64_t)lane * d * Sz, (int64_t)d * Sz, lds, blk, lane);
+      }
+      if (i < n) {
+        ck.in("LDS row read", (int64_t)lane * rowb, rowb, lds, blk, lane);
+        ck.in("crow", 0, (int64_t)d * 4, (int64_t)d * 4, blk, lane);
+        ck.in("D2", i * 4, 4, (int64_t)n * 4, blk, lane);
+        if (t == FP8) ck.in("row_scale", i * 4, 4, (int64_t)n * 4, blk, lane);
+      }
+    }
+    ck.in("block partials", blk * 8, 8, nblocks * 8, blk, 0);
+  }
+}
+
 // k_fold_few: 64 rows staged through LDS per block of 256 threads, the
 // four waves splitting up to kStagedMaxM candidates.
 void check_fold_few(Checker& ck, Dtype t, int n, int d, int m, int id0, int64_t crows, int sample) {
@@ -686,6 +719,14 @@ int main(int argc, char** argv) {
       else
         run(c.name, [&] { check_fold_few(ck, c.t, c.n, c.d, c.m, 0, c.m, 16); });
     }
+  }
+
+  // ---- k-means++ steps
+  if (!legacy) {
+    run("kpp step C1 4.8M x 42 f32", [&] { check_kpp_step(ck, F32, 4800000, 42, 16); });
+    run("kpp step 50M x 256 fp8", [&] { check_kpp_step(ck, FP8, 50000000, 256, 16); });
+    run("kpp step 1001 x 7 bf16", [&] { check_kpp_step(ck, BF16, 1001, 7, 16); });
+    run("kpp step 63 x 3 fp8", [&] { check_kpp_step(ck, FP8, 63, 3, 16); });
   }
 
   // ---- the Lloyd update on concrete assignments
