@@ -444,6 +444,7 @@ struct ReclArgs {
   float* centers;      // [k][d] output rows
   kmpar_stats* st;
   double band;         // FP32 band of the distances (see pick_near_end)
+  int xstride;         // workgroup b of the recluster is workgroup b * xstride of the grid
 };
 
 // The recluster's draws, one thread each, ahead of the sequential picks.
@@ -463,12 +464,14 @@ __global__ __launch_bounds__(kReclBlock) void k_recluster_grid(ReclArgs a) {
   __shared__ double sh_u, sh_base, sh_top, sh_plo, sh_phi;
   __shared__ int sh_pick, sh_owner, sh_failed, sh_stop, sh_pflag;
   constexpr int NW = kReclBlock / kWave;
-  const int b = blockIdx.x, tid = threadIdx.x, DP = a.DP, d = a.d;
+  // only every xstride-th workgroup takes part (see launch_recluster)
+  if (blockIdx.x % a.xstride) return;
+  const int b = blockIdx.x / a.xstride, tid = threadIdx.x, DP = a.DP, d = a.d;
   const int lane = tid % kWave, wv = tid / kWave;
   const int DL = LROWS ? DP + 1 : DP;  // odd LDS row stride: rows land in different banks
   const int m = *a.rs_end;
   // the blocks the candidate count needs (the grid is sized for the capacity)
-  const int G = min((int)gridDim.x, (m + a.fit - 1) / a.fit);
+  const int G = min((int)gridDim.x / a.xstride, (m + a.fit - 1) / a.fit);
   if (b >= G) return;
   const int lo = (int)((int64_t)b * m / G), hi = (int)((int64_t)(b + 1) * m / G);
   const int ns = hi - lo;
@@ -746,7 +749,7 @@ bool recluster_plan(int capT, int DP, int num_cu, bool global_rows, ReclPlan* p)
   int fit = (int)std::min<size_t>(kReclBlock, (kReclLdsBudget - head) / per_l);
   int G = (capT + fit - 1) / fit;
   if (!global_rows && G <= gmax) {
-    *p = ReclPlan{G, fit, true, head + (size_t)fit * per_l};
+    *p = ReclPlan{G, fit, true, head + (size_t)fit * per_l, num_cu};
     return true;
   }
   // global rows: one candidate per thread while the CUs suffice
@@ -754,7 +757,7 @@ bool recluster_plan(int capT, int DP, int num_cu, bool global_rows, ReclPlan* p)
   fit = (capT + G - 1) / G;
   const size_t lds = head + (size_t)fit * 8;
   if (lds > kReclLdsBudget) return false;
-  *p = ReclPlan{G, fit, false, lds};
+  *p = ReclPlan{G, fit, false, lds, num_cu};
   return true;
 }
 
@@ -787,14 +790,20 @@ hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, cons
   a.centers = centers;
   a.st = st;
   a.band = band;
+  // Workgroups are dealt to the XCDs in turn (workgroup i to XCD i mod 8),
+  // so when the recluster needs at most one XCD's CUs, a grid of 8 G
+  // workgroups of which every eighth takes part keeps its exchanges within
+  // one XCD's L2; the others exit at once.
+  a.xstride = G * kXcds <= plan.num_cu ? kXcds : 1;
   const void* fn = plan.lds_rows ? (const void*)k_recluster_grid<true>
                                  : (const void*)k_recluster_grid<false>;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds);
   if (e != hipSuccess) return e;
+  const int grid = G * a.xstride;
   if (plan.lds_rows)
-    hipLaunchKernelGGL(k_recluster_grid<true>, dim3(G), dim3(kReclBlock), plan.lds, s, a);
+    hipLaunchKernelGGL(k_recluster_grid<true>, dim3(grid), dim3(kReclBlock), plan.lds, s, a);
   else
-    hipLaunchKernelGGL(k_recluster_grid<false>, dim3(G), dim3(kReclBlock), plan.lds, s, a);
+    hipLaunchKernelGGL(k_recluster_grid<false>, dim3(grid), dim3(kReclBlock), plan.lds, s, a);
   KMPAR_RET_LAST();
 }
 

@@ -162,7 +162,9 @@ struct ReclPlan {
   int fit;
   bool lds_rows;
   size_t lds;
+  int num_cu;  // CUs of the device the plan is for
 };
+constexpr int kXcds = 8;  // XCDs of the chip, each with its own L2
 constexpr int kReclMaxBlocks = 512;
 bool recluster_plan(int capT, int DP, int num_cu, bool global_rows, ReclPlan* p);
 hipError_t launch_recluster(const float* Call, int DP, int d, const int* w, const int* rs_end,

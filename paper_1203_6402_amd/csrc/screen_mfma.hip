@@ -397,8 +397,12 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   static_assert(CT >= 1 && CT * KS * 64 * 16 <= STAGE, "chunk exceeds its staging buffer");
   constexpr int CHUNK_V = CT * KS * 64;             // 16-byte vectors per chunk
   // Two full staging buffers whatever the chunk: after the pass each wave
-  // reuses a quarter of them (WSTAGE bytes) for its own data.
-  __shared__ u16x8 sB[2][STAGE / 16];
+  // reuses a quarter of them (WSTAGE bytes) for its own data.  They are two
+  // distinct arrays, and each chunk reads one named array while the direct
+  // loads fill the other: the compiler then knows that the chunk's LDS reads
+  // do not alias the loads in flight and does not wait for them.
+  __shared__ u16x8 sB0[STAGE / 16];
+  __shared__ u16x8 sB1[STAGE / 16];
   static_assert(2 * STAGE == kWaves * WSTAGE, "wave quarters must tile the buffers");
   constexpr bool SC = ScaledRows<T>::value;  // codes with row scales
   constexpr bool BCAST = screen_bcast(KS, ONEG, SC);  // LDS for four copies of each bias
@@ -420,12 +424,11 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const u16x8* __restrict__ Bg = static_cast<const u16x8*>(a.B);
 
-  // Issues the direct loads of chunk c into buffer c & 1 (each wave moves
-  // 1 KB per instruction; lane i lands at base + 16 i).
-  auto stage = [&](int c) {
+  // Issues the direct loads of chunk c into dst (each wave moves 1 KB per
+  // instruction; lane i lands at base + 16 i).
+  auto stage = [&](int c, u16x8* dst) __attribute__((always_inline)) {
     const int nt = min(CT, ntiles - c * CT);
     const int nv = nt * KS * 64;
-    u16x8* dst = sB[c & 1];
     const u16x8* src = Bg + (int64_t)c * CHUNK_V;
     for (int v0 = wave * 64; v0 < nv; v0 += kWaves * 64)
       __builtin_amdgcn_global_load_lds((gbl_void*)(src + v0 + lane), (lds_void*)(dst + v0), 16, 0, 0);
@@ -445,7 +448,7 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     }
   };
 
-  if (nchunks > 0) stage(0);
+  if (nchunks > 0) stage(0, sB0);
   stage_ncg(0);
 
   // A operands of this wave's points, kept in registers for the pass: from
@@ -521,7 +524,9 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
       ix[r][i] = -1;
     }
 
-  for (int c = 0; c < nchunks; ++c) {
+  // Chunk c, held in buf (sB0 for even c, sB1 for odd c); chunk c + 1 goes
+  // to next.
+  auto chunk = [&](int c, const u16x8* buf, u16x8* next) __attribute__((always_inline)) {
 #pragma unroll
     for (int i = 0; i < NBT; ++i) {
       const int e = i * kWaves * 64 + threadIdx.x;
@@ -538,11 +543,10 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();  // chunk c is in LDS; everyone is done with chunk c-1
     if (c + 1 < nchunks) {
-      stage(c + 1);
+      stage(c + 1, next);
       stage_ncg(c + 1);
     }
     const int nt = min(CT, ntiles - c * CT);
-    const u16x8* buf = sB[c & 1];
     const float* ncs = sN[c & 1];
     const int cg = ONEG ? c : c % GC;  // position of the chunk in its tag group
     const uint32_t t0 = cg * CT;       // tag of the chunk's first tile
@@ -615,16 +619,22 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
         s1[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], v1, FLT_MAX);
       }
     }
+  };
+  for (int c = 0; c < nchunks; c += 2) {
+    chunk(c, sB0, sB1);
+    if (c + 1 < nchunks) chunk(c + 1, sB1, sB0);
   }
 
   // Once every wave is past its last chunk the staging buffers are idle and
-  // each wave works in its own quarter of them.
+  // each wave works in its own quarter of them (waves 0 and 1 in sB0, 2 and
+  // 3 in sB1).
   __syncthreads();
   const int p = wbase + lane;
   const bool valid = lane < WP && p < a.n;  // lanes past the wave's points idle
   const float nx = valid ? a.norms[p] : 0.0f;
   const float D = (a.first || !valid) ? INFINITY : a.D2[p];
-  char* xw = reinterpret_cast<char*>(&sB[0][0]) + wave * WSTAGE;
+  static_assert(2 * WSTAGE == STAGE, "two wave quarters per staging buffer");
+  char* xw = reinterpret_cast<char*>(wave < 2 ? sB0 : sB1) + (wave & 1) * WSTAGE;
 
   // Merge of the 16 columns of every point through LDS: lane l writes the
   // (largest, second largest, id) of each (row tile, row) at [point][l % 16]
@@ -678,12 +688,10 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   const int nvalid = max(0, min(WP, a.n - wbase));
   const int rowb = d * (int)sizeof(T);  // <= 1 KB, so R >= 16
   const int R = min(WP, (WSTAGE / rowb) & ~15);  // rows per staging group
-  const bool staged = nvalid == WP;
-  if (staged) stage_rows<T>(xw, X, wbase, R, rowb, lane);
 
   // One lane per point: decide, refine, fold or list.  The refinement
-  // reads the point's row from the staged copy and the candidate row as
-  // float4.
+  // reads the point's row (from a staged copy, or from X) and the candidate
+  // row as float4.
   float sp = 1.0f;  // the point's row scale (FP8)
   if constexpr (SC) sp = valid ? a.row_scale[p] : 0.0f;
   const bool in_range = tag_ok && nx >= kNormMin && nx <= kNormMax &&
@@ -694,6 +702,10 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   const bool jok = j1 >= 0 && j1 < m;  // a candidate of the pass, not a padding column
   const bool refine = valid && in_range && jok && lbmin < D;
   const float* crow = a.C + (int64_t)(id0 + (jok ? j1 : 0)) * a.DP;  // read only when refining
+  // A full wave copies its rows into LDS (one coalesced copy) unless none of
+  // its lanes refines.
+  const bool staged = nvalid == WP && __ballot(refine) != 0;
+  if (staged) stage_rows<T>(xw, X, wbase, R, rowb, lane);
   float r1 = 0.0f;
   if (staged) {
     for (int c0 = 0; c0 < WP; c0 += R) {
@@ -746,8 +758,10 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   }
 }
 
+// The grouped screen runs two waves per SIMD up to six k-steps (one beyond).
 template <int SPLIT, int KS, typename T, bool DIRECT>
-__global__ __launch_bounds__(kWaves * 64) void k_screen(ScreenArgs a) {
+__global__ __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(KS <= 6 ? 2 : 1)))
+void k_screen(ScreenArgs a) {
   screen_body<SPLIT, KS, T, DIRECT, false>(a, blockIdx.x);
 }
 // The single-group screen; k_screen_one3, held to the registers of three
