@@ -211,6 +211,9 @@ KppLayout kpp_layout(void* ws, int64_t n, int d, int k) {
   L.w.pphi = c.take<double>(nb);
   L.w.crow = c.take<float>(d);
   L.w.stop = c.take<int>(4);
+  L.w.qkey = c.take<unsigned long long>(kKppQ);
+  L.w.qidx = c.take<int>(kKppQ);
+  L.w.qphi = c.take<double>(kKppQ);
   L.picks = c.take<int>(k);
   L.st = c.take<kmpar_stats>(1);
   L.bytes = c.off;
@@ -383,7 +386,7 @@ hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const
   const bool fp8 = dt == KMPAR_FP8_E4M3;
   hipError_t e = launch_prep_b(dt, split, KS, fa.C, DP, fa.d, fa.rs, fa.m_host, max_tiles, om2g, B,
                                ncg, fa.X, fa.row_scale, fp8 ? cand : nullptr,
-                               fp8 ? scg : nullptr, s);
+                               fp8 ? scg : nullptr, list_len, st, s);
   if (e != hipSuccess) return e;
   ScreenArgs sa{};
   sa.X = fa.X;

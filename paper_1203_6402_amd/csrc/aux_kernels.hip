@@ -183,8 +183,10 @@ __global__ __launch_bounds__(256) void k_draw_count(const float* D2, int n, cons
   if (threadIdx.x == 0 && ftot) atomicAdd(&st->flagged_draws, ftot);
 }
 
-// In-place exclusive scan of a[0..L) by one block; *total = sum.
-__global__ __launch_bounds__(1024) void k_scan1(int* a, int L, int* total) {
+// In-place exclusive scan of a[0..L) by one block; *total = sum.  With rs,
+// it also commits round t: m_t = min(total, cap), rs[t+1] = rs[t] + m_t.
+__global__ __launch_bounds__(1024) void k_scan1(int* a, int L, int* total, int* rs, int t, int cap,
+                                                kmpar_stats* st) {
   __shared__ long long sh[17];
   const int R = (L + 1023) / 1024;
   const int lo = min(L, (int)threadIdx.x * R), hi = min(L, lo + R);
@@ -198,16 +200,12 @@ __global__ __launch_bounds__(1024) void k_scan1(int* a, int L, int* total) {
     run += v;
   }
   if (threadIdx.x == 0 && total) *total = (int)tot;
-}
-
-// Commits round t: m_t = min(total, cap), rs[t+1] = rs[t] + m_t.
-__global__ void k_round_commit(const int* total, int* rs, int t, int cap, kmpar_stats* st) {
-  if (threadIdx.x != 0) return;
-  const int tot = *total;
-  const int m = tot < cap ? tot : cap;
-  rs[t + 1] = rs[t] + m;
-  st->round_count[t] = m;
-  if (tot > cap) st->status = KMPAR_E_OVERFLOW;
+  if (threadIdx.x == 0 && rs) {
+    const int m = tot < cap ? (int)tot : cap;
+    rs[t + 1] = rs[t] + m;
+    st->round_count[t] = m;
+    if (tot > cap) st->status = KMPAR_E_OVERFLOW;
+  }
 }
 
 // Writes the kept point indices in increasing point order, ranked from the
@@ -252,8 +250,7 @@ hipError_t launch_round_compact(int n, int* cnt, const uint64_t* keep, int* scan
                                 int t, int cap_round, int* cand_point, kmpar_stats* st,
                                 hipStream_t s) {
   const int nb = (n + kDrawChunk - 1) / kDrawChunk;
-  hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, cnt, nb, scan_total);
-  hipLaunchKernelGGL(k_round_commit, dim3(1), dim3(64), 0, s, scan_total, rs, t, cap_round, st);
+  hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, cnt, nb, scan_total, rs, t, cap_round, st);
   hipLaunchKernelGGL(k_draw_write, dim3(nb), dim3(256), 0, s, keep, cnt, rs, t, cap_round,
                      cand_point);
   KMPAR_RET_LAST();
@@ -1055,7 +1052,8 @@ hipError_t launch_lloyd_update(kmpar_dtype dt, const void* X, const float* row_s
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sort_count, dim3(nbs), dim3(256), lds, s, A, n, k, w.bcnt, nbs);
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, w.bcnt, L, w.scan_tmp);
-  hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, w.scan_tmp, ntiles, (int*)nullptr);
+  hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, w.scan_tmp, ntiles, (int*)nullptr,
+                     (int*)nullptr, 0, 0, (kmpar_stats*)nullptr);
   hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(256), 0, s, w.bcnt, L, w.scan_tmp);
   const int nbits = 32 - __builtin_clz((unsigned)k);  // bits of the largest key, k
   hipLaunchKernelGGL(k_sort_scatter, dim3(nbs), dim3(64), lds, s, A, n, k, nbits, w.bcnt, nbs,

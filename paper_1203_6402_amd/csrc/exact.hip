@@ -35,12 +35,19 @@ __host__ __device__ constexpr int radix_width(int L) { return L < 5 ? 11 : 8; }
 
 // The race clock of point i in draw t.  0 - ln(V) is +0 when V = 1, so a
 // key is never -0 (whose bits would sort above every positive key).
+// -ln V of point i's race draw in round (step) t; the key is -ln V / D^2.
+__device__ __forceinline__ double race_neglog(uint64_t seed, uint64_t i, uint64_t t, uint64_t inst) {
+  const uint64_t w = philox_word0(seed, kTagExact, i, t, inst);
+  const double v = (double)((w >> 11) + 1) * 0x1.0p-53;
+  return 0.0 - log(v);
+}
+__device__ __forceinline__ double race_key_of(float d2, double neglog) {
+  return d2 > 0.0f ? neglog / (double)d2 : INFINITY;
+}
 __device__ __forceinline__ double race_key(float d2, uint64_t seed, uint64_t i, uint64_t t,
                                            uint64_t inst) {
   if (!(d2 > 0.0f)) return INFINITY;
-  const uint64_t w = philox_word0(seed, kTagExact, i, t, inst);
-  const double v = (double)((w >> 11) + 1) * 0x1.0p-53;
-  return (0.0 - log(v)) / (double)d2;
+  return race_key_of(d2, race_neglog(seed, i, t, inst));
 }
 
 __device__ __forceinline__ unsigned long long key_bits(double k) {
@@ -279,6 +286,8 @@ __global__ __launch_bounds__(64) void k_kpp_step(const T* X, const float* row_sc
     for (int e = 0; e < d; ++e) reinterpret_cast<T*>(rows)[lane * d + e] = X[i * d + e];
   }
   const float sc = live ? row_scale_of<T>(row_scale, i) : 1.0f;
+  // the draw does not depend on the rows: computed while they are in flight
+  const double nl = (live && t > 0) ? race_neglog(seed, (uint64_t)i, (uint64_t)t, inst) : 0.0;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -301,7 +310,7 @@ __global__ __launch_bounds__(64) void k_kpp_step(const T* X, const float* row_sc
     D2[i] = dd;
     ph = (double)dd;
     if (t > 0) {
-      kb = key_bits(race_key(dd, seed, (uint64_t)i, (uint64_t)t, inst));
+      kb = key_bits(race_key_of(dd, nl));
       ki = (int)i;
     }
   }
@@ -322,9 +331,10 @@ __global__ __launch_bounds__(64) void k_kpp_step(const T* X, const float* row_sc
   }
 }
 
-// One block: the cost of the first s centers (FP64, block partials summed in
-// a fixed order) into phi_steps[s - 1] (and psi when s = 1); for s < k the
-// smallest (key, index) over the blocks is center s, whose row goes to crow
+// One block: the cost of the first s centers (FP64, the partials of
+// k_kpp_reduce summed in a fixed order) into phi_steps[s - 1] (and psi when
+// s = 1); for s < k the smallest (key, index) over them is center s, whose
+// row goes to crow
 // and centers[s].  An infinite smallest key (every point on a center) ends
 // the run with KMPAR_E_TOOFEW.
 template <typename T>
@@ -414,6 +424,59 @@ __global__ __launch_bounds__(1024) void k_kpp_pick(const unsigned long long* pke
   }
 }
 
+// First level of the pick: block q reduces the step's block partials
+// [q per, (q + 1) per) to one (smallest key, its point, FP64 D^2 sum), in a
+// fixed order; the pick then reduces these kKppQ partials.
+__global__ __launch_bounds__(256) void k_kpp_reduce(const unsigned long long* pkey, const int* pidx,
+                                                    const double* pphi, int nb, const int* stop,
+                                                    unsigned long long* qkey, int* qidx,
+                                                    double* qphi) {
+  __shared__ double sh[256 / kWave + 1];
+  __shared__ unsigned long long skb[256 / kWave];
+  __shared__ int ski[256 / kWave];
+  if (*stop) return;
+  const int per = (nb + gridDim.x - 1) / gridDim.x;
+  const int b0 = min(nb, (int)blockIdx.x * per), b1 = min(nb, b0 + per);
+  unsigned long long kb = ~0ull;
+  int ki = INT_MAX;
+  double ph = 0.0;
+  for (int b = b0 + threadIdx.x; b < b1; b += 256) {
+    ph += pphi[b];
+    const unsigned long long k = pkey[b];
+    const int i = pidx[b];
+    if (k < kb || (k == kb && i < ki)) {
+      kb = k;
+      ki = i;
+    }
+  }
+  const double tot = block_sum<double, 256>(ph, sh);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long ob = __shfl_xor(kb, off, kWave);
+    const int oi = __shfl_xor(ki, off, kWave);
+    if (ob < kb || (ob == kb && oi < ki)) {
+      kb = ob;
+      ki = oi;
+    }
+  }
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  if (lane == 0) {
+    skb[wv] = kb;
+    ski[wv] = ki;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 256 / kWave; ++q)
+      if (skb[q] < kb || (skb[q] == kb && ski[q] < ki)) {
+        kb = skb[q];
+        ki = ski[q];
+      }
+    qkey[blockIdx.x] = kb;
+    qidx[blockIdx.x] = ki;
+    qphi[blockIdx.x] = tot;
+  }
+}
+
 template <typename T>
 static hipError_t run_kmeanspp(const void* Xv, const float* rsc, int n, int d, int k,
                                uint64_t seed, uint64_t inst, const KppWs& w, int* picks,
@@ -430,7 +493,9 @@ static hipError_t run_kmeanspp(const void* Xv, const float* rsc, int n, int d, i
     hipLaunchKernelGGL(k_kpp_step<T>, dim3(nb), dim3(64), lds, s, X, rsc, n, d, w.crow,
                        step == 1 ? 1 : 0, seed, step < k ? step : 0, inst, w.stop, w.D2, w.pkey,
                        w.pidx, w.pphi);
-    hipLaunchKernelGGL(k_kpp_pick<T>, dim3(1), dim3(1024), 0, s, w.pkey, w.pidx, w.pphi, nb, X,
+    hipLaunchKernelGGL(k_kpp_reduce, dim3(kKppQ), dim3(256), 0, s, w.pkey, w.pidx, w.pphi, nb,
+                       w.stop, w.qkey, w.qidx, w.qphi);
+    hipLaunchKernelGGL(k_kpp_pick<T>, dim3(1), dim3(1024), 0, s, w.qkey, w.qidx, w.qphi, kKppQ, X,
                        rsc, d, step, k, w.stop, picks, centers, w.crow, phi_steps, st);
   }
   return hipGetLastError();

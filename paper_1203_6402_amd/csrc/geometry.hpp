@@ -68,6 +68,10 @@ KMPAR_HD inline int seg_width(int d) {
 constexpr int kStreamMaxM = 4;
 constexpr int kStagedMaxM = 64;
 
+// Blocks of the first level of the k-means++ pick (each reduces a run of
+// the step's one-wave block partials).
+constexpr int kKppQ = 256;
+
 // Rescan of listed points: points per block step, grid limit (and slice-
 // winner slots / kRescanPts), candidate rows per LDS chunk, most slices.
 constexpr int kRescanPts = 32;

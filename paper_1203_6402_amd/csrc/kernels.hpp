@@ -85,11 +85,12 @@ bool screen_supported(kmpar_dtype dt, bool centers_are_rows, int d);
 float screen_g(kmpar_dtype dt, int split, int d, int tag_bits);
 // B operands of the candidates C[rs[0] ..) (or C[0 .. m_host)), their biases
 // and, for FP8 rows, their scales: FP8 rows (split 1, against rows of X)
-// take the candidates' e4m3 codes from X rows cand[id].
+// take the candidates' e4m3 codes from X rows cand[id].  It also adds the
+// previous pass's *list_len to st->n_rescanned (st nullable) and clears it.
 hipError_t launch_prep_b(kmpar_dtype dt, int split, int KS, const float* C, int DP, int d,
                          const int* rs, int m_host, int max_tiles, float om2g, void* B, float* ncg,
                          const void* X, const float* rsc, const int* cand, float* scg,
-                         hipStream_t s);
+                         int* list_len, kmpar_stats* st, hipStream_t s);
 hipError_t launch_screen(kmpar_dtype dt, int split, int KS, const ScreenArgs& a, hipStream_t s);
 bool screen_a_direct(kmpar_dtype dt, int split, int d);
 // The screen's A operands and, when norms != nullptr, ||x||^2, from one read of X.
@@ -219,6 +220,9 @@ struct KppWs {
   double* pphi;             // [ceil(n / 64)] per-block FP64 sum of D^2
   float* crow;              // [d] the latest center
   int* stop;                // 1 once every point lies on a center
+  unsigned long long* qkey; // [kKppQ] the same over runs of block partials
+  int* qidx;                // [kKppQ]
+  double* qphi;             // [kKppQ]
 };
 // k-means++ on all of X (Algorithm 1) with race-key draws: k - 1 steps of
 // one fold + key pass over X and one pick.

@@ -109,11 +109,18 @@ __device__ __forceinline__ uint16_t b_elem(float c, int part) {
 // CODES: the operands are the e4m3 codes of X row cand[id0 + j] (SPLIT 1),
 // and scg receives each candidate's row scale, 0 past m or when the scale
 // is outside the screen's range (then the bias is trivial as well).
+// Block 0 also hands the previous pass's listed count to the stats and
+// clears it for the screen that follows.
 template <int SPLIT, int KS, bool CODES>
 __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, const int* rs,
                                                int m_host, float oneminus2g, u16x8* B,
                                                float* ncg, const fp8_t* Xc, const float* rsc,
-                                               const int* cand, float* scg) {
+                                               const int* cand, float* scg, int* list_len,
+                                               kmpar_stats* st) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && list_len) {
+    if (st) st->n_rescanned += *list_len;
+    *list_len = 0;
+  }
   int id0 = 0, m = m_host;
   if (rs) {
     id0 = rs[0];
@@ -953,7 +960,8 @@ hipError_t launch_rownorm(kmpar_dtype dt, const void* X, const float* row_scale,
 template <int SPLIT, bool CODES = false, int MAXKS = kScreenMaxKS>
 static hipError_t launch_prep_split(int KS, const float* C, int DP, int d, const int* rs, int m_host,
                                     int max_tiles, float om2g, void* B, float* ncg, const void* X,
-                                    const float* rsc, const int* cand, float* scg, hipStream_t s) {
+                                    const float* rsc, const int* cand, float* scg, int* list_len,
+                                    kmpar_stats* st, hipStream_t s) {
   if (KS < 1 || KS > MAXKS) return hipErrorInvalidValue;
   u16x8* b = static_cast<u16x8*>(B);
   const fp8_t* xc = static_cast<const fp8_t*>(X);
@@ -962,7 +970,7 @@ static hipError_t launch_prep_split(int KS, const float* C, int DP, int d, const
   case V:                                                                                      \
     if constexpr (V <= MAXKS)                                                                  \
       hipLaunchKernelGGL((k_prep_b<SPLIT, V, CODES>), dim3(max_tiles), dim3(64), 0, s, C, DP, d, \
-                         rs, m_host, om2g, b, ncg, xc, rsc, cand, scg);                        \
+                         rs, m_host, om2g, b, ncg, xc, rsc, cand, scg, list_len, st);          \
     break;
     KMPAR_PREP(1) KMPAR_PREP(2) KMPAR_PREP(3) KMPAR_PREP(4) KMPAR_PREP(5) KMPAR_PREP(6)
     KMPAR_PREP(7) KMPAR_PREP(8) KMPAR_PREP(9) KMPAR_PREP(10) KMPAR_PREP(11) KMPAR_PREP(12)
@@ -1014,26 +1022,25 @@ float screen_g(kmpar_dtype dt, int split, int d, int tag_bits) {
 hipError_t launch_prep_b(kmpar_dtype dt, int split, int KS, const float* C, int DP, int d,
                          const int* rs, int m_host, int max_tiles, float om2g, void* B, float* ncg,
                          const void* X, const float* rsc, const int* cand, float* scg,
-                         hipStream_t s) {
+                         int* list_len, kmpar_stats* st, hipStream_t s) {
   if (max_tiles <= 0) return hipSuccess;
   const bool fp8 = dt == KMPAR_FP8_E4M3;
   if (fp8 && split == 1) {
     if (!cand || !scg) return hipErrorInvalidValue;
     return launch_prep_split<1, true, 8>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, X, rsc,
-                                         cand, scg, s);
+                                         cand, scg, list_len, st, s);
   }
   if (fp8) return hipErrorInvalidValue;
   switch (split) {
-    case 1: return launch_prep_split<1>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, s);
-    case 2: return launch_prep_split<2>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, s);
-    case 3: return launch_prep_split<3>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, s);
+    case 1: return launch_prep_split<1>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, list_len, st, s);
+    case 2: return launch_prep_split<2>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, list_len, st, s);
+    case 3: return launch_prep_split<3>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, list_len, st, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_screen(kmpar_dtype dt, int split, int KS, const ScreenArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_list_reset, dim3(1), dim3(64), 0, s, a.list_len, a.stats);
   if (dt == KMPAR_F32 && split == 3) return launch_split<3, float>(KS, a, s);
   if (dt == KMPAR_BF16 && split == 1) return launch_split<1, bf16_t>(KS, a, s);
   if (dt == KMPAR_BF16 && split == 2) return launch_split<2, bf16_t>(KS, a, s);

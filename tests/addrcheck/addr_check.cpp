@@ -7,7 +7,8 @@
 //     the MFMA operand and bias reads, the per-wave merge, the staging of
 //     the wave's rows, the refinement reads, D2 / A / S and the list;
 //   * the operand preparation (k_prep_a, k_first_prep, k_prep_b);
-//   * the few-center folds (k_fold_stream, k_fold_few) and the k-means++ step;
+//   * the few-center folds (k_fold_stream, k_fold_few) and the k-means++ step
+//     and its first-level pick reduction;
 //   * the listed-point rescan (k_rescan, k_rescan_merge);
 //   * the Lloyd update (k_sort_count, k_sort_scatter, k_chunk_list,
 //     k_seg_sum, k_centroid), run on a concrete assignment;
@@ -424,6 +425,15 @@ void check_kpp_step(Checker& ck, Dtype t, int n, int d, int sample) {
       }
     }
     ck.in("block partials", blk * 8, 8, nblocks * 8, blk, 0);
+  }
+  // k_kpp_reduce: block q reads a run of the block partials, writes slot q
+  const int64_t per = (nblocks + kKppQ - 1) / kKppQ;
+  for (int q = 0; q < kKppQ; ++q) {
+    const int64_t b0 = std::min(nblocks, q * per), b1 = std::min(nblocks, b0 + per);
+    for (int tid = 0; tid < 256; ++tid)
+      for (int64_t b = b0 + tid; b < b1; b += 256)
+        ck.in("partials (reduce)", b * 8, 8, nblocks * 8, q, tid);
+    ck.in("first-level slot", (int64_t)q * 8, 8, (int64_t)kKppQ * 8, q, 0);
   }
 }
 
