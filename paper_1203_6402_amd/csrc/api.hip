@@ -107,6 +107,8 @@ struct InitLayout {
   void* B;
   float* ncg;
   float* scg;
+  int* cperm;     // the round's candidates in norm order (tile positions)
+  float2* tnr;    // each tile's norm interval
   void* Apre;
   ExactWs ex;     // exact-ell rounds only
   size_t bytes;
@@ -155,6 +157,8 @@ InitLayout init_layout(void* ws, int64_t n, int d, int k, double ell, int rounds
   L.B = c.take<char>(screen_b_bytes(tiles, d));
   L.ncg = c.take<float>((size_t)tiles * 16);
   L.scg = c.take<float>((size_t)tiles * 16);
+  L.cperm = c.take<int>((size_t)tiles * 16);
+  L.tnr = c.take<float2>((size_t)tiles);
   L.Apre = c.take<char>(a_bytes(dt, true, n, d));
   L.ex = ExactWs{};
   if (exact) {
@@ -376,7 +380,7 @@ hipError_t timed_fold(kmpar_ctx* ctx, int slot, kmpar_dtype dt, int DP, const Fo
 hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const FoldArgs& fa,
                         int max_tiles, const float* norms, const void* Apre, void* B, float* ncg,
                         const int* cand, float* scg, int* list, int* list_len, int4* rpart,
-                        kmpar_stats* st, hipStream_t s) {
+                        int* cperm, float2* tnr, kmpar_stats* st, hipStream_t s) {
   const int KS = screen_ksteps(split, fa.d);
   // A pass of at most kScreenOneGroupMaxTiles tiles tags each tile by its
   // index in the pass (single-group screen); the bound covers the tag.
@@ -384,9 +388,20 @@ hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const
   const float om2g =
       1.0f - 2.0f * screen_g(dt, split, fa.d, tag_bits > 0 ? tag_bits : screen_tag_bits(KS));
   const bool fp8 = dt == KMPAR_FP8_E4M3;
+  // The candidates in norm order and each tile's norm interval, for the
+  // tile skip of the three-wave single-group screen in passes that keep D
+  // (init rounds); other passes keep id order.
+  if (!(cperm && tag_bits > 0 && screen_three_waves(KS, true, fp8) && !fa.first)) {
+    cperm = nullptr;
+    tnr = nullptr;
+  }
+  if (cperm) {
+    hipError_t e0 = launch_cand_sort(fa.C, DP, fa.d, fa.rs, fa.m_host, cperm, tnr, s);
+    if (e0 != hipSuccess) return e0;
+  }
   hipError_t e = launch_prep_b(dt, split, KS, fa.C, DP, fa.d, fa.rs, fa.m_host, max_tiles, om2g, B,
                                ncg, fa.X, fa.row_scale, fp8 ? cand : nullptr,
-                               fp8 ? scg : nullptr, list_len, st, s);
+                               fp8 ? scg : nullptr, list_len, st, cperm, s);
   if (e != hipSuccess) return e;
   ScreenArgs sa{};
   sa.X = fa.X;
@@ -412,6 +427,8 @@ hipError_t refined_pass(kmpar_ctx* ctx, kmpar_dtype dt, int split, int DP, const
   sa.list_len = list_len;
   sa.stats = st;
   sa.tag_bits = tag_bits;
+  sa.cperm = cperm;
+  sa.tnr = tnr;
   e = timed(ctx, kSlotScreen, fa.n, nullptr, fa.rs, fa.m_host, s,
             [&] { return launch_screen(dt, split, KS, sa, s); });
   if (e != hipSuccess) return e;
@@ -741,7 +758,8 @@ int kmpar_init(kmpar_ctx* ctx, const void* X, const float* row_scale, kmpar_dtyp
     fa.rs = L.rs + t;
     if (refined) {
       KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (cap_round + 15) / 16, L.norms, Apre, L.B,
-                             L.ncg, L.cand_point, L.scg, L.list, L.list_len, L.rescan_part, st, s));
+                             L.ncg, L.cand_point, L.scg, L.list, L.list_len, L.rescan_part, L.cperm,
+                             L.tnr, st, s));
     } else {
       KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
     }
@@ -824,7 +842,8 @@ static int assign_pass(kmpar_ctx* ctx, kmpar_dtype dtype, const AssignLayout& L,
       KMPAR_HIP(launch_rownorm(dtype, fa.X, fa.row_scale, fa.n, d, L.norms, s));
     }
     KMPAR_HIP(refined_pass(ctx, dtype, split, DP, fa, (m + 15) / 16, L.norms, Apre, L.B, L.ncg,
-                           nullptr, L.scg, L.list, L.list_len, L.rescan_part, nullptr, s));
+                           nullptr, L.scg, L.list, L.list_len, L.rescan_part, nullptr, nullptr,
+                           nullptr, s));
   } else {
     KMPAR_HIP(timed_fold(ctx, kSlotDirect, dtype, DP, fa, s));
   }

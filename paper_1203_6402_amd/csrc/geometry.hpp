@@ -68,6 +68,10 @@ KMPAR_HD inline int seg_width(int d) {
 constexpr int kStreamMaxM = 4;
 constexpr int kStagedMaxM = 64;
 
+// Candidates of a pass that the norm sort of the screen's tiles handles
+// (one block, keys in LDS); larger passes keep id order.
+constexpr int kCandSortMax = 8192;
+
 // Blocks of the first level of the k-means++ pick (each reduces a run of
 // the step's one-wave block partials).
 constexpr int kKppQ = 256;

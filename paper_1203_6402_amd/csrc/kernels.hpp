@@ -77,6 +77,8 @@ struct ScreenArgs {
   int* list_len;
   kmpar_stats* stats;    // nullable: receives the listed counts
   int tag_bits;          // > 0: single-group screen, tiles tagged by their index in the pass
+  const int* cperm;      // nullable: candidate (offset from id0) at each tile position
+  const float2* tnr;     // nullable: ||c|| interval of each tile (with cperm)
 };
 
 int screen_split(kmpar_dtype dt, bool centers_are_rows);
@@ -90,7 +92,11 @@ float screen_g(kmpar_dtype dt, int split, int d, int tag_bits);
 hipError_t launch_prep_b(kmpar_dtype dt, int split, int KS, const float* C, int DP, int d,
                          const int* rs, int m_host, int max_tiles, float om2g, void* B, float* ncg,
                          const void* X, const float* rsc, const int* cand, float* scg,
-                         int* list_len, kmpar_stats* st, hipStream_t s);
+                         int* list_len, kmpar_stats* st, const int* cperm, hipStream_t s);
+// The pass's candidates in norm order (cperm) and the norm interval of each
+// tile of 16 (tnr), for the screen.
+hipError_t launch_cand_sort(const float* C, int DP, int d, const int* rs, int m_host, int* cperm,
+                            float2* tnr, hipStream_t s);
 hipError_t launch_screen(kmpar_dtype dt, int split, int KS, const ScreenArgs& a, hipStream_t s);
 bool screen_a_direct(kmpar_dtype dt, int split, int d);
 // The screen's A operands and, when norms != nullptr, ||x||^2, from one read of X.

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
                                                int m_host, float oneminus2g, u16x8* B,
                                                float* ncg, const fp8_t* Xc, const float* rsc,
                                                const int* cand, float* scg, int* list_len,
-                                               kmpar_stats* st) {
+                                               kmpar_stats* st, const int* cperm) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && list_len) {
     if (st) st->n_rescanned += *list_len;
     *list_len = 0;
@@ -129,11 +129,12 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
   const int q = blockIdx.x;
   if (q * 16 >= m) return;
   const int lane = threadIdx.x;
-  const int j = q * 16 + (lane % 16);
+  const int j = q * 16 + (lane % 16);  // position in the pass's tiles
   const bool valid = j < m;
-  const float* c = C + (int64_t)(id0 + (valid ? j : 0)) * DP;
+  const int src = valid ? (cperm ? cperm[j] : j) : 0;  // the candidate at position j
+  const float* c = C + (int64_t)(id0 + src) * DP;
   int64_t xrow = 0;
-  if constexpr (CODES) xrow = valid ? (int64_t)cand[id0 + j] * d : 0;
+  if constexpr (CODES) xrow = valid ? (int64_t)cand[id0 + src] * d : 0;
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     u16x8 v;
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(64) void k_prep_b(const float* C, int DP, int d, co
     if (valid)
       for (int e = 0; e < d; ++e) nc = fmaf(c[e], c[e], nc);
     float sc = 1.0f;
-    if constexpr (CODES) sc = valid ? rsc[cand[id0 + j]] : 0.0f;
+    if constexpr (CODES) sc = valid ? rsc[cand[id0 + src]] : 0.0f;
     const bool sc_ok = sc >= kScaleMin && sc <= kScaleMax;
     // Past m: +inf (never the maximum).  Beyond 2^100 (or not finite), or a
     // scale out of range: a bias that makes the candidate's lower bound -inf.
@@ -321,11 +322,12 @@ template <int KRT, bool SC>
 __device__ __forceinline__ void epilogue(const f32x4 (&acc)[KRT], uint32_t keep, uint32_t tq,
                                          float (&s1)[KRT][4], float (&s2)[KRT][4],
                                          const float (&srow)[KRT][4], const float* ncs, int q,
-                                         int lane) {
+                                         int lane, unsigned skip = 0) {
   float2 col = make_float2(0.0f, 0.0f);
   if constexpr (SC) col = reinterpret_cast<const float2*>(ncs)[q * 16 + (lane % 16)];
 #pragma unroll
-  for (int r = 0; r < KRT; ++r)
+  for (int r = 0; r < KRT; ++r) {
+    if ((skip >> r) & 1u) continue;  // row tile r cannot gain from this tile (wave-uniform)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       float a = acc[r][i];
@@ -334,6 +336,7 @@ __device__ __forceinline__ void epilogue(const f32x4 (&acc)[KRT], uint32_t keep,
       s2[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], s2[r][i], v);
       s1[r][i] = __builtin_amdgcn_fmed3f(s1[r][i], v, FLT_MAX);
     }
+  }
 }
 
 // Starts the copy of rows [row0, row0 + nr) of X (raw elements, rowb bytes
@@ -388,7 +391,7 @@ __device__ __forceinline__ float refine_dist(const T* x, const float* c, int d, 
 // ONEG: the pass has at most kScreenOneGroupMaxTiles tiles and each value
 // carries its tile's index in the pass (a.tag_bits bits), so the running
 // maxima are the pass's maxima and no per-group maxima or ids are kept.
-template <int SPLIT, int KS, typename T, bool DIRECT, bool ONEG>
+template <int SPLIT, int KS, typename T, bool DIRECT, bool ONEG, bool PRUNE = false>
 __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   constexpr int KRT = screen_krt_t<KS, T>();  // row tiles per wave
   constexpr int WP = KRT * 16;         // points per wave
@@ -455,8 +458,21 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     }
   };
 
+  // Tile skip (three-wave single-group screen of a pass that keeps D):
+  // ||x - c||^2 >= (||x|| - ||c||)^2, so a candidate tile whose norm
+  // interval lies far enough from a row tile's cannot bring any of its
+  // points below D (nor within the band of it).  Lane j < CT * KRT judges
+  // (tile j / KRT of a chunk, row tile j % KRT).
+  static_assert(!PRUNE || THREE, "the tile skip is built into the three-wave screen only");
+  const bool prune = PRUNE && a.tnr != nullptr && !a.first;
+  float2 tnr_next = make_float2(INFINITY, 0.0f);
+  auto stage_tnr = [&](int c) {
+    const int tq = c * CT + lane / KRT;
+    tnr_next = (prune && lane < CT * KRT && tq < ntiles) ? a.tnr[tq] : make_float2(INFINITY, 0.0f);
+  };
   if (nchunks > 0) stage(0, sB0);
   stage_ncg(0);
+  stage_tnr(0);
 
   // A operands of this wave's points, kept in registers for the pass: from
   // the prepared buffer, or straight from X when d % 8 == 0 and X is bf16
@@ -520,6 +536,43 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
         srow[r][i] = (sp >= kScaleMin && sp <= kScaleMax) ? sp : 0.0f;
       }
     }
+  // The norm interval [xlo, xhi] and the distance limit dlim of row tile
+  // lane % KRT (reduced over its 16 points), for the tile skip.  ||x||
+  // comes from the FP32 ||x||^2 (relative error below (d + 1) 2^-24 before
+  // the root), widened by (d + 8) 2^-24; a point without finite norm or D
+  // keeps its row tile from being skipped.
+  float pxlo = INFINITY, pxhi = 0.0f, pdl = 0.0f;
+  if (prune) {
+    const float ue = 0x1.0p-24f;
+    const int pl = wbase + lane;
+    float xl = INFINITY, xh = 0.0f, dl = 0.0f;
+    if (lane < WP && pl < a.n) {
+      const float n2 = a.norms[pl], dd = a.D2[pl];
+      if (n2 >= 0.0f && n2 <= FLT_MAX && dd >= 0.0f && dd <= FLT_MAX) {
+        const float x = sqrtf(n2);
+        xl = x * (1.0f - (d + 8) * ue);
+        xh = x * (1.0f + (d + 8) * ue);
+        dl = dd;
+      } else {
+        xl = 0.0f;
+        xh = INFINITY;
+        dl = INFINITY;
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      xl = fminf(xl, __shfl_xor(xl, off, 16));
+      xh = fmaxf(xh, __shfl_xor(xh, off, 16));
+      dl = fmaxf(dl, __shfl_xor(dl, off, 16));
+    }
+    const int src = 16 * (lane % KRT);
+    pxlo = __shfl(xl, src);
+    pxhi = __shfl(xh, src);
+    // a skipped candidate must lie beyond (1 + 2 band) D in the FP32 direct
+    // form, band = 2 (d + 2) 2^-24: D is raised and the squared gap lowered
+    // by more than that and every rounding of the test
+    pdl = __shfl(dl, src) * (1.0f + (8 * d + 32) * ue);
+  }
   float s1[KRT][4], s2[KRT][4], c1[KRT][4], c2[KRT][4];
   int ix[KRT][4];
 #pragma unroll
@@ -549,9 +602,17 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();  // chunk c is in LDS; everyone is done with chunk c-1
+    // bit q * KRT + r: row tile r skips tile q of this chunk
+    uint64_t skipm = 0;
+    if (prune) {
+      const float gap = fmaxf(tnr_next.x - pxhi, pxlo - tnr_next.y);
+      const float ue = 0x1.0p-24f;
+      skipm = __ballot(gap > 0.0f && gap * gap * (1.0f - (2 * d + 16) * ue) > pdl);
+    }
     if (c + 1 < nchunks) {
       stage(c + 1, next);
       stage_ncg(c + 1);
+      stage_tnr(c + 1);
     }
     const int nt = min(CT, ntiles - c * CT);
     const float* ncs = sN[c & 1];
@@ -571,18 +632,21 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     // (two accumulator sets, unrolled by two so no copies are needed).
     f32x4 acc0[KRT], acc1[KRT];
     // each tile's values go to the group pair (the running pair when ONEG)
-    auto fold = [&](const f32x4 (&acc)[KRT], int q) {
+    auto fold = [&](const f32x4 (&acc)[KRT], int q, unsigned sk = 0) {
       if constexpr (ONEG)
-        epilogue<KRT, SC>(acc, keep, t0 + q, s1, s2, srow, ncs, q, lane);
+        epilogue<KRT, SC>(acc, keep, t0 + q, s1, s2, srow, ncs, q, lane, sk);
       else
-        epilogue<KRT, SC>(acc, keep, t0 + q, c1, c2, srow, ncs, q, lane);
+        epilogue<KRT, SC>(acc, keep, t0 + q, c1, c2, srow, ncs, q, lane, sk);
     };
     if constexpr (!PIPE) {
       // three waves per SIMD: the other waves' vector work overlaps a
       // wave's matrix instructions, so one accumulator set suffices
+      constexpr unsigned FULL = (1u << KRT) - 1u;
       for (int q = 0; q < nt; ++q) {
+        const unsigned sk = (unsigned)(skipm >> (q * KRT)) & FULL;
+        if (sk == FULL) continue;  // no row tile of the wave can gain from tile q
         mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, q, lane, acc0);
-        fold(acc0, q);
+        fold(acc0, q, sk);
       }
     } else {
     mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, 0, lane, acc0);
@@ -707,8 +771,11 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   const float lbmin = fmaf(b1, -2.0f, nxg);
   const float lb2 = fmaf(b2, -2.0f, nxg);
   const bool jok = j1 >= 0 && j1 < m;  // a candidate of the pass, not a padding column
+  // the winner's candidate: tiles hold the candidates in norm order when
+  // the pass sorted them (cperm), else in id order
+  const int jc = (jok && a.cperm) ? a.cperm[j1] : j1;
   const bool refine = valid && in_range && jok && lbmin < D;
-  const float* crow = a.C + (int64_t)(id0 + (jok ? j1 : 0)) * a.DP;  // read only when refining
+  const float* crow = a.C + (int64_t)(id0 + (jok ? jc : 0)) * a.DP;  // read only when refining
   // A full wave copies its rows into LDS (one coalesced copy) unless none of
   // its lanes refines.
   const bool staged = nvalid == WP && __ballot(refine) != 0;
@@ -750,7 +817,7 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     if (lb2 > r1) {
       if (a.S) a.S[p] = D;
       a.D2[p] = r1;
-      a.A[p] = id0 + j1;
+      a.A[p] = id0 + jc;
     } else {
       listed = true;
     }
@@ -777,10 +844,10 @@ template <int SPLIT, int KS, typename T, bool DIRECT>
 __global__ __launch_bounds__(kWaves * 64) void k_screen_one(ScreenArgs a) {
   screen_body<SPLIT, KS, T, DIRECT, true>(a, blockIdx.x);
 }
-template <int SPLIT, int KS, typename T, bool DIRECT>
+template <int SPLIT, int KS, typename T, bool DIRECT, bool PRUNE>
 __global__ __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 void k_screen_one3(ScreenArgs a) {
-  screen_body<SPLIT, KS, T, DIRECT, true>(a, blockIdx.x);
+  screen_body<SPLIT, KS, T, DIRECT, true, PRUNE>(a, blockIdx.x);
 }
 
 // Adds the previous pass's listed count to the stats and clears it.
@@ -798,10 +865,16 @@ static void launch_one(const ScreenArgs& a, hipStream_t s) {
   constexpr bool THREE = screen_three_waves(KS, true, ScaledRows<T>::value);
   if (a.tag_bits > 0) {
     if constexpr (THREE) {
-      if (a.Apre)
-        hipLaunchKernelGGL((k_screen_one3<SPLIT, KS, T, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+      // passes that keep D with sorted candidate tiles take the tile skip
+      const bool pr = a.tnr != nullptr && !a.first;
+      if (a.Apre && pr)
+        hipLaunchKernelGGL((k_screen_one3<SPLIT, KS, T, false, true>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+      else if (a.Apre)
+        hipLaunchKernelGGL((k_screen_one3<SPLIT, KS, T, false, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+      else if (pr)
+        hipLaunchKernelGGL((k_screen_one3<SPLIT, KS, T, true, true>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
       else
-        hipLaunchKernelGGL((k_screen_one3<SPLIT, KS, T, true>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
+        hipLaunchKernelGGL((k_screen_one3<SPLIT, KS, T, true, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
     } else {
       if (a.Apre)
         hipLaunchKernelGGL((k_screen_one<SPLIT, KS, T, false>), dim3(blocks), dim3(kWaves * 64), 0, s, a);
@@ -961,7 +1034,7 @@ template <int SPLIT, bool CODES = false, int MAXKS = kScreenMaxKS>
 static hipError_t launch_prep_split(int KS, const float* C, int DP, int d, const int* rs, int m_host,
                                     int max_tiles, float om2g, void* B, float* ncg, const void* X,
                                     const float* rsc, const int* cand, float* scg, int* list_len,
-                                    kmpar_stats* st, hipStream_t s) {
+                                    kmpar_stats* st, const int* cperm, hipStream_t s) {
   if (KS < 1 || KS > MAXKS) return hipErrorInvalidValue;
   u16x8* b = static_cast<u16x8*>(B);
   const fp8_t* xc = static_cast<const fp8_t*>(X);
@@ -970,7 +1043,7 @@ static hipError_t launch_prep_split(int KS, const float* C, int DP, int d, const
   case V:                                                                                      \
     if constexpr (V <= MAXKS)                                                                  \
       hipLaunchKernelGGL((k_prep_b<SPLIT, V, CODES>), dim3(max_tiles), dim3(64), 0, s, C, DP, d, \
-                         rs, m_host, om2g, b, ncg, xc, rsc, cand, scg, list_len, st);          \
+                         rs, m_host, om2g, b, ncg, xc, rsc, cand, scg, list_len, st, cperm);   \
     break;
     KMPAR_PREP(1) KMPAR_PREP(2) KMPAR_PREP(3) KMPAR_PREP(4) KMPAR_PREP(5) KMPAR_PREP(6)
     KMPAR_PREP(7) KMPAR_PREP(8) KMPAR_PREP(9) KMPAR_PREP(10) KMPAR_PREP(11) KMPAR_PREP(12)
@@ -1019,22 +1092,93 @@ float screen_g(kmpar_dtype dt, int split, int d, int tag_bits) {
   return (float)(safety * (split_err + acc_err + misc + tag_err + scale_err) / 2.0);
 }
 
+// The candidates of a pass in the order of their norms (bitonic sort of
+// (||c||^2, offset) pairs in LDS): cperm[pos] is the offset from id0 of the
+// candidate at position pos < m, and tnr[q] an interval holding ||c|| of
+// every candidate of tile q (FP64 norms of the FP32 rows, widened by 2^-20
+// on each side).  A pass of more than kCandSortMax candidates keeps id order
+// and gets intervals [0, inf) (its tiles are never skipped).
+__global__ __launch_bounds__(1024) void k_cand_sort(const float* C, int DP, int d, const int* rs,
+                                                    int m_host, int* cperm, float2* tnr) {
+  __shared__ float key[kCandSortMax];
+  __shared__ int idx[kCandSortMax];
+  int id0 = 0, m = m_host;
+  if (rs) {
+    id0 = rs[0];
+    m = rs[1] - id0;
+  }
+  const int tid = threadIdx.x;
+  const int ntiles = (m + 15) / 16;
+  if (m > kCandSortMax) {
+    for (int pos = tid; pos < ntiles * 16; pos += 1024) cperm[pos] = pos < m ? pos : -1;
+    for (int q = tid; q < ntiles; q += 1024) tnr[q] = make_float2(0.0f, INFINITY);
+    return;
+  }
+  int N = 1;
+  while (N < m) N <<= 1;
+  for (int i = tid; i < N; i += 1024) {
+    float k = INFINITY;
+    if (i < m) {
+      const float* c = C + (int64_t)(id0 + i) * DP;
+      double s2 = 0.0;
+      for (int e = 0; e < d; ++e) s2 += (double)c[e] * (double)c[e];
+      k = (float)s2;
+      if (!(k <= FLT_MAX)) k = INFINITY;  // NaN sorts last too
+    }
+    key[i] = k;
+    idx[i] = i;
+  }
+  __syncthreads();
+  for (int k = 2; k <= N; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < N; i += 1024) {
+        const int o = i ^ j;
+        if (o > i) {
+          const float ka = key[i], kb = key[o];
+          const int ia = idx[i], ib = idx[o];
+          const bool gt = ka > kb || (ka == kb && ia > ib);
+          if (((i & k) == 0) == gt) {  // ascending runs where (i & k) == 0
+            key[i] = kb;
+            key[o] = ka;
+            idx[i] = ib;
+            idx[o] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int pos = tid; pos < ntiles * 16; pos += 1024) cperm[pos] = pos < m ? idx[pos] : -1;
+  for (int q = tid; q < ntiles; q += 1024) {
+    const int hi = min(m, q * 16 + 16) - 1;
+    const double lo2 = key[q * 16], hi2 = key[hi];  // the tile's smallest and largest keys
+    // keys are rounded to FP32 (relative 2^-24); 2^-20 covers that and sqrt
+    tnr[q] = make_float2((float)(sqrt(lo2) * (1.0 - 0x1.0p-20)),
+                         hi2 <= (double)FLT_MAX ? (float)(sqrt(hi2) * (1.0 + 0x1.0p-20)) : INFINITY);
+  }
+}
+
+hipError_t launch_cand_sort(const float* C, int DP, int d, const int* rs, int m_host, int* cperm,
+                            float2* tnr, hipStream_t s) {
+  hipLaunchKernelGGL(k_cand_sort, dim3(1), dim3(1024), 0, s, C, DP, d, rs, m_host, cperm, tnr);
+  return hipGetLastError();
+}
+
 hipError_t launch_prep_b(kmpar_dtype dt, int split, int KS, const float* C, int DP, int d,
                          const int* rs, int m_host, int max_tiles, float om2g, void* B, float* ncg,
                          const void* X, const float* rsc, const int* cand, float* scg,
-                         int* list_len, kmpar_stats* st, hipStream_t s) {
+                         int* list_len, kmpar_stats* st, const int* cperm, hipStream_t s) {
   if (max_tiles <= 0) return hipSuccess;
   const bool fp8 = dt == KMPAR_FP8_E4M3;
   if (fp8 && split == 1) {
     if (!cand || !scg) return hipErrorInvalidValue;
     return launch_prep_split<1, true, 8>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, X, rsc,
-                                         cand, scg, list_len, st, s);
+                                         cand, scg, list_len, st, cperm, s);
   }
   if (fp8) return hipErrorInvalidValue;
   switch (split) {
-    case 1: return launch_prep_split<1>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, list_len, st, s);
-    case 2: return launch_prep_split<2>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, list_len, st, s);
-    case 3: return launch_prep_split<3>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, list_len, st, s);
+    case 1: return launch_prep_split<1>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, list_len, st, cperm, s);
+    case 2: return launch_prep_split<2>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, list_len, st, cperm, s);
+    case 3: return launch_prep_split<3>(KS, C, DP, d, rs, m_host, max_tiles, om2g, B, ncg, nullptr, nullptr, nullptr, nullptr, list_len, st, cperm, s);
   }
   return hipErrorInvalidValue;
 }

@@ -106,8 +106,12 @@ void check_prep_b(Checker& ck, const ScreenShape& s) {
     for (int lane = 0; lane < 64; ++lane) {
       const int j = q * 16 + lane % 16;
       const bool valid = j < s.m;
-      const int64_t crow = (int64_t)(s.id0 + (valid ? j : 0)) * DP;
-      if (s.codes && valid) ck.in("cand", (int64_t)(s.id0 + j) * 4, 4, cand_sz, q, lane);
+      // init rounds read the candidate at position j through cperm: any of
+      // the pass's candidates; the last one stands for them here
+      if (!s.first && valid) ck.in("cperm", (int64_t)j * 4, 4, (int64_t)s.tiles_cap * 16 * 4, q, lane);
+      const int src = valid ? (s.first ? j : s.m - 1) : 0;
+      const int64_t crow = (int64_t)(s.id0 + src) * DP;
+      if (s.codes && valid) ck.in("cand", (int64_t)(s.id0 + src) * 4, 4, cand_sz, q, lane);
       for (int st = 0; st < KS; ++st) {
         for (int e = 0; e < 8; ++e) {
           const int k = st * 32 + (lane / 16) * 8 + e;
@@ -268,6 +272,8 @@ void check_screen(Checker& ck, const ScreenShape& s, int sample) {
       } else if (valid) {
         ck.in("X row (refine)", p * d * Sz, (int64_t)d * Sz, Xsz, blk, tid);
       }
+      if (valid && s.m > 0 && !s.first)
+        ck.in("cperm (winner)", (int64_t)jmax_refined * 4, 4, (int64_t)s.tiles_cap * 16 * 4, blk, tid);
       if (valid && s.m > 0) {
         for (int j1 : {0, jmax_refined}) {
           const int64_t row = (int64_t)(s.id0 + j1) * DP;
@@ -480,6 +486,35 @@ void check_fold_few(Checker& ck, Dtype t, int n, int d, int m, int id0, int64_t 
   }
 }
 
+// k_cand_sort: one block of 1024 threads over the m candidates of a pass.
+void check_cand_sort(Checker& ck, int m, int d, int id0, int64_t crows, int tiles_cap) {
+  const int DP = padded_dim_hd(d);
+  const int64_t Csz = crows * DP * 4;
+  const int ntiles = (m + 15) / 16;
+  if (ntiles > tiles_cap) ck.fail("sort: pass has more tiles than cperm / tnr");
+  for (int tid = 0; tid < 1024; ++tid) {
+    if (m > kCandSortMax) {
+      for (int pos = tid; pos < ntiles * 16; pos += 1024) ck.in("cperm", (int64_t)pos * 4, 4, (int64_t)tiles_cap * 64, 0, tid);
+      for (int q = tid; q < ntiles; q += 1024) ck.in("tnr", (int64_t)q * 8, 8, (int64_t)tiles_cap * 8, 0, tid);
+      continue;
+    }
+    int N = 1;
+    while (N < m) N <<= 1;
+    if (N > kCandSortMax) ck.fail("sort: keys exceed the LDS arrays");
+    for (int i = tid; i < N; i += 1024) {
+      if (i < m) {
+        ck.in("C row (sort)", ((int64_t)(id0 + i) * DP) * 4, (int64_t)d * 4, Csz, 0, tid);
+      }
+      ck.in("LDS key", (int64_t)i * 4, 4, (int64_t)kCandSortMax * 4, 0, tid);
+    }
+    for (int pos = tid; pos < ntiles * 16; pos += 1024) ck.in("cperm", (int64_t)pos * 4, 4, (int64_t)tiles_cap * 64, 0, tid);
+    for (int q = tid; q < ntiles; q += 1024) {
+      ck.in("LDS key (tile ends)", (int64_t)(std::min(m, q * 16 + 16) - 1) * 4, 4, (int64_t)kCandSortMax * 4, 0, tid);
+      ck.in("tnr", (int64_t)q * 8, 8, (int64_t)tiles_cap * 8, 0, tid);
+    }
+  }
+}
+
 // k_rescan + k_rescan_merge for a list of nlist points.
 void check_rescan(Checker& ck, Dtype t, int n, int d, int m, int id0, int64_t crows, int nlist) {
   const int DP = padded_dim_hd(d), Sz = elem_size(t);
@@ -669,6 +704,8 @@ int main(int argc, char** argv) {
           run("screen " + tag + " m=" + std::to_string(m) + " id0=" + std::to_string(id0),
               [&] { check_screen(ck, s, 12); });
           run("prep_b " + tag + " m=" + std::to_string(m), [&] { check_prep_b(ck, s); });
+          run("cand_sort " + tag + " m=" + std::to_string(m),
+              [&] { check_cand_sort(ck, (int)m, c.d, (int)id0, capT, tiles); });
         }
       }
       if (!direct)
