@@ -173,6 +173,25 @@ def test_refined_heavy_tailed_large_norm_gap(plain, refined):
     _same_init(a, b)
 
 
+@pytest.mark.parametrize("d", [15, 42])
+def test_refined_tile_skip_on_collinear_rows(plain, refined, d):
+    # Rows on one ray from the origin: ||x - c|| equals | ||x|| - ||c|| | up
+    # to rounding, so the norm bound behind the screen's tile skip is tight
+    # for every pair and many points sit right at its margin; a tenth of the
+    # rows are repeated (distance 0 once one of them is a center).
+    rng = np.random.default_rng(d)
+    u = rng.normal(size=d)
+    u /= np.linalg.norm(u)
+    r = np.exp(rng.uniform(0.0, np.log(1e4), size=12000))
+    X = (r[:, None] * u[None, :]).astype(np.float32)
+    X[::10] = X[1::10][: X[::10].shape[0]]
+    Xd = _dev(X)
+    a = plain.init(Xd, k=80, ell=160.0, rounds=5, seed=3, trace=True)
+    b = refined.init(Xd, k=80, ell=160.0, rounds=5, seed=3, trace=True)
+    torch.cuda.synchronize()
+    _same_init(a, b)
+
+
 @pytest.mark.parametrize("d,span", [(4, 6), (20, 3)])
 def test_flagged_argmins_on_integer_lattice(plain, refined, d, span):
     # Integer coordinates make every FP32 distance exact, so a runner-up
