@@ -71,6 +71,7 @@ constexpr int kStagedMaxM = 64;
 // Candidates of a pass that the norm sort of the screen's tiles handles
 // (one block, keys in LDS); larger passes keep id order.
 constexpr int kCandSortMax = 8192;
+constexpr int kCandBuckets = 1024;  // log2 ||c||^2 buckets of that sort (one per thread)
 
 // Blocks of the first level of the k-means++ pick (each reduces a run of
 // the step's one-wave block partials).

@@ -1092,68 +1092,99 @@ float screen_g(kmpar_dtype dt, int split, int d, int tag_bits) {
   return (float)(safety * (split_err + acc_err + misc + tag_err + scale_err) / 2.0);
 }
 
-// The candidates of a pass in the order of their norms (bitonic sort of
-// (||c||^2, offset) pairs in LDS): cperm[pos] is the offset from id0 of the
-// candidate at position pos < m, and tnr[q] an interval holding ||c|| of
-// every candidate of tile q (FP64 norms of the FP32 rows, widened by 2^-20
-// on each side).  A pass of more than kCandSortMax candidates keeps id order
+// The candidates of a pass grouped by their norms: a counting sort of the
+// candidates into kCandBuckets buckets of log2 ||c||^2 spanning the pass's
+// range (every position's order matters only for which tiles can be skipped;
+// within a bucket the order is that of the LDS atomics).  cperm[pos] is the
+// offset from id0 of the candidate at position pos < m, and tnr[q] an
+// interval holding ||c|| of every candidate of tile q (the smallest and
+// largest FP64 norm of its 16 rows, rounded to FP32 and widened by 2^-20 on
+// each side).  A pass of more than kCandSortMax candidates keeps id order
 // and gets intervals [0, inf) (its tiles are never skipped).
 __global__ __launch_bounds__(1024) void k_cand_sort(const float* C, int DP, int d, const int* rs,
                                                     int m_host, int* cperm, float2* tnr) {
   __shared__ float key[kCandSortMax];
-  __shared__ int idx[kCandSortMax];
+  __shared__ float skey[kCandSortMax];
+  __shared__ int cnt[kCandBuckets];
+  __shared__ int sh[1024 / kWave + 1];
+  __shared__ float lmin_s[1024 / kWave], lmax_s[1024 / kWave];
   int id0 = 0, m = m_host;
   if (rs) {
     id0 = rs[0];
     m = rs[1] - id0;
   }
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
   const int ntiles = (m + 15) / 16;
   if (m > kCandSortMax) {
     for (int pos = tid; pos < ntiles * 16; pos += 1024) cperm[pos] = pos < m ? pos : -1;
     for (int q = tid; q < ntiles; q += 1024) tnr[q] = make_float2(0.0f, INFINITY);
     return;
   }
-  int N = 1;
-  while (N < m) N <<= 1;
-  for (int i = tid; i < N; i += 1024) {
-    float k = INFINITY;
-    if (i < m) {
-      const float* c = C + (int64_t)(id0 + i) * DP;
-      double s2 = 0.0;
-      for (int e = 0; e < d; ++e) s2 += (double)c[e] * (double)c[e];
-      k = (float)s2;
-      if (!(k <= FLT_MAX)) k = INFINITY;  // NaN sorts last too
-    }
+  for (int b = tid; b < kCandBuckets; b += 1024) cnt[b] = 0;
+  // keys, and the range of log2 of the finite positive ones
+  float lo = INFINITY, hi = -INFINITY;
+  for (int i = tid; i < m; i += 1024) {
+    const float* c = C + (int64_t)(id0 + i) * DP;
+    double s2 = 0.0;
+    for (int e = 0; e < d; ++e) s2 += (double)c[e] * (double)c[e];
+    float k = (float)s2;
+    if (!(k <= FLT_MAX)) k = INFINITY;  // NaN goes with the infinite keys
     key[i] = k;
-    idx[i] = i;
+    if (k > 0.0f && k <= FLT_MAX) {
+      const float l = log2f(k);
+      lo = fminf(lo, l);
+      hi = fmaxf(hi, l);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, off, kWave));
+    hi = fmaxf(hi, __shfl_xor(hi, off, kWave));
+  }
+  if (lane == 0) {
+    lmin_s[wv] = lo;
+    lmax_s[wv] = hi;
   }
   __syncthreads();
-  for (int k = 2; k <= N; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < N; i += 1024) {
-        const int o = i ^ j;
-        if (o > i) {
-          const float ka = key[i], kb = key[o];
-          const int ia = idx[i], ib = idx[o];
-          const bool gt = ka > kb || (ka == kb && ia > ib);
-          if (((i & k) == 0) == gt) {  // ascending runs where (i & k) == 0
-            key[i] = kb;
-            key[o] = ka;
-            idx[i] = ib;
-            idx[o] = ia;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  for (int pos = tid; pos < ntiles * 16; pos += 1024) cperm[pos] = pos < m ? idx[pos] : -1;
+  lo = INFINITY;
+  hi = -INFINITY;
+#pragma unroll
+  for (int q = 0; q < 1024 / kWave; ++q) {
+    lo = fminf(lo, lmin_s[q]);
+    hi = fmaxf(hi, lmax_s[q]);
+  }
+  // bucket 0: zero rows; the last: non-finite; the others split [lo, hi]
+  const float scale = hi > lo ? (float)(kCandBuckets - 3) / (hi - lo) : 0.0f;
+  auto bucket = [&](float k) {
+    if (!(k > 0.0f)) return 0;
+    if (!(k <= FLT_MAX)) return kCandBuckets - 1;
+    const int b = 1 + (int)((log2f(k) - lo) * scale);
+    return b < 1 ? 1 : (b > kCandBuckets - 2 ? kCandBuckets - 2 : b);
+  };
+  for (int i = tid; i < m; i += 1024) atomicAdd(&cnt[bucket(key[i])], 1);
+  __syncthreads();
+  // bucket offsets (kCandBuckets == 1024: one bucket per thread)
+  int tot;
+  const int off = block_excl_scan<int, 1024>(cnt[tid], sh, &tot);
+  cnt[tid] = off;  // the scan's barriers order this after every read of cnt
+  __syncthreads();
+  for (int i = tid; i < m; i += 1024) {
+    const float k = key[i];
+    const int pos = atomicAdd(&cnt[bucket(k)], 1);
+    cperm[pos] = i;
+    skey[pos] = k;
+  }
+  for (int pos = m + tid; pos < ntiles * 16; pos += 1024) cperm[pos] = -1;
+  __syncthreads();
   for (int q = tid; q < ntiles; q += 1024) {
-    const int hi = min(m, q * 16 + 16) - 1;
-    const double lo2 = key[q * 16], hi2 = key[hi];  // the tile's smallest and largest keys
+    float a2 = INFINITY, b2 = 0.0f;
+    for (int pos = q * 16; pos < min(m, q * 16 + 16); ++pos) {
+      a2 = fminf(a2, skey[pos]);
+      b2 = fmaxf(b2, skey[pos]);
+    }
     // keys are rounded to FP32 (relative 2^-24); 2^-20 covers that and sqrt
-    tnr[q] = make_float2((float)(sqrt(lo2) * (1.0 - 0x1.0p-20)),
-                         hi2 <= (double)FLT_MAX ? (float)(sqrt(hi2) * (1.0 + 0x1.0p-20)) : INFINITY);
+    tnr[q] = make_float2((float)(sqrt((double)a2) * (1.0 - 0x1.0p-20)),
+                         b2 <= FLT_MAX ? (float)(sqrt((double)b2) * (1.0 + 0x1.0p-20)) : INFINITY);
   }
 }
 

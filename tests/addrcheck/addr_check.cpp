@@ -486,30 +486,32 @@ void check_fold_few(Checker& ck, Dtype t, int n, int d, int m, int id0, int64_t 
   }
 }
 
-// k_cand_sort: one block of 1024 threads over the m candidates of a pass.
+// k_cand_sort: one block of 1024 threads over the m candidates of a pass
+// (keys, bucket counts, positions from the bucket offsets, tile intervals).
 void check_cand_sort(Checker& ck, int m, int d, int id0, int64_t crows, int tiles_cap) {
   const int DP = padded_dim_hd(d);
-  const int64_t Csz = crows * DP * 4;
+  const int64_t Csz = crows * DP * 4, cap16 = (int64_t)tiles_cap * 16;
   const int ntiles = (m + 15) / 16;
   if (ntiles > tiles_cap) ck.fail("sort: pass has more tiles than cperm / tnr");
+  if (kCandBuckets != 1024) ck.fail("sort: one bucket per thread");
   for (int tid = 0; tid < 1024; ++tid) {
     if (m > kCandSortMax) {
-      for (int pos = tid; pos < ntiles * 16; pos += 1024) ck.in("cperm", (int64_t)pos * 4, 4, (int64_t)tiles_cap * 64, 0, tid);
+      for (int pos = tid; pos < ntiles * 16; pos += 1024) ck.in("cperm", (int64_t)pos * 4, 4, cap16 * 4, 0, tid);
       for (int q = tid; q < ntiles; q += 1024) ck.in("tnr", (int64_t)q * 8, 8, (int64_t)tiles_cap * 8, 0, tid);
       continue;
     }
-    int N = 1;
-    while (N < m) N <<= 1;
-    if (N > kCandSortMax) ck.fail("sort: keys exceed the LDS arrays");
-    for (int i = tid; i < N; i += 1024) {
-      if (i < m) {
-        ck.in("C row (sort)", ((int64_t)(id0 + i) * DP) * 4, (int64_t)d * 4, Csz, 0, tid);
-      }
+    ck.in("LDS bucket", (int64_t)tid * 4, 4, (int64_t)kCandBuckets * 4, 0, tid);
+    for (int i = tid; i < m; i += 1024) {
+      ck.in("C row (sort)", ((int64_t)(id0 + i) * DP) * 4, (int64_t)d * 4, Csz, 0, tid);
       ck.in("LDS key", (int64_t)i * 4, 4, (int64_t)kCandSortMax * 4, 0, tid);
+      // positions are bucket offsets plus arrivals: some pos in [0, m)
+      ck.in("cperm (pos)", (int64_t)(m - 1) * 4, 4, cap16 * 4, 0, tid);
+      ck.in("LDS skey (pos)", (int64_t)(m - 1) * 4, 4, (int64_t)kCandSortMax * 4, 0, tid);
     }
-    for (int pos = tid; pos < ntiles * 16; pos += 1024) ck.in("cperm", (int64_t)pos * 4, 4, (int64_t)tiles_cap * 64, 0, tid);
+    for (int pos = m + tid; pos < ntiles * 16; pos += 1024) ck.in("cperm (pad)", (int64_t)pos * 4, 4, cap16 * 4, 0, tid);
     for (int q = tid; q < ntiles; q += 1024) {
-      ck.in("LDS key (tile ends)", (int64_t)(std::min(m, q * 16 + 16) - 1) * 4, 4, (int64_t)kCandSortMax * 4, 0, tid);
+      for (int pos = q * 16; pos < std::min(m, q * 16 + 16); ++pos)
+        ck.in("LDS skey (tile)", (int64_t)pos * 4, 4, (int64_t)kCandSortMax * 4, 0, tid);
       ck.in("tnr", (int64_t)q * 8, 8, (int64_t)tiles_cap * 8, 0, tid);
     }
   }
