@@ -473,6 +473,7 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
   if (nchunks > 0) stage(0, sB0);
   stage_ncg(0);
   stage_tnr(0);
+  unsigned folded = 0;  // tile skip: bit r, row tile r took the values of some tile
 
   // A operands of this wave's points, kept in registers for the pass: from
   // the prepared buffer, or straight from X when d % 8 == 0 and X is bf16
@@ -643,8 +644,11 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
       // wave's matrix instructions, so one accumulator set suffices
       constexpr unsigned FULL = (1u << KRT) - 1u;
       for (int q = 0; q < nt; ++q) {
-        const unsigned sk = (unsigned)(skipm >> (q * KRT)) & FULL;
+        // a chunk of more than 64 / KRT tiles (one k-step) has judges for
+        // its first 64 / KRT tiles only; the rest are never skipped
+        const unsigned sk = q * KRT < 64 ? (unsigned)(skipm >> (q * KRT)) & FULL : 0u;
         if (sk == FULL) continue;  // no row tile of the wave can gain from tile q
+        folded |= ~sk & FULL;
         mfma_tile<KS, KRT, BCAST, SC>(Aop, buf, ncs, q, lane, acc0);
         fold(acc0, q, sk);
       }
@@ -812,6 +816,9 @@ __device__ __forceinline__ void screen_body(const ScreenArgs& a, int blk) {
     // non-finite values give none) or in a first pass, which writes every
     // point, the direct form decides.
     if (!a.first && jok && lbmin >= D) return;
+    // The tile skip ruled out every tile of the pass for this point's row
+    // tile: each candidate lies beyond the band above D, so D, A and S stand.
+    if (prune && nchunks > 0 && !((folded >> (lane / 16)) & 1u)) return;
     listed = true;
   } else if (r1 < D) {
     if (lb2 > r1) {

@@ -192,6 +192,30 @@ def test_refined_tile_skip_on_collinear_rows(plain, refined, d):
     _same_init(a, b)
 
 
+@pytest.mark.parametrize("d,kind", [(8, "ray"), (8, "gauss"), (42, "gauss")])
+def test_refined_tile_skip_rows_in_norm_order(plain, refined, d, kind):
+    # X stored in ascending norm: each row tile of the screen spans a narrow
+    # norm interval, so most (row tile, candidate tile) pairs are skipped and
+    # many row tiles skip every tile of a round (those points keep D without
+    # a rescan).  d = 8 runs one k-step with 24-tile chunks, more tiles than
+    # the skip has judges for (tiles 16 on of each chunk are never skipped).
+    if kind == "ray":
+        rng = np.random.default_rng(d)
+        u = rng.normal(size=d)
+        u /= np.linalg.norm(u)
+        X = (np.exp(rng.uniform(0.0, np.log(1e4), size=20000))[:, None] * u[None, :]).astype(np.float32)
+    else:
+        X = synth.gauss_mixture(20000, d, 200, 10.0, seed=d)
+    X = np.ascontiguousarray(X[np.argsort((X.astype(np.float64) ** 2).sum(1), kind="stable")])
+    Xd = _dev(X)
+    a = plain.init(Xd, k=200, ell=800.0, rounds=4, seed=2, trace=True)
+    b = refined.init(Xd, k=200, ell=800.0, rounds=4, seed=2, trace=True)
+    torch.cuda.synchronize()
+    _same_init(a, b)
+    if kind == "gauss":  # on the ray many points sit at the bound's margin and are listed
+        assert b.stats["n_rescanned"] <= 0.05 * 20000 * 4
+
+
 @pytest.mark.parametrize("d,span", [(4, 6), (20, 3)])
 def test_flagged_argmins_on_integer_lattice(plain, refined, d, span):
     # Integer coordinates make every FP32 distance exact, so a runner-up
